@@ -1,0 +1,152 @@
+"""Pins for the oracle's assembled operators.
+
+* P1 on the six-tetrahedra split is h times the 7-point finite-difference
+  Laplacian (diagonal 6h, axis neighbours -h, every other coupling zero).
+* A . 1 = 0 without boundary conditions.
+* Exact reproduction: for ell linear, (A ell)_i = 0 on interior rows; for q
+  quadratic (p >= 2), (A q)_i = -lap(q) int phi_i; for c cubic (p = 3),
+  (A c)_i = (M (-lap c))_i, since -lap(c) is linear and in the space.
+* Structure: nnz counts from the sparsity pattern.
+"""
+import numpy as np
+import pytest
+
+import fem_inputs
+from oracle import assemble
+from oracle import mesh as om
+
+
+def _lap7(n):
+    """h * 7-point Laplacian with Dirichlet identity rows on the (n+1)^3 lattice."""
+    h = 1.0 / n
+    L = n + 1
+    N = L ** 3
+    A = np.zeros((N, N))
+    for k in range(L):
+        for j in range(L):
+            for i in range(L):
+                r = i + L * (j + L * k)
+                if min(i, j, k) == 0 or max(i, j, k) == n:
+                    A[r, r] = 1.0
+                    continue
+                A[r, r] = 6 * h
+                for d in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+                    ii, jj, kk = i + d[0], j + d[1], k + d[2]
+                    if min(ii, jj, kk) == 0 or max(ii, jj, kk) == n:
+                        continue
+                    A[r, ii + L * (jj + L * kk)] = -h
+    return A
+
+
+@pytest.mark.parametrize("n", [2, 4])
+def test_p1_is_7point(n):
+    lev = om.single_level(n, 1)
+    A = assemble.apply_bc(assemble.stiffness(lev), lev.boundary).toarray()
+    assert np.max(np.abs(A - _lap7(n))) < 1e-14
+
+
+@pytest.mark.parametrize("p,coef", [(1, 15), (2, 230), (3, 1311)])
+def test_nnz_structure(p, coef):
+    poly = {1: (15, 21, 9, 1), 2: (230, 138, 24, 1), 3: (1311, 459, 45, 1)}[p]
+    for n in (1, 2, 3):
+        A = assemble.stiffness(om.single_level(n, p))
+        A.eliminate_zeros()
+        pattern_nnz = np.unique(np.stack([np.repeat(om.single_level(n, p).cell_dofs, refelem_n(p), axis=1).ravel(),
+                                          np.tile(om.single_level(n, p).cell_dofs, (1, refelem_n(p))).ravel()]),
+                                axis=1).shape[1]
+        assert pattern_nnz == poly[0] * n ** 3 + poly[1] * n ** 2 + poly[2] * n + poly[3]
+
+
+def refelem_n(p):
+    return (p + 1) * (p + 2) * (p + 3) // 6
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("jit", [False, True])
+@pytest.mark.parametrize("kvar", [False, True])
+def test_constants_in_kernel_and_symmetry(p, jit, kvar):
+    n = 3
+    lev = om.single_level(n, p, fem_inputs.jitter_offsets(n, 0.15) if jit else None)
+    k = fem_inputs.k_exp_fourier(lev.vert_xyz) if kvar else None
+    A = assemble.stiffness(lev, k)
+    scale = abs(A).max()
+    assert np.max(np.abs(A @ np.ones(lev.n_dofs))) < 1e-13 * scale
+    assert abs(A - A.T).max() < 1e-14 * scale
+
+
+def _interior_rows(lev):
+    return lev.interior()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("jit", [False, True])
+def test_linear_exactness(p, jit):
+    n = 3
+    lev = om.single_level(n, p, fem_inputs.jitter_offsets(n, 0.15) if jit else None)
+    A = assemble.stiffness(lev)
+    xyz = lev.dof_xyz()
+    ell = 0.3 + 1.1 * xyz[:, 0] - 0.7 * xyz[:, 1] + 2.3 * xyz[:, 2]
+    r = (A @ ell)[_interior_rows(lev)]
+    assert np.max(np.abs(r)) < 1e-13
+
+
+@pytest.mark.parametrize("p", [2, 3])
+@pytest.mark.parametrize("jit", [False, True])
+def test_quadratic_exactness(p, jit):
+    from oracle import refelem
+    n = 3
+    lev = om.single_level(n, p, fem_inputs.jitter_offsets(n, 0.15) if jit else None)
+    A = assemble.stiffness(lev)
+    x, y, z = lev.dof_xyz().T
+    q = 1.0 + x * x - 2.0 * y * y + 3.0 * z * z + 0.5 * x * y - z * x + 0.25 * y * z + x
+    minus_lap_q = -(2.0 - 4.0 + 6.0)
+    # int phi_i over the mesh, by assembling the reference integrals
+    _, det = lev.geometric_factors()
+    wi = np.bincount(lev.cell_dofs.ravel(),
+                     weights=(det[:, None] * refelem.basis_integrals(p)[None, :]).ravel(),
+                     minlength=lev.n_dofs)
+    I = _interior_rows(lev)
+    assert np.max(np.abs((A @ q)[I] - minus_lap_q * wi[I])) < 1e-13
+
+
+@pytest.mark.parametrize("jit", [False, True])
+def test_cubic_exactness_p3(jit):
+    n = 3
+    lev = om.single_level(n, 3, fem_inputs.jitter_offsets(n, 0.15) if jit else None)
+    A = assemble.stiffness(lev)
+    M = assemble.mass(lev)
+    x, y, z = lev.dof_xyz().T
+    c = x ** 3 + 2 * y ** 2 * z - x * y * z + 0.5 * z ** 3 + y
+    minus_lap_c = -(6 * x + 4 * z + 3 * z)
+    I = _interior_rows(lev)
+    assert np.max(np.abs((A @ c)[I] - (M @ minus_lap_c)[I])) < 1e-13
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_mass_total(p):
+    lev = om.single_level(3, p, fem_inputs.jitter_offsets(3, 0.15))
+    M = assemble.mass(lev)
+    assert abs(M.sum() - 1.0) < 1e-13
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("kvar", [False, True])
+def test_matfree_matches_csr(p, kvar):
+    n = 3
+    lev = om.single_level(n, p, fem_inputs.jitter_offsets(n, 0.15))
+    k = fem_inputs.k_exp_fourier(lev.vert_xyz) if kvar else None
+    x = fem_inputs.uniform_vector(lev.n_dofs, 0)
+    A = assemble.apply_bc(assemble.stiffness(lev, k), lev.boundary)
+    y1 = A @ x
+    y2 = assemble.matfree_action(lev, x, k, bc=True, chunk=37)
+    assert np.linalg.norm(y1 - y2) <= 1e-14 * np.linalg.norm(y1)
+    y3 = assemble.matfree_action(lev, x, k, bc=False)
+    assert np.linalg.norm(assemble.stiffness(lev, k) @ x - y3) <= 1e-14 * np.linalg.norm(y3)
+
+
+def test_kvar_constant_equals_scaled():
+    lev = om.single_level(2, 3)
+    k = np.full(lev.n_vertices, 2.5)
+    A1 = assemble.stiffness(lev, k)
+    A0 = assemble.stiffness(lev)
+    assert abs(A1 - 2.5 * A0).max() < 1e-14
