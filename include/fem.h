@@ -1,0 +1,215 @@
+/*
+ * fem.h - C ABI of the MI355X (gfx950) matrix-free Poisson / multigrid-CG library.
+ *
+ * The library applies the operator of the weak form
+ *     a(u, v) = int_Omega k grad(u) . grad(v) dx                (paper Section 2, eq. 4)
+ * for continuous Lagrange P1-P3 elements (Section 2, Listing 1: FunctionSpace(mesh, "CG", degree))
+ * on a tetrahedral unit cube refined uniformly (Listing 1: UnitCubeMesh, MeshHierarchy), with
+ * homogeneous Dirichlet conditions on all six faces (Listing 1: DirichletBC), and solves
+ * A u = b by conjugate gradients preconditioned with a geometric multigrid V-cycle whose levels
+ * are smoothed by two Chebyshev iterations and whose coarsest level is solved directly
+ * (Section 4, Listing 2).  k is either 1 (the paper's problem) or a continuous piecewise-linear
+ * field given by its vertex values.  It also computes dJ/dk for J = 1/2 ||u - u_obs||^2_{L2} by
+ * the adjoint method (the sensitivities motivated in Section 1).
+ *
+ * Conventions
+ *  - Every entry point returns fem_status: 0 = FEM_OK, > 0 warning, < 0 error.  Arguments are
+ *    validated on the host before anything is enqueued; a call that returns an error has
+ *    enqueued nothing (a solve may leave x holding its last iterate).  fem_last_error() gives a
+ *    per-thread message for the most recent failure.
+ *  - Device pointers are plain pointers into caller-owned device memory; "stream" is a
+ *    hipStream_t passed as void* (NULL = the default stream).  The library never allocates
+ *    memory visible to the caller: mesh data and solver workspaces live in caller buffers sized
+ *    by the *_bytes queries (256-byte aligned) that must outlive the handles using them.
+ *  - Vectors are in the library's dof order: the P_p dofs of level l sit on the lattice of
+ *    spacing h_l / p, and dof (I, J, K) has index I + L (J + L K), L = p n_l + 1.  Vertex
+ *    fields (k, dJ/dk) use the vertex lattice: index i + (n_l+1) (j + (n_l+1) k).
+ *  - Level 0 is the coarsest mesh; level n_refine the finest.
+ *  - Apply, mass, diagonal, transfer and gradient calls are stream-ordered and asynchronous.
+ *    Solver calls are host-synchronous (they take convergence decisions on the host).
+ *  - Calls that use the same mesh level (or the same solver workspace) on different streams
+ *    concurrently race: each level owns one interface scratch area inside the mesh buffer.
+ */
+#ifndef FEM_H
+#define FEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fem_status;
+enum {
+    FEM_OK = 0,
+    FEM_WARN_NOT_CONVERGED = 1,
+    FEM_ERR_INVALID_ARG = -1,
+    FEM_ERR_UNSUPPORTED = -2,
+    FEM_ERR_WORKSPACE = -3,
+    FEM_ERR_HIP = -4,
+    FEM_ERR_BREAKDOWN = -5,
+    FEM_ERR_STATE = -6
+};
+
+typedef enum { FEM_F64 = 0, FEM_F32 = 1 } fem_dtype;
+
+/* flags for the operator applications */
+enum {
+    FEM_BC_IDENTITY = 0,  /* y = P_I A P_I x + P_B x: identity rows/zero columns on boundary dofs */
+    FEM_BC_NONE = 1,      /* y = A x, the raw operator (A . 1 = 0 for the stiffness operator)  */
+    FEM_BC_ZERO_ROWS = 2  /* y = P_I A x: boundary rows zeroed, columns kept                     */
+};
+
+/* mesh description */
+enum { FEM_MESH_JITTER = 1u };
+typedef struct {
+    int32_t n;              /* cubes per direction of the coarsest mesh (>= 1)            */
+    int32_t n_refine;       /* uniform refinements; levels = n_refine + 1 (<= 7)           */
+    int32_t degree;         /* Lagrange degree p in {1, 2, 3}                              */
+    uint32_t flags;         /* FEM_MESH_JITTER: move coarsest interior vertices             */
+    const double* jitter;   /* host, ((n+1)^3, 3) offsets in units of h = 1/n, x fastest;
+                               read only when FEM_MESH_JITTER is set; boundary rows ignored */
+} fem_mesh_desc;
+
+typedef struct {
+    int64_t n_cells, n_dofs, n_interior, n_vertices;
+    int32_t n, degree, brick;   /* cubes per direction, degree, cubes per brick edge */
+    int32_t pad;
+} fem_level_info;
+
+typedef struct fem_mesh fem_mesh;
+
+/* Build a mesh hierarchy on the host: topology, numbering, per-cell geometric factors
+ * G = |det J| J^-1 J^-T, cell-to-dof maps, brick reduction and transfer tables.
+ * Section 2, Listing 1 (UnitCubeMesh, MeshHierarchy, FunctionSpace).  Host only.
+ * Errors: FEM_ERR_INVALID_ARG (NULL, n < 1, degree outside 1..3, sizes beyond int32 indexing),
+ *         FEM_ERR_INVALID_ARG when jitter inverts a cell. */
+fem_status fem_mesh_create(const fem_mesh_desc* desc, fem_mesh** out);
+
+/* Bytes of the device buffer the mesh needs (256-byte multiple). Host only. */
+fem_status fem_mesh_device_bytes(const fem_mesh* mesh, size_t* bytes);
+
+/* Copy the mesh to a caller-owned device buffer of at least fem_mesh_device_bytes bytes on the
+ * current HIP device.  Blocks until the copy is complete.  The buffer must outlive the mesh.
+ * Errors: FEM_ERR_INVALID_ARG (NULL, misaligned), FEM_ERR_WORKSPACE (too small), FEM_ERR_HIP. */
+fem_status fem_mesh_upload(fem_mesh* mesh, void* device_buffer, size_t bytes, void* stream);
+
+fem_status fem_mesh_levels(const fem_mesh* mesh, int32_t* n_levels);
+fem_status fem_mesh_info(const fem_mesh* mesh, int32_t level, fem_level_info* info);
+
+/* Lattice coordinates of every dof of a level: host array (3 * n_dofs) int32, (I, J, K) per dof. */
+fem_status fem_mesh_dof_lattice(const fem_mesh* mesh, int32_t level, int32_t* ijk);
+
+/* Vertex positions of a level: host array (3 * n_vertices) double. */
+fem_status fem_mesh_vertex_coords(const fem_mesh* mesh, int32_t level, double* xyz);
+
+void fem_mesh_destroy(fem_mesh* mesh);
+
+/* y = A(k) x, the matrix-free stiffness action on one level (Section 2, eq. 4; the element
+ * integrals use a quadrature rule exact for the polynomial integrand: degree 2p-2 for k = 1,
+ * 2p-1 for P1 k).  k_vertex: NULL for k = 1, else n_vertices values of dtype.  x, y: n_dofs
+ * values of dtype, device, x != y.  flags: FEM_BC_IDENTITY | FEM_BC_NONE | FEM_BC_ZERO_ROWS.
+ * Stream-ordered.  Deterministic: the scatter-add runs in a fixed order.
+ * Errors: FEM_ERR_INVALID_ARG, FEM_ERR_STATE (mesh not uploaded), FEM_ERR_HIP. */
+fem_status fem_apply_laplacian(const fem_mesh* mesh, int32_t level, fem_dtype dtype,
+                               const void* k_vertex, const void* x, void* y,
+                               uint32_t flags, void* stream);
+
+/* y = alpha * A(k) x + beta * z (z may equal y; z ignored when beta == 0). Same layout rules. */
+fem_status fem_apply_laplacian_axpby(const fem_mesh* mesh, int32_t level, fem_dtype dtype,
+                                     const void* k_vertex, const void* x, double alpha,
+                                     const void* z, double beta, void* y,
+                                     uint32_t flags, void* stream);
+
+/* y = M x, the consistent mass matrix int phi_i phi_j (used for J and the adjoint right-hand
+ * side).  flags as above (FEM_BC_NONE gives the raw matrix). */
+fem_status fem_apply_mass(const fem_mesh* mesh, int32_t level, fem_dtype dtype,
+                          const void* x, void* y, uint32_t flags, void* stream);
+
+/* d = diag(A_bc(k)) (boundary entries 1), the Jacobi scaling of the Chebyshev smoother
+ * (Section 4, Listing 2). */
+fem_status fem_assemble_diagonal(const fem_mesh* mesh, int32_t level, fem_dtype dtype,
+                                 const void* k_vertex, void* d, void* stream);
+
+/* Multigrid transfers between level fine_level-1 and fine_level (Section 4: nested spaces
+ * from uniform refinement).  Prolongation: x_fine += P x_coarse (P interpolates the coarse
+ * function at the fine nodes).  Restriction: r_coarse = P^T r_fine with boundary rows zeroed. */
+fem_status fem_prolong(const fem_mesh* mesh, int32_t fine_level, fem_dtype dtype,
+                       const void* x_coarse, void* x_fine, void* stream);
+fem_status fem_restrict(const fem_mesh* mesh, int32_t fine_level, fem_dtype dtype,
+                        const void* r_fine, void* r_coarse, void* stream);
+
+/* Solver */
+enum { FEM_PREC_FP64 = 0, FEM_PREC_MIXED = 1 };
+enum { FEM_COARSE_AUTO = 0, FEM_COARSE_DENSE = 1, FEM_COARSE_NESTED = 2 };
+
+typedef struct {
+    double rtol;                 /* stop when ||b - A x|| / ||b|| <= rtol                       */
+    int32_t max_it;              /* outer CG iterations                                         */
+    int32_t precision;           /* FEM_PREC_FP64 or FEM_PREC_MIXED                             */
+    int32_t n_levels_used;       /* levels in the outer V-cycle (0 = all); the lowest of them is
+                                    solved directly, or by nested FP64 MG-PCG over the levels below */
+    int32_t cheb_degree;         /* Chebyshev steps per smoothing (Listing 2: 2)                */
+    double cheb_lo, cheb_hi;     /* interval [lo, hi] * lambda_max of D^-1 A                     */
+    int32_t eig_iters;           /* Lanczos steps for lambda_max                               */
+    int32_t coarse_method;       /* FEM_COARSE_*                                                */
+    const double* lambda_max_override; /* host, NULL or one value per mesh level (0 = estimate) */
+    double coarse_rtol;          /* nested coarse solve tolerance                               */
+    int32_t replace_every;       /* true-residual replacement period (0 = never)               */
+    int32_t flexible;            /* 1: Polak-Ribiere beta                                       */
+    double* history;             /* host, may be NULL: relative residual per iteration          */
+    int32_t history_cap;
+    int32_t pad;
+} fem_solve_opts;
+
+typedef struct {
+    int32_t iterations;
+    int32_t coarse_iterations;   /* nested coarse solver iterations, summed                  */
+    double rel_residual_true;    /* ||b - A x|| / ||b|| in FP64 at exit                        */
+    double setup_ms, solve_ms, coarse_ms;
+    double level_ms[8];          /* time spent per mesh level in the V-cycles                  */
+    double lambda_max[8];
+} fem_solve_stats;
+
+void fem_solve_opts_default(fem_solve_opts* opts);
+
+typedef struct fem_solver fem_solver;
+
+/* Workspace bytes for a solver on this mesh with these options (256-byte multiple). */
+fem_status fem_solve_workspace_bytes(const fem_mesh* mesh, const fem_solve_opts* opts, size_t* bytes);
+
+/* A solver handle binds mesh, options and a caller-owned device workspace. */
+fem_status fem_solver_create(const fem_mesh* mesh, const fem_solve_opts* opts,
+                             void* workspace, size_t ws_bytes, fem_solver** out);
+/* Per-coefficient setup: injected k on every level, Jacobi diagonals, lambda_max by Lanczos,
+ * coarse operator and its dense inverse (or nested solver).  k_vertex: NULL (k = 1) or FP64
+ * device array on the finest level's vertices.  Host-synchronous. */
+fem_status fem_solver_setup(fem_solver* s, const double* k_vertex, void* stream);
+/* Solve A_bc(k) x = b (b, x FP64 device, finest level; x in: initial guess, out: solution).
+ * Returns FEM_WARN_NOT_CONVERGED when max_it is reached, FEM_ERR_BREAKDOWN on p^T A p <= 0 or
+ * non-finite scalars. */
+fem_status fem_solver_solve(fem_solver* s, const double* b, double* x, fem_solve_stats* stats, void* stream);
+/* z = B r: one application of the multigrid preconditioner (FP64 in/out, finest level). */
+fem_status fem_solver_vcycle(fem_solver* s, const double* r, double* z, void* stream);
+void fem_solver_destroy(fem_solver* s);
+
+/* One-shot: create, set up, solve, destroy. */
+fem_status fem_mg_cg_solve(const fem_mesh* mesh, const double* k_vertex, const double* b, double* x,
+                           const fem_solve_opts* opts, void* workspace, size_t ws_bytes,
+                           fem_solve_stats* stats, void* stream);
+
+/* grad_v = - sum_K int_K psi_v grad(u) . grad(lambda) dx over the cells K containing vertex v
+ * (psi_v the P1 hat function): the derivative of lambda^T A(k) u with respect to the vertex
+ * value k_v, negated.  u, lambda: FP64 n_dofs of `level`; grad: FP64 n_vertices, overwritten.
+ * k_vertex is accepted for symmetry with the solve and not read (A is linear in k). */
+fem_status fem_adjoint_grad_k(const fem_mesh* mesh, int32_t level, const double* k_vertex,
+                              const double* u, const double* lambda, double* grad, void* stream);
+
+const char* fem_status_string(fem_status s);
+const char* fem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEM_H */

@@ -1,0 +1,50 @@
+// Constants shared by the host code and the gfx950 kernels of the library.
+#pragma once
+#include <cstdint>
+
+#if defined(__HIPCC__)
+#define FEM_HD __host__ __device__
+#else
+#define FEM_HD
+#endif
+
+namespace fem {
+
+// Local dofs of Lagrange P_p on a tetrahedron: (p+1)(p+2)(p+3)/6.
+FEM_HD constexpr int nloc_of(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+
+// Points of the barycentric lattice {m : |m| = 2p}: the fine-mesh nodes inside one coarse cell
+// after one uniform refinement.
+FEM_HD constexpr int nfine_pts(int p) { return (2 * p + 1) * (2 * p + 2) * (2 * p + 3) / 6; }
+
+// Quadrature points per cell.  Stiffness with k = 1 has integrand degree 2p-2, with a P1
+// coefficient (and the adjoint gradient, which carries one P1 factor) degree 2p-1.
+//   degree <= 1: 1 point (centroid)   degree 2: 4 points   degree 3: 5 points
+//   degree 4: 11 points               degree 5: 14 points
+FEM_HD constexpr int nq_of(int p, bool kvar) {
+    return p == 1 ? 1 : p == 2 ? (kvar ? 5 : 4) : (kvar ? 14 : 11);
+}
+
+// Six tetrahedra per cube, one per axis order s (lexicographic order of the permutations of
+// {0,1,2}); the cell's vertices follow the monotone lattice path
+//   v0 = c, v1 = v0 + e_s0, v2 = v1 + e_s1, v3 = c + (1,1,1).
+FEM_HD constexpr int perm_axis(int t, int k) {
+    // t = 0..5 : (0,1,2) (0,2,1) (1,0,2) (1,2,0) (2,0,1) (2,1,0)
+    return (t == 0) ? k : (t == 1) ? (k == 0 ? 0 : k == 1 ? 2 : 1)
+         : (t == 2) ? (k == 0 ? 1 : k == 1 ? 0 : 2) : (t == 3) ? (k == 0 ? 1 : k == 1 ? 2 : 0)
+         : (t == 4) ? (k == 0 ? 2 : k == 1 ? 0 : 1) : (k == 0 ? 2 : k == 1 ? 1 : 0);
+}
+
+// The boundary flag of a dof lives in the sign bit of the cell-to-dof map entry.
+constexpr uint32_t kBoundaryBit = 0x80000000u;
+
+// Geometric factor storage order (symmetric 3x3): 00, 11, 22, 01, 02, 12.
+enum { G00 = 0, G11 = 1, G22 = 2, G01 = 3, G02 = 4, G12 = 5 };
+
+// Cell-wise operations that scatter-add into shared dofs.
+enum Kind : int { K_APPLY = 0, K_DIAG = 1, K_MASS = 2, K_RESTRICT = 3, K_GRAD = 4 };
+
+// Row treatment of boundary dofs in scatter kernels.
+enum RowMode : int { ROW_NONE = 0, ROW_IDENTITY = 1, ROW_ZERO = 2, ROW_ONE = 3 };
+
+}  // namespace fem

@@ -1,0 +1,332 @@
+// Mesh hierarchy on the host: the tetrahedral unit cube of the paper (Section 2, Listing 1:
+// UnitCubeMesh(N, N, N), MeshHierarchy(mesh, r)), its P_p numbering, the per-cell geometric
+// factors and the tables the kernels use.
+//
+// Cube split: each cube is cut into the 6 tetrahedra that share its main diagonal; uniform
+// refinement (new vertices at edge midpoints) maps the split of n^3 cubes onto the split of
+// (2n)^3 cubes, so level l is the split of (n 2^l)^3 cubes with vertices at edge midpoints of
+// level l-1 (and only level 0 may be perturbed).
+//
+// Layout for the kernels:
+//  * cells are ordered brick by brick: bricks of B^3 cubes (B = 4, 2 or 1, the largest that
+//    divides n), bricks x-fastest, cubes inside a brick x-fastest, the 6 tetrahedra of a cube
+//    consecutive.  Cell index c = brick * 6 B^3 + cube_local * 6 + t.
+//  * cell-to-dof map: structure of arrays, map[i * C + c] for local node i, int32 with the sign
+//    bit set on boundary dofs.
+//  * geometric factor G = |det J| J^-1 J^-T: structure of arrays, 6 entries (00,11,22,01,02,12),
+//    FP64 and an FP32 copy.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+
+#include "internal.hpp"
+
+namespace fem {
+
+static int choose_brick(int n) { return (n % 4 == 0) ? 4 : (n % 2 == 0) ? 2 : 1; }
+
+static void build_red(RedTable& t, int po, int B) {
+    t.po = po;
+    t.B = B;
+    t.NC = 6 * B * B * B;
+    const int PB = po * B, QS = PB + 1;
+    t.Q = QS * QS * QS;
+    std::vector<std::array<int, 4>> mi;
+    node_multi_indices(po, mi);
+    const int nl = (int)mi.size();
+    std::vector<std::vector<int32_t>> lists(t.Q);
+    t.q_of.assign((size_t)t.NC * nl, -1);
+    for (int cl = 0; cl < t.NC; ++cl) {
+        const int cube = cl / 6, tt = cl % 6;
+        const int lx = cube % B, ly = (cube / B) % B, lz = cube / (B * B);
+        int V[4][3];
+        V[0][0] = lx; V[0][1] = ly; V[0][2] = lz;
+        for (int k = 0; k < 3; ++k) V[1][k] = V[0][k];
+        V[1][perm_axis(tt, 0)] += 1;
+        for (int k = 0; k < 3; ++k) V[2][k] = V[1][k];
+        V[2][perm_axis(tt, 1)] += 1;
+        for (int k = 0; k < 3; ++k) V[3][k] = V[0][k] + 1;
+        for (int i = 0; i < nl; ++i) {
+            int X[3] = {0, 0, 0};
+            for (int v = 0; v < 4; ++v)
+                for (int k = 0; k < 3; ++k) X[k] += mi[i][v] * V[v][k];
+            const int q = X[0] + QS * (X[1] + QS * X[2]);
+            lists[q].push_back(i * t.NC + cl);
+            t.q_of[(size_t)cl * nl + i] = q;
+        }
+    }
+    t.off.assign(t.Q + 1, 0);
+    t.ent.clear();
+    t.slot.assign(t.Q, -1);
+    int nslot = 0;
+    for (int q = 0; q < t.Q; ++q) {
+        std::sort(lists[q].begin(), lists[q].end());
+        t.off[q] = (int32_t)t.ent.size();
+        t.ent.insert(t.ent.end(), lists[q].begin(), lists[q].end());
+        const int a = q % QS, b = (q / QS) % QS, c = q / (QS * QS);
+        const bool inside = a > 0 && a < PB && b > 0 && b < PB && c > 0 && c < PB;
+        if (!inside) t.slot[q] = nslot++;
+    }
+    t.off[t.Q] = (int32_t)t.ent.size();
+    t.QB = nslot;
+}
+
+static int find_red(fem_mesh& m, int po, int B) {
+    for (size_t i = 0; i < m.red.size(); ++i)
+        if (m.red[i].po == po && m.red[i].B == B) return (int)i;
+    RedTable t;
+    build_red(t, po, B);
+    m.red.push_back(std::move(t));
+    return (int)m.red.size() - 1;
+}
+
+static void cell_vertices(const HostLevel& L, int64_t c, int V[4][3]) {
+    const int64_t brick = c / L.NC;
+    const int cl = (int)(c % L.NC);
+    const int cube = cl / 6, t = cl % 6;
+    const int B = L.B;
+    const int bx = (int)(brick % L.nb), by = (int)((brick / L.nb) % L.nb), bz = (int)(brick / ((int64_t)L.nb * L.nb));
+    V[0][0] = bx * B + cube % B;
+    V[0][1] = by * B + (cube / B) % B;
+    V[0][2] = bz * B + cube / (B * B);
+    for (int k = 0; k < 3; ++k) V[1][k] = V[0][k];
+    V[1][perm_axis(t, 0)] += 1;
+    for (int k = 0; k < 3; ++k) V[2][k] = V[1][k];
+    V[2][perm_axis(t, 1)] += 1;
+    for (int k = 0; k < 3; ++k) V[3][k] = V[0][k] + 1;
+}
+
+static void build_level(HostLevel& L, const std::vector<std::array<int, 4>>& mi) {
+    const int n = L.n, p = L.p, nl = L.nloc;
+    L.B = choose_brick(n);
+    L.nb = n / L.B;
+    L.NC = 6 * L.B * L.B * L.B;
+    L.L = p * n + 1;
+    L.C = 6LL * n * n * n;
+    L.N = (int64_t)L.L * L.L * L.L;
+    L.NI = (int64_t)(L.L - 2) * (L.L - 2) * (L.L - 2);
+    L.NV = (int64_t)(n + 1) * (n + 1) * (n + 1);
+    L.nbricks = (int64_t)L.nb * L.nb * L.nb;
+    const int64_t C = L.C;
+    L.map.assign((size_t)nl * C, 0);
+    L.G64.assign((size_t)6 * C, 0.0);
+    L.G32.assign((size_t)6 * C, 0.0f);
+    const int N1 = n + 1, Lp = L.L;
+    for (int64_t c = 0; c < C; ++c) {
+        int V[4][3];
+        cell_vertices(L, c, V);
+        for (int i = 0; i < nl; ++i) {
+            int X[3] = {0, 0, 0};
+            for (int v = 0; v < 4; ++v)
+                for (int k = 0; k < 3; ++k) X[k] += mi[i][v] * V[v][k];
+            const bool bnd = X[0] == 0 || X[1] == 0 || X[2] == 0 || X[0] == Lp - 1 || X[1] == Lp - 1 ||
+                             X[2] == Lp - 1;
+            const int64_t g = X[0] + (int64_t)Lp * (X[1] + (int64_t)Lp * X[2]);
+            L.map[(size_t)i * C + c] = (int32_t)((uint32_t)g | (bnd ? kBoundaryBit : 0u));
+        }
+        double x[4][3];
+        for (int v = 0; v < 4; ++v) {
+            const int64_t vid = V[v][0] + (int64_t)N1 * (V[v][1] + (int64_t)N1 * V[v][2]);
+            for (int k = 0; k < 3; ++k) x[v][k] = L.vxyz[3 * vid + k];
+        }
+        double J[3][3];  // columns are the edges x1-x0, x2-x0, x3-x0
+        for (int r = 0; r < 3; ++r)
+            for (int col = 0; col < 3; ++col) J[r][col] = x[col + 1][r] - x[0][r];
+        // adjugate: J^-1 = adj / det
+        double adj[3][3];
+        adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+        adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+        adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+        adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+        adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+        adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        const double det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
+        // G = |det| J^-1 J^-T = adj adj^T / |det|
+        double G[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double s = 0.0;
+                for (int k = 0; k < 3; ++k) s += adj[a][k] * adj[b][k];
+                G[a][b] = s / std::fabs(det);
+            }
+        const double g6[6] = {G[0][0], G[1][1], G[2][2], G[0][1], G[0][2], G[1][2]};
+        for (int e = 0; e < 6; ++e) {
+            L.G64[(size_t)e * C + c] = g6[e];
+            L.G32[(size_t)e * C + c] = (float)g6[e];
+        }
+        // orientation of the path tetrahedron on the uniform lattice: sign of the permutation
+        const int t = (int)((c % L.NC) % 6);
+        const double sgn = (t == 0 || t == 3 || t == 4) ? 1.0 : -1.0;
+        const double h = 1.0 / n;
+        if (!(det * sgn > 0.05 * h * h * h)) {
+            throw std::runtime_error("mesh cell inverted or degenerate (jitter too large)");
+        }
+    }
+}
+
+// Structural check: every map entry equals the dof the brick reduction table expects.
+static void validate_level(const HostLevel& L, const RedTable& t) {
+    const int PB = L.p * L.B, QS = PB + 1;
+    for (int64_t c = 0; c < L.C; ++c) {
+        const int64_t brick = c / L.NC;
+        const int cl = (int)(c % L.NC);
+        const int bx = (int)(brick % L.nb), by = (int)((brick / L.nb) % L.nb), bz = (int)(brick / ((int64_t)L.nb * L.nb));
+        for (int i = 0; i < L.nloc; ++i) {
+            const int q = t.q_of[(size_t)cl * L.nloc + i];
+            const int a = q % QS, b = (q / QS) % QS, cc = q / (QS * QS);
+            const int64_t g = (bx * PB + a) + (int64_t)L.L * ((by * PB + b) + (int64_t)L.L * (bz * PB + cc));
+            const uint32_t m = (uint32_t)L.map[(size_t)i * L.C + c] & ~kBoundaryBit;
+            if ((int64_t)m != g) throw std::runtime_error("cell-to-dof map disagrees with the brick table");
+        }
+    }
+}
+
+// Fine points of one uniform refinement owned by each coarse cell: the first coarse cell (in
+// cell order) whose closure contains the point owns it.
+static void build_owner(HostLevel& Lc, const HostLevel& Lf, const std::vector<std::array<int, 4>>& pts) {
+    const int np = (int)pts.size();
+    Lc.nwords = (np + 31) / 32;
+    Lc.owner.assign((size_t)Lc.nwords * Lc.C, 0u);
+    std::vector<uint8_t> claimed((size_t)Lf.N, 0);
+    const int64_t Lfl = Lf.L;
+    for (int64_t c = 0; c < Lc.C; ++c) {
+        int V[4][3];
+        cell_vertices(Lc, c, V);
+        for (int m = 0; m < np; ++m) {
+            int X[3] = {0, 0, 0};
+            for (int v = 0; v < 4; ++v)
+                for (int k = 0; k < 3; ++k) X[k] += pts[m][v] * V[v][k];
+            const int64_t g = X[0] + Lfl * (X[1] + Lfl * X[2]);
+            if (!claimed[g]) {
+                claimed[g] = 1;
+                Lc.owner[(size_t)(m / 32) * Lc.C + c] |= 1u << (m % 32);
+            }
+        }
+    }
+    for (int64_t g = 0; g < Lf.N; ++g)
+        if (!claimed[g]) throw std::runtime_error("fine dof not covered by any coarse cell");
+}
+
+static void build_tab(Tabulation& T, int p, int kvar) {
+    const Rule& r = rule_for_degree(kvar ? 2 * p - 1 : 2 * p - 2);
+    const int nl = nloc_of(p);
+    T.p = p;
+    T.kvar = kvar;
+    T.nq = (int)r.w.size();
+    if (T.nq != nq_of(p, kvar != 0)) throw std::runtime_error("quadrature size mismatch");
+    T.stride = 1 + 4 + 3 * nl;
+    T.t64.assign((size_t)T.nq * T.stride, 0.0);
+    std::vector<double> dphi(nl * 3);
+    for (int q = 0; q < T.nq; ++q) {
+        double* o = &T.t64[(size_t)q * T.stride];
+        o[0] = r.w[q];
+        for (int v = 0; v < 4; ++v) o[1 + v] = r.lam[4 * q + v];
+        eval_basis_grad(p, &r.x[3 * q], nullptr, dphi.data());
+        for (int d = 0; d < 3; ++d)
+            for (int i = 0; i < nl; ++i) o[5 + d * nl + i] = dphi[i * 3 + d];
+    }
+    T.t32.assign(T.t64.begin(), T.t64.end());
+}
+
+fem_status build_mesh(const fem_mesh_desc& d, fem_mesh& m) {
+    m.desc = d;
+    m.desc.jitter = nullptr;
+    m.p = d.degree;
+    m.nlev = d.n_refine + 1;
+    const int p = d.degree;
+    std::vector<std::array<int, 4>> mi;
+    node_multi_indices(p, mi);
+    m.lev.resize(m.nlev);
+    for (int l = 0; l < m.nlev; ++l) {
+        HostLevel& L = m.lev[l];
+        L.n = d.n << l;
+        L.p = p;
+        L.nloc = nloc_of(p);
+        const int n = L.n, N1 = n + 1;
+        L.vxyz.assign((size_t)N1 * N1 * N1 * 3, 0.0);
+        if (l == 0) {
+            for (int k = 0; k < N1; ++k)
+                for (int j = 0; j < N1; ++j)
+                    for (int i = 0; i < N1; ++i) {
+                        const size_t v = (size_t)i + N1 * ((size_t)j + N1 * k);
+                        double x[3] = {(double)i / n, (double)j / n, (double)k / n};
+                        const bool interior = i > 0 && j > 0 && k > 0 && i < n && j < n && k < n;
+                        if ((d.flags & FEM_MESH_JITTER) && d.jitter && interior)
+                            for (int a = 0; a < 3; ++a) x[a] += d.jitter[3 * v + a] / n;
+                        for (int a = 0; a < 3; ++a) L.vxyz[3 * v + a] = x[a];
+                    }
+        } else {
+            const HostLevel& Cc = m.lev[l - 1];
+            const int nc1 = Cc.n + 1;
+            for (int k = 0; k < N1; ++k)
+                for (int j = 0; j < N1; ++j)
+                    for (int i = 0; i < N1; ++i) {
+                        const size_t v = (size_t)i + N1 * ((size_t)j + N1 * k);
+                        const size_t lo = (size_t)(i / 2) + nc1 * ((size_t)(j / 2) + nc1 * (k / 2));
+                        const size_t hi = (size_t)((i + 1) / 2) + nc1 * ((size_t)((j + 1) / 2) + nc1 * ((k + 1) / 2));
+                        for (int a = 0; a < 3; ++a) L.vxyz[3 * v + a] = 0.5 * (Cc.vxyz[3 * lo + a] + Cc.vxyz[3 * hi + a]);
+                    }
+        }
+        build_level(L, mi);
+        L.red = find_red(m, p, L.B);
+        L.red1 = find_red(m, 1, L.B);
+        validate_level(L, m.red[L.red]);
+        L.slot_elems = L.nbricks * std::max(m.red[L.red].QB, m.red[L.red1].QB);
+    }
+    std::vector<std::array<int, 4>> pts;
+    fine_points(p, pts);
+    m.npts = (int)pts.size();
+    for (int l = 0; l + 1 < m.nlev; ++l) build_owner(m.lev[l], m.lev[l + 1], pts);
+    for (int kv = 0; kv < 2; ++kv) build_tab(m.tab[kv], p, kv);
+    // prolongation table: coarse basis at the fine points m / (2p)
+    const int nl = nloc_of(p);
+    m.fine_mi.resize((size_t)m.npts * 4);
+    m.ploc64.resize((size_t)m.npts * nl);
+    for (int q = 0; q < m.npts; ++q) {
+        for (int v = 0; v < 4; ++v) m.fine_mi[4 * q + v] = pts[q][v];
+        const double xi[3] = {pts[q][1] / (2.0 * p), pts[q][2] / (2.0 * p), pts[q][3] / (2.0 * p)};
+        eval_basis_grad(p, xi, &m.ploc64[(size_t)q * nl], nullptr);
+        for (int j = 0; j < nl; ++j)  // exact zeros / ones where the basis is at a node or a zero set
+            if (std::fabs(m.ploc64[(size_t)q * nl + j]) < 1e-15) m.ploc64[(size_t)q * nl + j] = 0.0;
+    }
+    m.ploc32.assign(m.ploc64.begin(), m.ploc64.end());
+    mass_matrix(p, m.mref64);
+    m.mref32.assign(m.mref64.begin(), m.mref64.end());
+
+    // device layout
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    for (auto& t : m.red) {
+        t.d_off = take(t.off.size() * 4);
+        t.d_ent = take(t.ent.size() * 4);
+        t.d_slot = take(t.slot.size() * 4);
+    }
+    for (auto& T : m.tab) {
+        T.d64 = take(T.t64.size() * 8);
+        T.d32 = take(T.t32.size() * 4);
+    }
+    m.d_fine_mi = take(m.fine_mi.size() * 4);
+    m.d_ploc64 = take(m.ploc64.size() * 8);
+    m.d_ploc32 = take(m.ploc32.size() * 4);
+    m.d_mref64 = take(m.mref64.size() * 8);
+    m.d_mref32 = take(m.mref32.size() * 4);
+    for (auto& L : m.lev) {
+        L.d_map = take(L.map.size() * 4);
+        L.d_G64 = take(L.G64.size() * 8);
+        L.d_G32 = take(L.G32.size() * 4);
+        L.d_slots = take((size_t)L.slot_elems * 8);
+        L.d_owner = take(L.owner.size() * 4);
+    }
+    m.bytes = off;
+    return FEM_OK;
+}
+
+}  // namespace fem

@@ -1,0 +1,175 @@
+// Launchers for the cell-wise kernels (stiffness action, diagonal, mass, transfers, adjoint
+// gradient): fill the kernel arguments from the mesh's device tables and dispatch the template
+// instance for the degree, brick size, coefficient kind and precision.
+#include "ops.hpp"
+#include "scatter.hpp"
+
+namespace fem {
+
+namespace {
+
+template <int KIND, typename T, int P, int B, bool KV>
+void launch_main(const SArgs<T>& a, int64_t nbricks, hipStream_t s) {
+    hipLaunchKernelGGL((k_brick<KIND, P, B, KV, T>), dim3((unsigned)nbricks), dim3(brick_threads(B)), 0, s, a);
+}
+
+template <int KIND, typename T, int P, int B>
+void launch_kv(bool kv, const SArgs<T>& a, int64_t nbricks, hipStream_t s) {
+    if constexpr (KIND == K_APPLY || KIND == K_DIAG) {
+        if (kv) { launch_main<KIND, T, P, B, true>(a, nbricks, s); return; }
+    }
+    launch_main<KIND, T, P, B, false>(a, nbricks, s);
+}
+
+template <int KIND, typename T, int P>
+void launch_b(int B, bool kv, const SArgs<T>& a, int64_t nbricks, hipStream_t s) {
+    if (B == 4) launch_kv<KIND, T, P, 4>(kv, a, nbricks, s);
+    else if (B == 2) launch_kv<KIND, T, P, 2>(kv, a, nbricks, s);
+    else launch_kv<KIND, T, P, 1>(kv, a, nbricks, s);
+}
+
+template <int KIND, typename T>
+void launch_p(int P, int B, bool kv, const SArgs<T>& a, int64_t nbricks, hipStream_t s) {
+    if (P == 1) launch_b<KIND, T, 1>(B, kv, a, nbricks, s);
+    else if (P == 2) launch_b<KIND, T, 2>(B, kv, a, nbricks, s);
+    else launch_b<KIND, T, 3>(B, kv, a, nbricks, s);
+}
+
+template <typename T, int PO>
+void launch_fix_b(int B, const SArgs<T>& a, int64_t c0, int64_t c1, int64_t tot, hipStream_t s) {
+    const unsigned grid = (unsigned)((tot + 255) / 256);
+    if (B == 4) hipLaunchKernelGGL((k_fixup<PO, 4, T>), dim3(grid), dim3(256), 0, s, a, c0, c1, tot);
+    else if (B == 2) hipLaunchKernelGGL((k_fixup<PO, 2, T>), dim3(grid), dim3(256), 0, s, a, c0, c1, tot);
+    else hipLaunchKernelGGL((k_fixup<PO, 1, T>), dim3(grid), dim3(256), 0, s, a, c0, c1, tot);
+}
+
+template <typename T>
+void launch_fix(int PO, int B, const SArgs<T>& a, int64_t c0, int64_t c1, int64_t tot, hipStream_t s) {
+    if (PO == 1) launch_fix_b<T, 1>(B, a, c0, c1, tot, s);
+    else if (PO == 2) launch_fix_b<T, 2>(B, a, c0, c1, tot, s);
+    else launch_fix_b<T, 3>(B, a, c0, c1, tot, s);
+}
+
+template <typename T>
+const T* tab_ptr(const fem_mesh& m, int kvar);
+template <>
+const double* tab_ptr<double>(const fem_mesh& m, int kvar) { return dptr<double>(m, m.tab[kvar].d64); }
+template <>
+const float* tab_ptr<float>(const fem_mesh& m, int kvar) { return dptr<float>(m, m.tab[kvar].d32); }
+
+template <typename T>
+size_t G_off(const HostLevel& L);
+template <>
+size_t G_off<double>(const HostLevel& L) { return L.d_G64; }
+template <>
+size_t G_off<float>(const HostLevel& L) { return L.d_G32; }
+
+template <typename T>
+size_t mref_off(const fem_mesh& m) { return sizeof(T) == 8 ? m.d_mref64 : m.d_mref32; }
+template <typename T>
+size_t ploc_off(const fem_mesh& m) { return sizeof(T) == 8 ? m.d_ploc64 : m.d_ploc32; }
+
+template <int KIND, typename T>
+fem_status run_kind(const fem_mesh& m, int level, bool kvar, const ScatterIO<T>& io, hipStream_t s) {
+    // level: the mesh level whose cells the kernel loops over
+    const HostLevel& L = m.lev[level];
+    const int po = (KIND == K_GRAD) ? 1 : m.p;
+    const RedTable& R = m.red[(KIND == K_GRAD) ? L.red1 : L.red];
+    SArgs<T> a{};
+    a.n = L.n;
+    a.nb = L.nb;
+    a.Lout = po * L.n + 1;
+    a.C = L.C;
+    a.map = dptr<int32_t>(m, L.d_map);
+    a.G = dptr<T>(m, G_off<T>(L));
+    a.tab = tab_ptr<T>(m, (KIND == K_GRAD) ? 1 : (kvar ? 1 : 0));
+    a.aux = (KIND == K_MASS) ? dptr<T>(m, mref_off<T>(m)) : (KIND == K_RESTRICT) ? dptr<T>(m, ploc_off<T>(m)) : nullptr;
+    a.fine_mi = dptr<int32_t>(m, m.d_fine_mi);
+    a.owner = (KIND == K_RESTRICT) ? dptr<uint32_t>(m, L.d_owner) : nullptr;
+    a.red_off = dptr<int32_t>(m, R.d_off);
+    a.red_ent = dptr<int32_t>(m, R.d_ent);
+    a.red_slot = dptr<int32_t>(m, R.d_slot);
+    a.slots = const_cast<T*>(dptr<T>(m, L.d_slots));
+    a.QB = R.QB;
+    a.mask_cols = io.mask_cols;
+    a.Lin = (KIND == K_RESTRICT) ? m.lev[level + 1].L : 0;
+    a.x = io.x;
+    a.x2 = io.x2;
+    a.k = io.k;
+    a.y = io.y;
+    a.z = io.z;
+    a.alpha = (T)io.alpha;
+    a.beta = (T)io.beta;
+    a.row_mode = io.row_mode;
+    a.xid = io.xid;
+    launch_p<KIND, T>(m.p, L.B, kvar, a, L.nbricks, s);
+    const int64_t Lo = a.Lout, nb = L.nb, np = Lo - nb - 1;
+    const int64_t c0 = (nb + 1) * Lo * Lo, c1 = (nb + 1) * np * Lo, c2 = (nb + 1) * np * np;
+    launch_fix<T>(po, L.B, a, c0, c1, c0 + c1 + c2, s);
+    return check_launch("scatter kernel");
+}
+
+}  // namespace
+
+template <typename T>
+fem_status run_scatter(const fem_mesh& m, int level, int kind, bool kvar, const ScatterIO<T>& io, hipStream_t s) {
+    switch (kind) {
+        case K_APPLY: return run_kind<K_APPLY, T>(m, level, kvar, io, s);
+        case K_DIAG: return run_kind<K_DIAG, T>(m, level, kvar, io, s);
+        case K_MASS: return run_kind<K_MASS, T>(m, level, false, io, s);
+        case K_RESTRICT: return run_kind<K_RESTRICT, T>(m, level, false, io, s);
+        case K_GRAD:
+            if constexpr (sizeof(T) == 8) return run_kind<K_GRAD, T>(m, level, false, io, s);
+            break;
+        default: break;
+    }
+    set_error("unsupported scatter kind");
+    return FEM_ERR_UNSUPPORTED;
+}
+
+template fem_status run_scatter<double>(const fem_mesh&, int, int, bool, const ScatterIO<double>&, hipStream_t);
+template fem_status run_scatter<float>(const fem_mesh&, int, int, bool, const ScatterIO<float>&, hipStream_t);
+
+namespace {
+template <typename T, int P>
+void launch_prolong_b(int B, const PArgs<T>& a, hipStream_t s) {
+    const unsigned grid = (unsigned)((a.C + 255) / 256);
+    if (B == 4) hipLaunchKernelGGL((k_prolong<P, 4, T>), dim3(grid), dim3(256), 0, s, a);
+    else if (B == 2) hipLaunchKernelGGL((k_prolong<P, 2, T>), dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_prolong<P, 1, T>), dim3(grid), dim3(256), 0, s, a);
+}
+}  // namespace
+
+template <typename T>
+fem_status run_prolong(const fem_mesh& m, int fine_level, const T* xc, T* xf, hipStream_t s) {
+    const HostLevel& Lc = m.lev[fine_level - 1];
+    PArgs<T> a{};
+    a.n = Lc.n;
+    a.nb = Lc.nb;
+    a.Lf = m.lev[fine_level].L;
+    a.C = Lc.C;
+    a.map = dptr<int32_t>(m, Lc.d_map);
+    a.owner = dptr<uint32_t>(m, Lc.d_owner);
+    a.fine_mi = dptr<int32_t>(m, m.d_fine_mi);
+    a.ploc = dptr<T>(m, ploc_off<T>(m));
+    a.xc = xc;
+    a.xf = xf;
+    if (m.p == 1) launch_prolong_b<T, 1>(Lc.B, a, s);
+    else if (m.p == 2) launch_prolong_b<T, 2>(Lc.B, a, s);
+    else launch_prolong_b<T, 3>(Lc.B, a, s);
+    return check_launch("prolongation kernel");
+}
+
+template fem_status run_prolong<double>(const fem_mesh&, int, const double*, double*, hipStream_t);
+template fem_status run_prolong<float>(const fem_mesh&, int, const float*, float*, hipStream_t);
+
+fem_status check_launch(const char* what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(std::string(what) + ": " + hipGetErrorString(e));
+        return FEM_ERR_HIP;
+    }
+    return FEM_OK;
+}
+
+}  // namespace fem

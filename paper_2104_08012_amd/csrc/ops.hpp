@@ -1,0 +1,36 @@
+// Host-side entry points of the device operations.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace fem {
+
+template <typename T>
+inline const T* dptr(const fem_mesh& m, size_t off) {
+    return reinterpret_cast<const T*>(m.dev + off);
+}
+
+template <typename T>
+struct ScatterIO {
+    const T* x = nullptr;
+    const T* x2 = nullptr;
+    const T* k = nullptr;
+    T* y = nullptr;
+    const T* z = nullptr;
+    double alpha = 1.0, beta = 0.0;
+    int row_mode = ROW_IDENTITY;
+    const T* xid = nullptr;
+    int mask_cols = 1;
+};
+
+// kind: K_APPLY, K_DIAG, K_MASS, K_RESTRICT (level = coarse level), K_GRAD (T = double).
+template <typename T>
+fem_status run_scatter(const fem_mesh& m, int level, int kind, bool kvar, const ScatterIO<T>& io, hipStream_t s);
+
+template <typename T>
+fem_status run_prolong(const fem_mesh& m, int fine_level, const T* xc, T* xf, hipStream_t s);
+
+fem_status check_launch(const char* what);
+
+}  // namespace fem

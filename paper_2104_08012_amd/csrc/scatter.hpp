@@ -1,0 +1,424 @@
+// Cell-wise kernels with a deterministic scatter-add, for gfx950.
+//
+// Every operator of the method that sums per-cell contributions into shared dofs (the stiffness
+// action, its diagonal, the mass action, the restriction and the adjoint gradient) runs through
+// the same two-kernel pattern:
+//
+//  1. k_brick: one workgroup per brick of B^3 cubes (6 B^3 cells, one cell per thread).  Each
+//     thread gathers its cell's inputs through the structure-of-arrays cell-to-dof map, forms the
+//     cell's local output vector (the "producer") and stores it in LDS.  After one barrier each
+//     thread sums, for some closure points of the brick, the LDS entries listed for that point in
+//     the brick reduction table, in the table's fixed order.  Points strictly inside the brick are
+//     owned by it alone and written straight to y; points on the brick's faces are written to a
+//     per-brick interface slot.
+//  2. k_fixup: one thread per brick-face lattice point sums the interface slots of the 1-8
+//     bricks that contain it, in ascending brick order, and writes y.
+//
+// No atomics and no colour passes: the result is bitwise reproducible for a given mesh, and
+// every output entry is written exactly once (so y need not be cleared, and y may alias z in
+// the axpby form y = alpha * (A x) + beta * z).
+//
+// Bricks are dealt to workgroups so that each of the 8 XCDs (separate L2 caches) receives a
+// contiguous range of bricks when the brick count is a multiple of 8.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace fem {
+
+template <typename T>
+struct SArgs {
+    int n, nb, Lout;                 // cubes per direction, bricks per direction, output lattice
+    int64_t C;                       // cells of the level the kernel loops over
+    const int32_t* map;              // SoA nloc * C (sign bit: boundary dof)
+    const T* G;                      // SoA 6 * C
+    const T* tab;                    // stiffness tabulation: per point w, lambda[4], D[3][nloc]
+    const T* aux;                    // mass: M_ref (nloc^2); restriction: P_loc (npts * nloc)
+    const int32_t* fine_mi;          // restriction: barycentric multi-index of each fine point
+    const uint32_t* owner;           // restriction: SoA owner masks of the coarse cells
+    const int32_t* red_off;
+    const int32_t* red_ent;
+    const int32_t* red_slot;
+    T* slots;                        // interface partials, QB per brick
+    int QB;
+    int mask_cols;                   // gather boundary dofs as zero
+    int Lin;                         // restriction: fine lattice size
+    const T* x;                      // input field (u for the gradient)
+    const T* x2;                     // second input (lambda for the gradient)
+    const T* k;                      // P1 coefficient on the vertex lattice, or null
+    T* y;                            // output (may alias z)
+    const T* z;
+    T alpha, beta;
+    int row_mode;                    // RowMode for boundary rows of the output
+    const T* xid;                    // values of identity rows
+};
+
+constexpr int brick_threads(int B) { return B == 4 ? 384 : 64; }
+
+__device__ __forceinline__ int brick_of_block(int bid, int nblocks) {
+    if ((nblocks & 7) == 0) {
+        const int per = nblocks >> 3;
+        return (bid & 7) * per + (bid >> 3);
+    }
+    return bid;
+}
+
+// Integer vertex coordinates of a cell from its brick and local index.
+template <int B>
+__device__ __forceinline__ void cell_vertices(int bx, int by, int bz, int cl, int V[4][3]) {
+    const int cube = cl / 6, t = cl - 6 * (cl / 6);
+    V[0][0] = bx * B + cube % B;
+    V[0][1] = by * B + (cube / B) % B;
+    V[0][2] = bz * B + cube / (B * B);
+    const int a0 = (t < 2) ? 0 : (t < 4) ? 1 : 2;
+    const int a1 = (t == 0 || t == 5) ? 1 : (t == 1 || t == 3) ? 2 : 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        V[1][k] = V[0][k] + (k == a0);
+        V[2][k] = V[1][k] + (k == a1);
+        V[3][k] = V[0][k] + 1;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T gather(const T* __restrict__ x, int32_t m, int mask) {
+    const uint32_t u = (uint32_t)m;
+    const T v = x[u & 0x7fffffffu];
+    return (mask && (m < 0)) ? T(0) : v;
+}
+
+// ---------------- producers: the per-cell local vector ----------------
+
+template <int KIND, int P, int B, bool KVAR, typename T>
+struct Producer;
+
+// Stiffness action: y_K = sum_q w_q k_q D_q^T G D_q x_K.
+template <int P, int B, bool KVAR, typename T>
+struct Producer<K_APPLY, P, B, KVAR, T> {
+    static constexpr int NL = nloc_of(P), NQ = nq_of(P, KVAR), ST = 5 + 3 * NL;
+    __device__ __forceinline__ static void run(const SArgs<T>& a, int64_t c, int cl, int bx, int by, int bz,
+                                               T* out) {
+        const T* __restrict__ tab = a.tab;
+        const int64_t C = a.C;
+        const T g00 = a.G[c], g11 = a.G[C + c], g22 = a.G[2 * C + c];
+        const T g01 = a.G[3 * C + c], g02 = a.G[4 * C + c], g12 = a.G[5 * C + c];
+        T xs[NL];
+#pragma unroll
+        for (int i = 0; i < NL; ++i) xs[i] = gather(a.x, a.map[i * C + c], a.mask_cols);
+        T kv[4] = {T(1), T(1), T(1), T(1)};
+        if constexpr (KVAR) {
+            int V[4][3];
+            cell_vertices<B>(bx, by, bz, cl, V);
+            const int n1 = a.n + 1;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) kv[v] = a.k[V[v][0] + n1 * (V[v][1] + n1 * V[v][2])];
+        }
+#pragma unroll
+        for (int i = 0; i < NL; ++i) out[i] = T(0);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const T* __restrict__ tq = tab + q * ST;
+            T gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                gx += tq[5 + i] * xs[i];
+                gy += tq[5 + NL + i] * xs[i];
+                gz += tq[5 + 2 * NL + i] * xs[i];
+            }
+            T s = tq[0];
+            if constexpr (KVAR) s *= tq[1] * kv[0] + tq[2] * kv[1] + tq[3] * kv[2] + tq[4] * kv[3];
+            const T wx = s * (g00 * gx + g01 * gy + g02 * gz);
+            const T wy = s * (g01 * gx + g11 * gy + g12 * gz);
+            const T wz = s * (g02 * gx + g12 * gy + g22 * gz);
+#pragma unroll
+            for (int i = 0; i < NL; ++i) out[i] += tq[5 + i] * wx + tq[5 + NL + i] * wy + tq[5 + 2 * NL + i] * wz;
+        }
+    }
+};
+
+// Diagonal: d_i = sum_q w_q k_q (D_q e_i)^T G (D_q e_i).
+template <int P, int B, bool KVAR, typename T>
+struct Producer<K_DIAG, P, B, KVAR, T> {
+    static constexpr int NL = nloc_of(P), NQ = nq_of(P, KVAR), ST = 5 + 3 * NL;
+    __device__ __forceinline__ static void run(const SArgs<T>& a, int64_t c, int cl, int bx, int by, int bz,
+                                               T* out) {
+        const T* __restrict__ tab = a.tab;
+        const int64_t C = a.C;
+        const T g00 = a.G[c], g11 = a.G[C + c], g22 = a.G[2 * C + c];
+        const T g01 = a.G[3 * C + c], g02 = a.G[4 * C + c], g12 = a.G[5 * C + c];
+        T kv[4] = {T(1), T(1), T(1), T(1)};
+        if constexpr (KVAR) {
+            int V[4][3];
+            cell_vertices<B>(bx, by, bz, cl, V);
+            const int n1 = a.n + 1;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) kv[v] = a.k[V[v][0] + n1 * (V[v][1] + n1 * V[v][2])];
+        }
+#pragma unroll
+        for (int i = 0; i < NL; ++i) out[i] = T(0);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const T* __restrict__ tq = tab + q * ST;
+            T s = tq[0];
+            if constexpr (KVAR) s *= tq[1] * kv[0] + tq[2] * kv[1] + tq[3] * kv[2] + tq[4] * kv[3];
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                const T dx = tq[5 + i], dy = tq[5 + NL + i], dz = tq[5 + 2 * NL + i];
+                out[i] += s * (g00 * dx * dx + g11 * dy * dy + g22 * dz * dz +
+                               T(2) * (g01 * dx * dy + g02 * dx * dz + g12 * dy * dz));
+            }
+        }
+    }
+};
+
+// Mass action: y_K = |det J| M_ref x_K, with |det J| = det G.
+template <int P, int B, bool KVAR, typename T>
+struct Producer<K_MASS, P, B, KVAR, T> {
+    static constexpr int NL = nloc_of(P);
+    __device__ __forceinline__ static void run(const SArgs<T>& a, int64_t c, int, int, int, int, T* out) {
+        const int64_t C = a.C;
+        const T g00 = a.G[c], g11 = a.G[C + c], g22 = a.G[2 * C + c];
+        const T g01 = a.G[3 * C + c], g02 = a.G[4 * C + c], g12 = a.G[5 * C + c];
+        const T det = g00 * (g11 * g22 - g12 * g12) - g01 * (g01 * g22 - g12 * g02) + g02 * (g01 * g12 - g11 * g02);
+        T xs[NL];
+#pragma unroll
+        for (int i = 0; i < NL; ++i) xs[i] = gather(a.x, a.map[i * C + c], a.mask_cols);
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            T s = T(0);
+#pragma unroll
+            for (int j = 0; j < NL; ++j) s += a.aux[i * NL + j] * xs[j];
+            out[i] = det * s;
+        }
+    }
+};
+
+// Restriction, per coarse cell: r_K[j] = sum over the fine points m owned by K of
+// P_loc[m][j] r_f[fine dof of m].
+template <int P, int B, bool KVAR, typename T>
+struct Producer<K_RESTRICT, P, B, KVAR, T> {
+    static constexpr int NL = nloc_of(P), NP = nfine_pts(P), NW = (NP + 31) / 32;
+    __device__ __forceinline__ static void run(const SArgs<T>& a, int64_t c, int cl, int bx, int by, int bz,
+                                               T* out) {
+        int V[4][3];
+        cell_vertices<B>(bx, by, bz, cl, V);
+        uint32_t w[NW];
+#pragma unroll
+        for (int i = 0; i < NW; ++i) w[i] = a.owner[i * a.C + c];
+#pragma unroll
+        for (int j = 0; j < NL; ++j) out[j] = T(0);
+        const int64_t Lf = a.Lin;
+#pragma unroll
+        for (int m = 0; m < NP; ++m) {
+            if ((w[m >> 5] >> (m & 31)) & 1u) {
+                const int* mi = a.fine_mi + 4 * m;
+                const int X = mi[0] * V[0][0] + mi[1] * V[1][0] + mi[2] * V[2][0] + mi[3] * V[3][0];
+                const int Y = mi[0] * V[0][1] + mi[1] * V[1][1] + mi[2] * V[2][1] + mi[3] * V[3][1];
+                const int Z = mi[0] * V[0][2] + mi[1] * V[1][2] + mi[2] * V[2][2] + mi[3] * V[3][2];
+                const T r = a.x[X + Lf * (Y + Lf * Z)];
+#pragma unroll
+                for (int j = 0; j < NL; ++j) out[j] += a.aux[m * NL + j] * r;
+            }
+        }
+    }
+};
+
+// Adjoint gradient, output on the 4 vertices: g_v = - sum_q w_q lambda_v(xi_q)
+// (D_q u_K)^T G (D_q l_K).
+template <int P, int B, bool KVAR, typename T>
+struct Producer<K_GRAD, P, B, KVAR, T> {
+    static constexpr int NL = nloc_of(P), NQ = nq_of(P, true), ST = 5 + 3 * NL;
+    __device__ __forceinline__ static void run(const SArgs<T>& a, int64_t c, int, int, int, int, T* out) {
+        const T* __restrict__ tab = a.tab;
+        const int64_t C = a.C;
+        const T g00 = a.G[c], g11 = a.G[C + c], g22 = a.G[2 * C + c];
+        const T g01 = a.G[3 * C + c], g02 = a.G[4 * C + c], g12 = a.G[5 * C + c];
+        T us[NL], ls[NL];
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int32_t m = a.map[i * C + c];
+            us[i] = gather(a.x, m, 1);
+            ls[i] = gather(a.x2, m, 1);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[v] = T(0);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const T* __restrict__ tq = tab + q * ST;
+            T ux = T(0), uy = T(0), uz = T(0), lx = T(0), ly = T(0), lz = T(0);
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                ux += tq[5 + i] * us[i];
+                uy += tq[5 + NL + i] * us[i];
+                uz += tq[5 + 2 * NL + i] * us[i];
+                lx += tq[5 + i] * ls[i];
+                ly += tq[5 + NL + i] * ls[i];
+                lz += tq[5 + 2 * NL + i] * ls[i];
+            }
+            const T s = tq[0] * (ux * (g00 * lx + g01 * ly + g02 * lz) + uy * (g01 * lx + g11 * ly + g12 * lz) +
+                                 uz * (g02 * lx + g12 * ly + g22 * lz));
+#pragma unroll
+            for (int v = 0; v < 4; ++v) out[v] -= tq[1 + v] * s;
+        }
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ void finalize(const SArgs<T>& a, int64_t g, T acc, bool bnd) {
+    T v = acc;
+    if (bnd) {
+        if (a.row_mode == ROW_IDENTITY) v = a.xid[g];
+        else if (a.row_mode == ROW_ZERO) v = T(0);
+        else if (a.row_mode == ROW_ONE) v = T(1);
+    }
+    T r = a.alpha * v;
+    if (a.beta != T(0)) r += a.beta * a.z[g];
+    a.y[g] = r;
+}
+
+template <int KIND, int P, int B, bool KVAR, typename T>
+__global__ void __launch_bounds__(brick_threads(B)) k_brick(SArgs<T> a) {
+    constexpr int PO = (KIND == K_GRAD) ? 1 : P;
+    constexpr int NLO = nloc_of(PO);
+    constexpr int NC = 6 * B * B * B;
+    constexpr int NT = brick_threads(B);
+    constexpr int PB = PO * B, QS = PB + 1, Q = QS * QS * QS;
+    __shared__ T ys[NLO * NC];
+    const int brick = brick_of_block(blockIdx.x, gridDim.x);
+    const int nb = a.nb;
+    const int bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
+    for (int cl = threadIdx.x; cl < NC; cl += NT) {
+        const int64_t c = (int64_t)brick * NC + cl;
+        T out[NLO];
+        Producer<KIND, P, B, KVAR, T>::run(a, c, cl, bx, by, bz, out);
+#pragma unroll
+        for (int i = 0; i < NLO; ++i) ys[i * NC + cl] = out[i];
+    }
+    __syncthreads();
+    const int64_t L = a.Lout;
+    for (int q = threadIdx.x; q < Q; q += NT) {
+        const int s = a.red_off[q], e = a.red_off[q + 1];
+        T acc = T(0);
+        for (int j = s; j < e; ++j) acc += ys[a.red_ent[j]];
+        const int slot = a.red_slot[q];
+        if (slot >= 0) {
+            a.slots[(int64_t)brick * a.QB + slot] = acc;
+        } else {
+            const int la = q % QS, lb = (q / QS) % QS, lc = q / (QS * QS);
+            const int64_t g = (bx * PB + la) + L * ((by * PB + lb) + L * (int64_t)(bz * PB + lc));
+            finalize(a, g, acc, false);
+        }
+    }
+}
+
+template <int PB>
+__device__ __forceinline__ int nonplane(int u) {
+    return (u / (PB - 1)) * PB + (u % (PB - 1)) + 1;
+}
+
+template <int PO, int B, typename T>
+__global__ void __launch_bounds__(256) k_fixup(SArgs<T> a, int64_t cnt0, int64_t cnt1, int64_t total) {
+    constexpr int PB = PO * B, QS = PB + 1;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int L = a.Lout, nb = a.nb;
+    const int np = L - nb - 1;   // lattice coordinates that are not on a brick plane
+    int I, J, K;
+    if (t < cnt0) {
+        const int64_t LL = (int64_t)L * L;
+        I = (int)(t / LL) * PB;
+        const int64_t r = t % LL;
+        J = (int)(r % L);
+        K = (int)(r / L);
+    } else if (t < cnt0 + cnt1) {
+        const int64_t u = t - cnt0, per = (int64_t)np * L;
+        J = (int)(u / per) * PB;
+        const int64_t r = u % per;
+        if constexpr (PB > 1) I = nonplane<PB>((int)(r % np)); else I = 0;
+        K = (int)(r / np);
+    } else {
+        const int64_t u = t - cnt0 - cnt1, per = (int64_t)np * np;
+        K = (int)(u / per) * PB;
+        const int64_t r = u % per;
+        if constexpr (PB > 1) {
+            I = nonplane<PB>((int)(r % np));
+            J = nonplane<PB>((int)(r / np));
+        } else {
+            I = J = 0;
+        }
+    }
+    int cb[3][2], cloc[3][2], cn[3];
+    const int X[3] = {I, J, K};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int x = X[d];
+        if (x % PB == 0) {
+            cn[d] = 0;
+            if (x / PB - 1 >= 0) { cb[d][cn[d]] = x / PB - 1; cloc[d][cn[d]] = PB; ++cn[d]; }
+            if (x / PB < nb) { cb[d][cn[d]] = x / PB; cloc[d][cn[d]] = 0; ++cn[d]; }
+        } else {
+            cn[d] = 1;
+            cb[d][0] = x / PB;
+            cloc[d][0] = x % PB;
+        }
+    }
+    T acc = T(0);
+    for (int iz = 0; iz < cn[2]; ++iz)
+        for (int iy = 0; iy < cn[1]; ++iy)
+            for (int ix = 0; ix < cn[0]; ++ix) {
+                const int64_t brick = cb[0][ix] + (int64_t)nb * (cb[1][iy] + (int64_t)nb * cb[2][iz]);
+                const int q = cloc[0][ix] + QS * (cloc[1][iy] + QS * cloc[2][iz]);
+                acc += a.slots[brick * a.QB + a.red_slot[q]];
+            }
+    const int64_t g = I + (int64_t)L * (J + (int64_t)L * K);
+    const bool bnd = I == 0 || J == 0 || K == 0 || I == L - 1 || J == L - 1 || K == L - 1;
+    finalize(a, g, acc, bnd);
+}
+
+// Prolongation, one thread per coarse cell: x_f[fine dof of m] += sum_j P_loc[m][j] x_c[map_j]
+// for the fine points m this coarse cell owns (each fine dof has exactly one owner).
+template <typename T>
+struct PArgs {
+    int n, nb, Lf;
+    int64_t C;
+    const int32_t* map;
+    const uint32_t* owner;
+    const int32_t* fine_mi;
+    const T* ploc;
+    const T* xc;
+    T* xf;
+};
+
+template <int P, int B, typename T>
+__global__ void __launch_bounds__(256) k_prolong(PArgs<T> a) {
+    constexpr int NL = nloc_of(P), NP = nfine_pts(P), NW = (NP + 31) / 32, NC = 6 * B * B * B;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.C) return;
+    const int brick = (int)(c / NC), cl = (int)(c % NC);
+    const int nb = a.nb;
+    int V[4][3];
+    cell_vertices<B>(brick % nb, (brick / nb) % nb, brick / (nb * nb), cl, V);
+    T e[NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) e[j] = gather(a.xc, a.map[j * a.C + c], 0);
+    uint32_t w[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) w[i] = a.owner[i * a.C + c];
+    const int64_t Lf = a.Lf;
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+        if ((w[m >> 5] >> (m & 31)) & 1u) {
+            const int* mi = a.fine_mi + 4 * m;
+            const int X = mi[0] * V[0][0] + mi[1] * V[1][0] + mi[2] * V[2][0] + mi[3] * V[3][0];
+            const int Y = mi[0] * V[0][1] + mi[1] * V[1][1] + mi[2] * V[2][1] + mi[3] * V[3][1];
+            const int Z = mi[0] * V[0][2] + mi[1] * V[1][2] + mi[2] * V[2][2] + mi[3] * V[3][2];
+            T s = T(0);
+#pragma unroll
+            for (int j = 0; j < NL; ++j) s += a.ploc[m * NL + j] * e[j];
+            a.xf[X + Lf * (Y + Lf * Z)] += s;
+        }
+    }
+}
+
+}  // namespace fem

@@ -1,0 +1,157 @@
+"""GPU parity of the cell-wise kernels against the oracle, through the C ABI.
+
+Tolerances: FP64 actions 1e-12 relative (2-norm, random x ~ U(-1,1)); FP32 actions 2e-6
+relative (single-precision rounding of ~30 terms per entry on the uniform mesh); transfers,
+diagonal, mass and gradient 1e-12 in FP64.  Mesh sizes span several bricks and odd sizes that
+fall back to smaller bricks (n = 5: 1-cube bricks, n = 6: 2-cube bricks).
+"""
+import numpy as np
+import pytest
+
+import fem_inputs
+from oracle import adjoint as oadj
+from oracle import assemble, transfer
+from tests.gpu_util import banner, make_pair, oracle_A, rel
+
+torch = pytest.importorskip("torch")
+
+CASES = [(5, 1, 0.0), (6, 2, 0.15), (8, 1, 0.0), (8, 2, 0.15), (8, 3, 0.15), (12, 2, 0.0), (4, 3, 0.0)]
+
+
+def _t(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda:0")
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,p,jit", CASES)
+@pytest.mark.parametrize("kvar", [False, True])
+def test_apply_fp64_parity(n, p, jit, kvar):
+    banner(f"apply fp64 n={n} p={p} jit={jit} kvar={kvar}")
+    mesh, levels = make_pair(n, 0, p, jit)
+    lev = levels[0]
+    k = fem_inputs.k_exp_fourier(lev.vert_xyz) if kvar else None
+    x = fem_inputs.uniform_vector(lev.n_dofs, 0)
+    kt = _t(k) if kvar else None
+    for bc in ("identity", "none", "zero_rows"):
+        y = mesh.apply(_t(x), kt, level=0, bc=bc)
+        torch.cuda.synchronize()
+        y_ref = oracle_A(lev, k, bc) @ x
+        assert rel(y.cpu().numpy(), y_ref) <= 1e-12, bc
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,p,jit", [(8, 2, 0.15), (6, 3, 0.0), (5, 1, 0.15)])
+@pytest.mark.parametrize("kvar", [False, True])
+def test_apply_fp32_parity(n, p, jit, kvar):
+    banner(f"apply fp32 n={n} p={p} kvar={kvar}")
+    mesh, levels = make_pair(n, 0, p, jit)
+    lev = levels[0]
+    k = fem_inputs.k_exp_fourier(lev.vert_xyz) if kvar else None
+    x = fem_inputs.uniform_vector(lev.n_dofs, 0)
+    y = mesh.apply(_t(x, torch.float32), _t(k, torch.float32) if kvar else None, level=0)
+    torch.cuda.synchronize()
+    y_ref = oracle_A(lev, k) @ x
+    assert rel(y.cpu().numpy(), y_ref) <= 2e-6
+
+
+@pytest.mark.gpu
+def test_apply_axpby_and_determinism():
+    banner("apply axpby / determinism")
+    mesh, levels = make_pair(8, 0, 2, 0.15)
+    lev = levels[0]
+    x = fem_inputs.uniform_vector(lev.n_dofs, 0)
+    z = fem_inputs.uniform_vector(lev.n_dofs, 7)
+    xt, zt = _t(x), _t(z)
+    y1 = mesh.apply(xt)
+    y2 = mesh.apply(xt)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    r = zt.clone()
+    mesh.apply(xt, out=r, alpha=-1.0, z=r, beta=1.0)      # in place: r = z - A x
+    torch.cuda.synchronize()
+    ref = z - oracle_A(lev) @ x
+    assert rel(r.cpu().numpy(), ref) <= 1e-12
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,p,jit", [(8, 2, 0.15), (6, 3, 0.0), (5, 1, 0.0)])
+def test_mass_parity(n, p, jit):
+    banner(f"mass n={n} p={p}")
+    mesh, levels = make_pair(n, 0, p, jit)
+    lev = levels[0]
+    x = fem_inputs.uniform_vector(lev.n_dofs, 0)
+    M = assemble.mass(lev)
+    y = mesh.mass(_t(x), level=0, bc="none")
+    yz = mesh.mass(_t(x), level=0, bc="zero_rows")
+    torch.cuda.synchronize()
+    assert rel(y.cpu().numpy(), M @ x) <= 1e-12
+    ref = M @ x
+    ref[lev.boundary] = 0
+    assert rel(yz.cpu().numpy(), ref) <= 1e-12
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,p,jit", [(8, 2, 0.15), (6, 3, 0.0), (5, 1, 0.0)])
+@pytest.mark.parametrize("kvar", [False, True])
+def test_diagonal_parity(n, p, jit, kvar):
+    banner(f"diag n={n} p={p} kvar={kvar}")
+    mesh, levels = make_pair(n, 0, p, jit)
+    lev = levels[0]
+    k = fem_inputs.k_exp_fourier(lev.vert_xyz) if kvar else None
+    d = mesh.diagonal(_t(k) if kvar else None, level=0)
+    torch.cuda.synchronize()
+    assert rel(d.cpu().numpy(), oracle_A(lev, k).diagonal()) <= 1e-12
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,p,jit", [(2, 1, 0.0), (4, 2, 0.15), (3, 3, 0.15), (6, 2, 0.0), (4, 3, 0.0)])
+def test_transfer_parity(n, p, jit):
+    banner(f"transfers n={n} p={p}")
+    mesh, levels = make_pair(n, 1, p, jit)
+    P = transfer.prolongation(levels[0], levels[1])
+    xc = fem_inputs.uniform_vector(levels[0].n_dofs, 0)
+    xf0 = fem_inputs.uniform_vector(levels[1].n_dofs, 1)
+    xf = _t(xf0)
+    mesh.prolong(_t(xc), xf, 1)
+    rf = fem_inputs.uniform_vector(levels[1].n_dofs, 2)
+    rc = mesh.restrict(_t(rf), 1)
+    torch.cuda.synchronize()
+    assert rel(xf.cpu().numpy(), xf0 + P @ xc) <= 1e-12
+    rc_ref = P.T @ rf
+    rc_ref[levels[0].boundary] = 0
+    assert rel(rc.cpu().numpy(), rc_ref) <= 1e-12
+    xf32 = _t(xf0, torch.float32)
+    mesh.prolong(_t(xc, torch.float32), xf32, 1)
+    rc32 = mesh.restrict(_t(rf, torch.float32), 1)
+    torch.cuda.synchronize()
+    assert rel(xf32.cpu().numpy(), xf0 + P @ xc) <= 2e-6
+    assert rel(rc32.cpu().numpy(), rc_ref) <= 2e-6
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,p,jit", [(8, 2, 0.15), (6, 3, 0.0), (5, 1, 0.15), (4, 2, 0.0)])
+def test_adjoint_grad_parity(n, p, jit):
+    banner(f"grad n={n} p={p}")
+    mesh, levels = make_pair(n, 0, p, jit)
+    lev = levels[0]
+    u = fem_inputs.uniform_vector(lev.n_dofs, 0)
+    lam = fem_inputs.uniform_vector(lev.n_dofs, 1)
+    u[lev.boundary] = 0
+    lam[lev.boundary] = 0
+    g = mesh.adjoint_grad_k(_t(u), _t(lam), level=0)
+    torch.cuda.synchronize()
+    g_ref = oadj.gradient_from_fields(lev, u, lam)
+    assert rel(g.cpu().numpy(), g_ref) <= 1e-12
+
+
+@pytest.mark.gpu
+def test_invalid_arguments_rejected_before_launch():
+    from paper_2104_08012_amd._lib import FemError
+    mesh, levels = make_pair(4, 0, 2, 0.0)
+    x = torch.zeros(levels[0].n_dofs, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(ValueError):
+        mesh.apply(x[:-1])
+    with pytest.raises(FemError):
+        mesh.apply(x, out=x)
+    with pytest.raises(FemError):
+        mesh.info(7)
