@@ -143,6 +143,7 @@ fem_status fem_restrict(const fem_mesh* mesh, int32_t fine_level, fem_dtype dtyp
 /* Solver */
 enum { FEM_PREC_FP64 = 0, FEM_PREC_MIXED = 1 };
 enum { FEM_COARSE_AUTO = 0, FEM_COARSE_DENSE = 1, FEM_COARSE_NESTED = 2 };
+enum { FEM_PC_MG = 0, FEM_PC_JACOBI = 1 };
 
 typedef struct {
     double rtol;                 /* stop when ||b - A x|| / ||b|| <= rtol                       */
@@ -160,7 +161,7 @@ typedef struct {
     int32_t flexible;            /* 1: Polak-Ribiere beta                                       */
     double* history;             /* host, may be NULL: relative residual per iteration          */
     int32_t history_cap;
-    int32_t pad;
+    int32_t preconditioner;      /* FEM_PC_MG (V-cycle) or FEM_PC_JACOBI (diag(A)^-1 on the finest level) */
 } fem_solve_opts;
 
 typedef struct {

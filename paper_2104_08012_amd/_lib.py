@@ -31,6 +31,8 @@ FEM_PREC_MIXED = 1
 FEM_COARSE_AUTO = 0
 FEM_COARSE_DENSE = 1
 FEM_COARSE_NESTED = 2
+FEM_PC_MG = 0
+FEM_PC_JACOBI = 1
 
 
 class MeshDesc(C.Structure):
@@ -50,7 +52,8 @@ class SolveOpts(C.Structure):
                 ("cheb_lo", C.c_double), ("cheb_hi", C.c_double), ("eig_iters", C.c_int32),
                 ("coarse_method", C.c_int32), ("lambda_max_override", C.POINTER(C.c_double)),
                 ("coarse_rtol", C.c_double), ("replace_every", C.c_int32), ("flexible", C.c_int32),
-                ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int32), ("pad", C.c_int32)]
+                ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int32),
+                ("preconditioner", C.c_int32)]
 
 
 class SolveStats(C.Structure):

@@ -74,7 +74,6 @@ fem_status run_kind(const fem_mesh& m, int level, bool kvar, const ScatterIO<T>&
     // level: the mesh level whose cells the kernel loops over
     const HostLevel& L = m.lev[level];
     const int po = (KIND == K_GRAD) ? 1 : m.p;
-    const RedTable& R = m.red[(KIND == K_GRAD) ? L.red1 : L.red];
     SArgs<T> a{};
     a.n = L.n;
     a.nb = L.nb;
@@ -86,11 +85,7 @@ fem_status run_kind(const fem_mesh& m, int level, bool kvar, const ScatterIO<T>&
     a.aux = (KIND == K_MASS) ? dptr<T>(m, mref_off<T>(m)) : (KIND == K_RESTRICT) ? dptr<T>(m, ploc_off<T>(m)) : nullptr;
     a.fine_mi = dptr<int32_t>(m, m.d_fine_mi);
     a.owner = (KIND == K_RESTRICT) ? dptr<uint32_t>(m, L.d_owner) : nullptr;
-    a.red_off = dptr<int32_t>(m, R.d_off);
-    a.red_ent = dptr<int32_t>(m, R.d_ent);
-    a.red_slot = dptr<int32_t>(m, R.d_slot);
     a.slots = const_cast<T*>(dptr<T>(m, L.d_slots));
-    a.QB = R.QB;
     a.mask_cols = io.mask_cols;
     a.Lin = (KIND == K_RESTRICT) ? m.lev[level + 1].L : 0;
     a.x = io.x;

@@ -23,7 +23,10 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "common.hpp"
+#include "incidence.hpp"
 
 namespace fem {
 
@@ -37,11 +40,7 @@ struct SArgs {
     const T* aux;                    // mass: M_ref (nloc^2); restriction: P_loc (npts * nloc)
     const int32_t* fine_mi;          // restriction: barycentric multi-index of each fine point
     const uint32_t* owner;           // restriction: SoA owner masks of the coarse cells
-    const int32_t* red_off;
-    const int32_t* red_ent;
-    const int32_t* red_slot;
-    T* slots;                        // interface partials, QB per brick
-    int QB;
+    T* slots;                        // interface partials, box_slots(PO B) per brick
     int mask_cols;                   // gather boundary dofs as zero
     int Lin;                         // restriction: fine lattice size
     const T* x;                      // input field (u for the gradient)
@@ -277,13 +276,48 @@ __device__ __forceinline__ void finalize(const SArgs<T>& a, int64_t g, T acc, bo
     a.y[g] = r;
 }
 
+// Sum, for every closure point of one type, the LDS entries of the cells that contain it (in the
+// fixed order of the incidence table), then write the point: to y if it lies strictly inside the
+// brick, else to the brick's interface slot.
+template <int PO, int B, int TY, typename T>
+__device__ __forceinline__ void reduce_type(const SArgs<T>& a, const T* ys, int brick, int bx, int by, int bz) {
+    constexpr Incidence<PO> INC{};
+    constexpr int ta = TY % PO, tb = (TY / PO) % PO, tc = TY / (PO * PO);
+    constexpr int ea = B + (ta == 0), eb = B + (tb == 0), ec = B + (tc == 0);
+    constexpr int NPTS = ea * eb * ec, CNT = INC.cnt[TY];
+    constexpr int NC = 6 * B * B * B, NT = brick_threads(B), PB = PO * B, QB = box_slots<PB>();
+    const int64_t L = a.Lout;
+    for (int idx = threadIdx.x; idx < NPTS; idx += NT) {
+        const int ka = idx % ea, kb = (idx / ea) % eb, kc = idx / (ea * eb);
+        T acc = T(0);
+#pragma unroll
+        for (int e = 0; e < CNT; ++e) {
+            const int X = ka + INC.dx[TY][e], Y = kb + INC.dy[TY][e], Z = kc + INC.dz[TY][e];
+            if (X >= 0 && X < B && Y >= 0 && Y < B && Z >= 0 && Z < B)
+                acc += ys[INC.i[TY][e] * NC + (X + B * (Y + B * Z)) * 6 + INC.t[TY][e]];
+        }
+        const int la = ta + PO * ka, lb = tb + PO * kb, lc = tc + PO * kc;
+        if (la == 0 || la == PB || lb == 0 || lb == PB || lc == 0 || lc == PB) {
+            a.slots[(int64_t)brick * QB + box_slot<PB>(la, lb, lc)] = acc;
+        } else {
+            const int64_t g = (bx * PB + la) + L * ((by * PB + lb) + L * (int64_t)(bz * PB + lc));
+            finalize(a, g, acc, false);
+        }
+    }
+}
+
+template <int PO, int B, typename T, int... TYs>
+__device__ __forceinline__ void reduce_all(const SArgs<T>& a, const T* ys, int brick, int bx, int by, int bz,
+                                           std::integer_sequence<int, TYs...>) {
+    (reduce_type<PO, B, TYs, T>(a, ys, brick, bx, by, bz), ...);
+}
+
 template <int KIND, int P, int B, bool KVAR, typename T>
 __global__ void __launch_bounds__(brick_threads(B)) k_brick(SArgs<T> a) {
     constexpr int PO = (KIND == K_GRAD) ? 1 : P;
     constexpr int NLO = nloc_of(PO);
     constexpr int NC = 6 * B * B * B;
     constexpr int NT = brick_threads(B);
-    constexpr int PB = PO * B, QS = PB + 1, Q = QS * QS * QS;
     __shared__ T ys[NLO * NC];
     const int brick = brick_of_block(blockIdx.x, gridDim.x);
     const int nb = a.nb;
@@ -296,20 +330,7 @@ __global__ void __launch_bounds__(brick_threads(B)) k_brick(SArgs<T> a) {
         for (int i = 0; i < NLO; ++i) ys[i * NC + cl] = out[i];
     }
     __syncthreads();
-    const int64_t L = a.Lout;
-    for (int q = threadIdx.x; q < Q; q += NT) {
-        const int s = a.red_off[q], e = a.red_off[q + 1];
-        T acc = T(0);
-        for (int j = s; j < e; ++j) acc += ys[a.red_ent[j]];
-        const int slot = a.red_slot[q];
-        if (slot >= 0) {
-            a.slots[(int64_t)brick * a.QB + slot] = acc;
-        } else {
-            const int la = q % QS, lb = (q / QS) % QS, lc = q / (QS * QS);
-            const int64_t g = (bx * PB + la) + L * ((by * PB + lb) + L * (int64_t)(bz * PB + lc));
-            finalize(a, g, acc, false);
-        }
-    }
+    reduce_all<PO, B, T>(a, ys, brick, bx, by, bz, std::make_integer_sequence<int, PO * PO * PO>{});
 }
 
 template <int PB>
@@ -319,7 +340,7 @@ __device__ __forceinline__ int nonplane(int u) {
 
 template <int PO, int B, typename T>
 __global__ void __launch_bounds__(256) k_fixup(SArgs<T> a, int64_t cnt0, int64_t cnt1, int64_t total) {
-    constexpr int PB = PO * B, QS = PB + 1;
+    constexpr int PB = PO * B;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
     const int L = a.Lout, nb = a.nb;
@@ -368,8 +389,7 @@ __global__ void __launch_bounds__(256) k_fixup(SArgs<T> a, int64_t cnt0, int64_t
         for (int iy = 0; iy < cn[1]; ++iy)
             for (int ix = 0; ix < cn[0]; ++ix) {
                 const int64_t brick = cb[0][ix] + (int64_t)nb * (cb[1][iy] + (int64_t)nb * cb[2][iz]);
-                const int q = cloc[0][ix] + QS * (cloc[1][iy] + QS * cloc[2][iz]);
-                acc += a.slots[brick * a.QB + a.red_slot[q]];
+                acc += a.slots[brick * box_slots<PB>() + box_slot<PB>(cloc[0][ix], cloc[1][iy], cloc[2][iz])];
             }
     const int64_t g = I + (int64_t)L * (J + (int64_t)L * K);
     const bool bnd = I == 0 || J == 0 || K == 0 || I == L - 1 || J == L - 1 || K == L - 1;

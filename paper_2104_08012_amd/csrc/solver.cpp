@@ -1,0 +1,744 @@
+// Multigrid-preconditioned conjugate gradients (host orchestration of the device kernels).
+//
+// Method (paper Section 4 and Listing 2): a geometric multigrid cycle over the uniformly refined
+// hierarchy, two Chebyshev iterations per level before and after the coarse correction, a direct
+// solve on the coarsest level used, here as the preconditioner of CG on the finest level.
+//   * Smoother: Chebyshev on D^-1 A over [lo, hi] * lambda_max (three-term recurrence of Saad,
+//     Iterative Methods for Sparse Linear Systems, Alg. 12.1), the same polynomial before and after
+//     the coarse correction so the cycle is symmetric; lambda_max from the largest Ritz value of a
+//     few Lanczos steps on D^-1 A started from a counter-based random vector.
+//   * Transfers: prolongation interpolates the coarse function at the fine nodes; restriction is
+//     its transpose with boundary rows zeroed; level operators are rediscretised with the
+//     coefficient injected at the coarse vertices.
+//   * Coarsest level: exact FP64 solve with the dense inverse of the interior block, assembled by
+//     probing the matrix-free operator with (2p+1)^3 colour vectors and inverted by a blocked
+//     Gauss-Jordan sweep.
+//   * Outer CG in FP64: x0 given (usually 0), stop when the true residual satisfies
+//     ||b - A x|| / ||b|| <= rtol.  Mixed precision keeps CG vectors, the outer operator, all
+//     inner products and the coarse solve in FP64 and runs the smoother, the level residuals and
+//     the transfers in FP32, casting at the entry and exit of the cycle and at the coarse level;
+//     the Polak-Ribiere beta and periodic true-residual replacement make CG tolerant of the
+//     slightly varying FP32 preconditioner.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vec.hpp"
+
+using namespace fem;
+
+namespace {
+
+struct LevelWs {
+    size_t x = 0, b = 0, r = 0, d = 0, dinv = 0, k64 = 0, k32 = 0, b64 = 0, x64 = 0;
+};
+
+struct Layout {
+    std::vector<LevelWs> lev;
+    size_t cg_r = 0, cg_z = 0, cg_p = 0, cg_q = 0, partial = 0, scal = 0, dense = 0, dense_xc = 0, jac_diag = 0;
+    size_t total = 0;
+    int lo = 0, hi = 0, mixed = 0;
+    int64_t dense_n = 0;
+};
+
+fem_status make_layout(const fem_mesh& m, const fem_solve_opts& o, bool with_k, Layout& L) {
+    L.hi = m.nlev - 1;
+    const int used = (o.n_levels_used <= 0 || o.n_levels_used > m.nlev) ? m.nlev : o.n_levels_used;
+    L.lo = m.nlev - used;
+    L.mixed = o.precision == FEM_PREC_MIXED;
+    const size_t ts = L.mixed ? 4 : 8;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t r = off;
+        off = align256(off + bytes);
+        return r;
+    };
+    L.lev.assign(m.nlev, LevelWs{});
+    for (int l = 0; l < m.nlev; ++l) {
+        const int64_t N = m.lev[l].N, NV = m.lev[l].NV;
+        LevelWs& w = L.lev[l];
+        if (with_k) {
+            w.k64 = take(NV * 8);
+            if (L.mixed) w.k32 = take(NV * 4);
+        }
+        if (l < L.lo) continue;
+        w.x = take(N * ts);
+        w.b = take(N * ts);
+        w.r = take(N * ts);
+        w.d = take(N * ts);
+        w.dinv = take(N * ts);
+        if (l == L.lo && L.mixed) {
+            w.b64 = take(N * 8);
+            w.x64 = take(N * 8);
+        }
+    }
+    const int64_t Nf = m.lev[L.hi].N;
+    L.cg_r = take(Nf * 8);
+    L.cg_z = take(Nf * 8);
+    L.cg_p = take(Nf * 8);
+    L.cg_q = take(Nf * 8);
+    L.partial = take(dot_partial_doubles() * 8);
+    L.scal = take(64 * 8);
+    if (o.preconditioner == FEM_PC_JACOBI) {
+        L.jac_diag = take(Nf * 8);
+        L.dense_n = 0;
+        L.total = off;
+        return FEM_OK;
+    }
+    const HostLevel& C = m.lev[L.lo];
+    const int64_t M = C.L - 2;
+    L.dense_n = M * M * M;
+    const int method = o.coarse_method;
+    if (method == FEM_COARSE_NESTED) {
+        set_error("nested coarse solver is not available in this build");
+        return FEM_ERR_UNSUPPORTED;
+    }
+    if (L.dense_n > 40000) {
+        set_error("coarsest level too large for the dense coarse solve (" + std::to_string(L.dense_n) +
+                  " interior dofs > 40000); use more levels");
+        return FEM_ERR_UNSUPPORTED;
+    }
+    L.dense = take((size_t)L.dense_n * L.dense_n * 8);
+    L.dense_xc = take(std::max<int64_t>(L.dense_n, 1) * 8);
+    L.total = off;
+    return FEM_OK;
+}
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Largest eigenvalue of a small symmetric tridiagonal matrix (cyclic Jacobi on a dense copy).
+double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
+    const int n = (int)a.size();
+    std::vector<double> A(n * n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        A[i * n + i] = a[i];
+        if (i + 1 < n) A[i * n + i + 1] = A[(i + 1) * n + i] = b[i];
+    }
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) off += A[i * n + j] * A[i * n + j];
+        if (off < 1e-30) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[p * n + q];
+                if (std::fabs(apq) < 1e-300) continue;
+                const double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {
+                    const double akp = A[k * n + p], akq = A[k * n + q];
+                    A[k * n + p] = c * akp - s * akq;
+                    A[k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double apk = A[p * n + k], aqk = A[q * n + k];
+                    A[p * n + k] = c * apk - s * aqk;
+                    A[q * n + k] = s * apk + c * aqk;
+                }
+            }
+    }
+    double mx = -1e300;
+    for (int i = 0; i < n; ++i) mx = std::max(mx, A[i * n + i]);
+    return mx;
+}
+
+}  // namespace
+
+struct fem_solver {
+    const fem_mesh* m = nullptr;
+    fem_solve_opts o{};
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout L;
+    bool kvar = false;
+    bool ready = false;
+    std::vector<double> lmax;
+    double* hscal = nullptr;   // pinned host scalars
+    hipStream_t s = nullptr;
+    double coarse_ms = 0.0;
+    std::vector<double> level_ms;
+    int coarse_iters = 0;
+    std::vector<hipEvent_t> ev;   // per level: pre start/end, post start/end; coarse start/end
+    bool timing = true;
+
+    template <typename T>
+    T* p(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+
+    fem_status apply64(int l, const double* x, double alpha, const double* z, double beta, double* y) {
+        ScatterIO<double> io;
+        io.x = x;
+        io.k = kvar ? p<double>(L.lev[l].k64) : nullptr;
+        io.y = y;
+        io.z = z;
+        io.alpha = alpha;
+        io.beta = beta;
+        io.row_mode = ROW_IDENTITY;
+        io.xid = x;
+        io.mask_cols = 1;
+        return run_scatter<double>(*m, l, K_APPLY, kvar, io, s);
+    }
+    template <typename T>
+    fem_status applyT(int l, const T* x, double alpha, const T* z, double beta, T* y);
+
+    fem_status dots(int npair, int64_t n, const double* x0, const double* y0, const double* x1, const double* y1,
+                    const double* x2, const double* y2, double* out) {
+        DotPairs<double> pr{{x0, x1, x2}, {y0, y1, y2}};
+        dot_launch<double>(npair, n, pr, p<double>(L.partial), p<double>(L.scal), s);
+        hipError_t e = hipMemcpyAsync(hscal, p<double>(L.scal), npair * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            set_error(std::string("solver reduction: ") + hipGetErrorString(e));
+            return FEM_ERR_HIP;
+        }
+        for (int i = 0; i < npair; ++i) out[i] = hscal[i];
+        return FEM_OK;
+    }
+
+    template <typename T>
+    fem_status vcycle(int l, const T* b, T* x);
+    fem_status coarse_solve_from(const double* b64, double* x64);
+    fem_status setup(const double* k);
+    fem_status lanczos(int l, double& lm);
+};
+
+template <>
+fem_status fem_solver::applyT<double>(int l, const double* x, double alpha, const double* z, double beta, double* y) {
+    return apply64(l, x, alpha, z, beta, y);
+}
+template <>
+fem_status fem_solver::applyT<float>(int l, const float* x, double alpha, const float* z, double beta, float* y) {
+    ScatterIO<float> io;
+    io.x = x;
+    io.k = kvar ? p<float>(L.lev[l].k32) : nullptr;
+    io.y = y;
+    io.z = z;
+    io.alpha = alpha;
+    io.beta = beta;
+    io.row_mode = ROW_IDENTITY;
+    io.xid = x;
+    io.mask_cols = 1;
+    return run_scatter<float>(*m, l, K_APPLY, kvar, io, s);
+}
+
+fem_status fem_solver::coarse_solve_from(const double* b64, double* x64) {
+    const HostLevel& C = m->lev[L.lo];
+    dense_solve_launch(C.L, p<double>(L.dense), b64, p<double>(L.dense_xc), x64, s);
+    return check_launch("coarse solve");
+}
+
+#define FEM_TRY(expr)                   \
+    do {                                \
+        const fem_status _st = (expr);  \
+        if (_st != FEM_OK) return _st;  \
+    } while (0)
+
+template <typename T>
+fem_status fem_solver::vcycle(int l, const T* b, T* x) {
+    const int nl = (int)m->lev.size();
+    hipEvent_t* e = timing ? &ev[4 * l] : nullptr;
+    if (l == L.lo) {
+        if (timing) hipEventRecord(ev[4 * nl], s);
+        if (L.mixed) {
+            const int64_t n = m->lev[l].N;
+            cast_launch<T, double>(n, b, p<double>(L.lev[l].b64), s);
+            FEM_TRY(coarse_solve_from(p<double>(L.lev[l].b64), p<double>(L.lev[l].x64)));
+            cast_launch<double, T>(n, p<double>(L.lev[l].x64), x, s);
+        } else {
+            FEM_TRY(coarse_solve_from(reinterpret_cast<const double*>(b), reinterpret_cast<double*>(x)));
+        }
+        if (timing) hipEventRecord(ev[4 * nl + 1], s);
+        return FEM_OK;
+    }
+    const HostLevel& H = m->lev[l];
+    const int64_t n = H.N;
+    const LevelWs& w = L.lev[l];
+    T* r = p<T>(w.r);
+    T* d = p<T>(w.d);
+    const T* dinv = p<T>(w.dinv);
+    const int deg = std::max(1, o.cheb_degree);
+    const double lm = lmax[l];
+    const double a = o.cheb_lo * lm, bb = o.cheb_hi * lm;
+    const double theta = 0.5 * (bb + a), delta = 0.5 * (bb - a), sigma = theta / delta;
+    if (timing) hipEventRecord(e[0], s);
+    // pre-smoothing from x = 0; r tracks b - A x
+    double rho = 1.0 / sigma;
+    cheb_launch<T>(n, 0.0, 1.0 / theta, dinv, b, d, x, true, true, s);
+    FEM_TRY(applyT<T>(l, d, -1.0, b, 1.0, r));
+    for (int k = 1; k < deg; ++k) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        cheb_launch<T>(n, rn * rho, 2.0 * rn / delta, dinv, r, d, x, false, false, s);
+        rho = rn;
+        FEM_TRY(applyT<T>(l, d, -1.0, r, 1.0, r));
+    }
+    // coarse-grid correction
+    T* bc = p<T>(L.lev[l - 1].b);
+    T* xc = p<T>(L.lev[l - 1].x);
+    {
+        ScatterIO<T> io;
+        io.x = r;
+        io.y = bc;
+        io.row_mode = ROW_ZERO;
+        FEM_TRY(run_scatter<T>(*m, l - 1, K_RESTRICT, false, io, s));
+    }
+    if (timing) hipEventRecord(e[1], s);
+    FEM_TRY(vcycle<T>(l - 1, bc, xc));
+    if (timing) hipEventRecord(e[2], s);
+    FEM_TRY(run_prolong<T>(*m, l, xc, x, s));
+    // post-smoothing from x
+    FEM_TRY(applyT<T>(l, x, -1.0, b, 1.0, r));
+    rho = 1.0 / sigma;
+    cheb_launch<T>(n, 0.0, 1.0 / theta, dinv, r, d, x, true, false, s);
+    for (int k = 1; k < deg; ++k) {
+        FEM_TRY(applyT<T>(l, d, -1.0, r, 1.0, r));
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        cheb_launch<T>(n, rn * rho, 2.0 * rn / delta, dinv, r, d, x, false, false, s);
+        rho = rn;
+    }
+    if (timing) hipEventRecord(e[3], s);
+    return FEM_OK;
+}
+
+// Largest Ritz value of o.eig_iters Lanczos steps on D^-1 A in the D inner product (FP64, using
+// the four FP64 CG vectors as scratch: v, w, v_prev and the diagonal D).
+fem_status fem_solver::lanczos(int l, double& lm) {
+    const HostLevel& H = m->lev[l];
+    const int64_t n = H.N;
+    double* v = p<double>(L.cg_r);
+    double* wv = p<double>(L.cg_z);
+    double* vp = p<double>(L.cg_p);
+    double* dg = p<double>(L.cg_q);
+    {
+        ScatterIO<double> io;
+        io.k = kvar ? p<double>(L.lev[l].k64) : nullptr;
+        io.y = dg;
+        io.row_mode = ROW_ONE;
+        FEM_TRY(run_scatter<double>(*m, l, K_DIAG, kvar, io, s));
+    }
+    random_launch(n, H.L, 0x5eed0005ull + (uint64_t)l, v, s);
+    fill_launch<double>(n, 0.0, vp, s);
+    double out[3];
+    mul_launch<double>(n, v, dg, wv, s);
+    FEM_TRY(dots(1, n, v, wv, nullptr, nullptr, nullptr, nullptr, out));
+    if (!(out[0] > 0)) {
+        set_error("Lanczos start vector has zero D-norm");
+        return FEM_ERR_BREAKDOWN;
+    }
+    axpby_launch<double>(n, 0.0, v, 1.0 / std::sqrt(out[0]), v, s);
+    std::vector<double> al, be;
+    double beta = 0.0;
+    const int steps = std::max(2, o.eig_iters);
+    for (int it = 0; it < steps; ++it) {
+        FEM_TRY(apply64(l, v, 1.0, nullptr, 0.0, wv));                // w = A v
+        FEM_TRY(dots(1, n, wv, v, nullptr, nullptr, nullptr, nullptr, out));
+        const double alpha = out[0];                                   // (D^-1 A v)^T D v
+        al.push_back(alpha);
+        div_launch<double>(n, wv, dg, wv, s);                          // w = D^-1 A v
+        axpby_launch<double>(n, -alpha, v, 1.0, wv, s);
+        if (beta != 0.0) axpby_launch<double>(n, -beta, vp, 1.0, wv, s);
+        mul_launch<double>(n, wv, dg, vp, s);                          // v_prev is free here
+        FEM_TRY(dots(1, n, wv, vp, nullptr, nullptr, nullptr, nullptr, out));
+        const double b2 = out[0];
+        if (!(b2 > 0) || it == steps - 1) break;
+        beta = std::sqrt(b2);
+        be.push_back(beta);
+        axpby_launch<double>(n, 1.0, v, 0.0, vp, s);                   // v_prev = v
+        axpby_launch<double>(n, 1.0 / beta, wv, 0.0, v, s);            // v = w / beta
+    }
+    be.resize(al.size() > 0 ? al.size() - 1 : 0);
+    lm = tridiag_max_eig(al, be);
+    if (!std::isfinite(lm) || lm <= 0) {
+        set_error("Lanczos estimate of lambda_max failed");
+        return FEM_ERR_BREAKDOWN;
+    }
+    return FEM_OK;
+}
+
+fem_status fem_solver::setup(const double* k) {
+    const double t0 = now_ms();
+    kvar = k != nullptr;
+    const int nl = m->nlev;
+    if (o.preconditioner == FEM_PC_JACOBI) {
+        if (kvar) inject_launch<double>(m->lev[L.hi].n, 1, m->lev[L.hi].n, k, p<double>(L.lev[L.hi].k64), s);
+        ScatterIO<double> io;
+        io.k = kvar ? p<double>(L.lev[L.hi].k64) : nullptr;
+        io.y = p<double>(L.jac_diag);
+        io.row_mode = ROW_ONE;
+        FEM_TRY(run_scatter<double>(*m, L.hi, K_DIAG, kvar, io, s));
+        lmax.assign(nl, 0.0);
+        if (hipStreamSynchronize(s) != hipSuccess) return check_launch("solver setup");
+        ready = true;
+        return check_launch("solver setup");
+    }
+    // coefficient on every level by injection
+    if (kvar) {
+        for (int l = 0; l < nl; ++l) {
+            const int stride = 1 << (nl - 1 - l);
+            inject_launch<double>(m->lev[l].n, stride, m->lev[nl - 1].n, k, p<double>(L.lev[l].k64), s);
+            if (L.mixed) inject_launch<float>(m->lev[l].n, stride, m->lev[nl - 1].n, k, p<float>(L.lev[l].k32), s);
+        }
+    }
+    // Jacobi scaling per level
+    for (int l = L.lo + 1; l <= L.hi; ++l) {
+        const int64_t n = m->lev[l].N;
+        double* dg = p<double>(L.cg_q);
+        ScatterIO<double> io;
+        io.k = kvar ? p<double>(L.lev[l].k64) : nullptr;
+        io.y = dg;
+        io.row_mode = ROW_ONE;
+        FEM_TRY(run_scatter<double>(*m, l, K_DIAG, kvar, io, s));
+        if (L.mixed) {
+            recip_launch<double>(n, dg, dg, s);
+            cast_launch<double, float>(n, dg, p<float>(L.lev[l].dinv), s);
+        } else {
+            recip_launch<double>(n, dg, p<double>(L.lev[l].dinv), s);
+        }
+    }
+    // lambda_max per smoothed level
+    lmax.assign(nl, 0.0);
+    for (int l = L.lo + 1; l <= L.hi; ++l) {
+        if (o.lambda_max_override && o.lambda_max_override[l] > 0) {
+            lmax[l] = o.lambda_max_override[l];
+        } else {
+            FEM_TRY(lanczos(l, lmax[l]));
+        }
+    }
+    // coarse operator: dense interior block by probing, then its inverse
+    {
+        const HostLevel& C = m->lev[L.lo];
+        const int P = C.p, S = 2 * P + 1;
+        double* A = p<double>(L.dense);
+        const int64_t nd = L.dense_n;
+        fill_launch<double>(nd * nd, 0.0, A, s);
+        double* v = p<double>(L.cg_r);
+        double* y = p<double>(L.cg_z);
+        for (int c2 = 0; c2 < S; ++c2)
+            for (int c1 = 0; c1 < S; ++c1)
+                for (int c0 = 0; c0 < S; ++c0) {
+                    probe_fill_launch(C.L, S, c0, c1, c2, v, s);
+                    FEM_TRY(apply64(L.lo, v, 1.0, nullptr, 0.0, y));
+                    probe_extract_launch(C.L, P, S, c0, c1, c2, y, A, s);
+                }
+        FEM_TRY(dense_invert(nd, A, nullptr, s));
+    }
+    const hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        set_error(std::string("solver setup: ") + hipGetErrorString(e));
+        return FEM_ERR_HIP;
+    }
+    ready = true;
+    (void)t0;
+    return check_launch("solver setup");
+}
+
+extern "C" {
+
+void fem_solve_opts_default(fem_solve_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->rtol = 1e-8;
+    o->max_it = 200;
+    o->precision = FEM_PREC_FP64;
+    o->n_levels_used = 0;
+    o->cheb_degree = 2;
+    o->cheb_lo = 0.1;
+    o->cheb_hi = 1.1;
+    o->eig_iters = 10;
+    o->coarse_method = FEM_COARSE_AUTO;
+    o->lambda_max_override = nullptr;
+    o->coarse_rtol = 1e-10;
+    o->replace_every = 25;
+    o->flexible = 0;
+    o->history = nullptr;
+    o->history_cap = 0;
+    o->preconditioner = FEM_PC_MG;
+}
+
+static fem_status check_opts(const fem_mesh* m, const fem_solve_opts* o) {
+    if (!m || !o) {
+        set_error("solver: NULL mesh or options");
+        return FEM_ERR_INVALID_ARG;
+    }
+    if (!(o->rtol > 0) || o->max_it < 1 || o->cheb_degree < 1 || o->cheb_degree > 16 || !(o->cheb_hi > o->cheb_lo) ||
+        !(o->cheb_lo > 0) || (o->precision != FEM_PREC_FP64 && o->precision != FEM_PREC_MIXED) ||
+        o->n_levels_used < 0 || o->eig_iters < 0 || o->eig_iters > 64 ||
+        (o->preconditioner != FEM_PC_MG && o->preconditioner != FEM_PC_JACOBI)) {
+        set_error("solver: invalid options");
+        return FEM_ERR_INVALID_ARG;
+    }
+    return FEM_OK;
+}
+
+fem_status fem_solve_workspace_bytes(const fem_mesh* m, const fem_solve_opts* o, size_t* bytes) {
+    fem_status st = check_opts(m, o);
+    if (st) return st;
+    if (!bytes) {
+        set_error("fem_solve_workspace_bytes: NULL output");
+        return FEM_ERR_INVALID_ARG;
+    }
+    Layout L;
+    st = make_layout(*m, *o, true, L);
+    if (st) return st;
+    *bytes = L.total;
+    return FEM_OK;
+}
+
+fem_status fem_solver_create(const fem_mesh* m, const fem_solve_opts* o, void* ws, size_t ws_bytes, fem_solver** out) {
+    fem_status st = check_opts(m, o);
+    if (st) return st;
+    if (!ws || !out) {
+        set_error("fem_solver_create: NULL workspace or output");
+        return FEM_ERR_INVALID_ARG;
+    }
+    if (!m->dev) {
+        set_error("fem_solver_create: mesh not uploaded");
+        return FEM_ERR_STATE;
+    }
+    if (((uintptr_t)ws & 255) != 0) {
+        set_error("fem_solver_create: workspace not 256-byte aligned");
+        return FEM_ERR_INVALID_ARG;
+    }
+    fem_solver* S = new fem_solver();
+    S->m = m;
+    S->o = *o;
+    S->o.history = o->history;
+    st = make_layout(*m, *o, true, S->L);
+    if (st) {
+        delete S;
+        return st;
+    }
+    if (ws_bytes < S->L.total) {
+        delete S;
+        set_error("fem_solver_create: workspace smaller than fem_solve_workspace_bytes");
+        return FEM_ERR_WORKSPACE;
+    }
+    S->ws = (char*)ws;
+    S->ws_bytes = ws_bytes;
+    if (hipHostMalloc((void**)&S->hscal, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        delete S;
+        set_error("fem_solver_create: pinned host allocation failed");
+        return FEM_ERR_HIP;
+    }
+    const int nl = m->nlev;
+    S->ev.resize(4 * nl + 2);
+    for (auto& e : S->ev) hipEventCreate(&e);
+    S->level_ms.assign(nl, 0.0);
+    *out = S;
+    return FEM_OK;
+}
+
+void fem_solver_destroy(fem_solver* S) {
+    if (!S) return;
+    for (auto& e : S->ev) hipEventDestroy(e);
+    if (S->hscal) hipHostFree(S->hscal);
+    delete S;
+}
+
+fem_status fem_solver_setup(fem_solver* S, const double* k, void* stream) {
+    if (!S) {
+        set_error("fem_solver_setup: NULL solver");
+        return FEM_ERR_INVALID_ARG;
+    }
+    S->s = (hipStream_t)stream;
+    S->ready = false;
+    return S->setup(k);
+}
+
+static void accumulate_times(fem_solver* S) {
+    const int nl = S->m->nlev;
+    float ms = 0.f;
+    for (int l = S->L.lo + 1; l <= S->L.hi; ++l) {
+        float a = 0.f, b = 0.f;
+        if (hipEventElapsedTime(&a, S->ev[4 * l], S->ev[4 * l + 1]) == hipSuccess &&
+            hipEventElapsedTime(&b, S->ev[4 * l + 2], S->ev[4 * l + 3]) == hipSuccess)
+            S->level_ms[l] += a + b;
+    }
+    if (hipEventElapsedTime(&ms, S->ev[4 * nl], S->ev[4 * nl + 1]) == hipSuccess) {
+        S->coarse_ms += ms;
+        S->level_ms[S->L.lo] += ms;
+    }
+    // the coarser levels' time is nested in each level's pre/post gap; subtract nothing (the
+    // pre and post segments exclude the recursion)
+}
+
+static fem_status apply_preconditioner(fem_solver* S, const double* r, double* z) {
+    const int hi = S->L.hi;
+    if (S->o.preconditioner == FEM_PC_JACOBI) {
+        const int64_t n = S->m->lev[hi].N;
+        div_launch<double>(n, r, S->p<double>(S->L.jac_diag), z, S->s);
+        return check_launch("Jacobi preconditioner");
+    }
+    if (S->L.mixed) {
+        const int64_t n = S->m->lev[hi].N;
+        float* b = S->p<float>(S->L.lev[hi].b);
+        float* x = S->p<float>(S->L.lev[hi].x);
+        cast_launch<double, float>(n, r, b, S->s);
+        FEM_TRY(S->vcycle<float>(hi, b, x));
+        cast_launch<float, double>(n, x, z, S->s);
+        return FEM_OK;
+    }
+    return S->vcycle<double>(hi, r, z);
+}
+
+fem_status fem_solver_vcycle(fem_solver* S, const double* r, double* z, void* stream) {
+    if (!S || !r || !z || r == z) {
+        set_error("fem_solver_vcycle: bad arguments");
+        return FEM_ERR_INVALID_ARG;
+    }
+    if (!S->ready) {
+        set_error("fem_solver_vcycle: solver not set up");
+        return FEM_ERR_STATE;
+    }
+    S->s = (hipStream_t)stream;
+    const bool t = S->timing;
+    S->timing = false;
+    const fem_status st = apply_preconditioner(S, r, z);
+    S->timing = t;
+    if (st) return st;
+    return check_launch("fem_solver_vcycle");
+}
+
+fem_status fem_solver_solve(fem_solver* S, const double* b, double* x, fem_solve_stats* stats, void* stream) {
+    if (!S || !b || !x || b == x) {
+        set_error("fem_solver_solve: bad arguments");
+        return FEM_ERR_INVALID_ARG;
+    }
+    if (!S->ready) {
+        set_error("fem_solver_solve: solver not set up");
+        return FEM_ERR_STATE;
+    }
+    S->s = (hipStream_t)stream;
+    const double t0 = now_ms();
+    const int hi = S->L.hi;
+    const int64_t n = S->m->lev[hi].N;
+    double* r = S->p<double>(S->L.cg_r);
+    double* z = S->p<double>(S->L.cg_z);
+    double* pp = S->p<double>(S->L.cg_p);
+    double* q = S->p<double>(S->L.cg_q);
+    S->coarse_ms = 0.0;
+    std::fill(S->level_ms.begin(), S->level_ms.end(), 0.0);
+    const fem_solve_opts& o = S->o;
+    double out[3];
+    FEM_TRY(S->dots(1, n, b, b, nullptr, nullptr, nullptr, nullptr, out));
+    const double nb = std::sqrt(out[0]);
+    int it = 0;
+    fem_status status = FEM_OK;
+    double rel = 0.0, rel_true = 0.0;
+    auto record = [&](int i, double v) {
+        if (o.history && i < o.history_cap) o.history[i] = v;
+    };
+    if (!std::isfinite(nb)) {
+        set_error("fem_solver_solve: right-hand side is not finite");
+        return FEM_ERR_BREAKDOWN;
+    }
+    if (nb == 0.0) {
+        fill_launch<double>(n, 0.0, x, S->s);
+        hipStreamSynchronize(S->s);
+        record(0, 0.0);
+    } else {
+        FEM_TRY(S->apply64(hi, x, -1.0, b, 1.0, r));            // r = b - A x
+        FEM_TRY(S->dots(1, n, r, r, nullptr, nullptr, nullptr, nullptr, out));
+        rel = std::sqrt(out[0]) / nb;
+        record(0, rel);
+        bool converged = rel <= o.rtol;
+        double rz = 0.0;
+        if (!converged) {
+            FEM_TRY(apply_preconditioner(S, r, z));
+            FEM_TRY(S->dots(1, n, r, z, nullptr, nullptr, nullptr, nullptr, out));
+            if (S->timing && S->o.preconditioner == FEM_PC_MG) accumulate_times(S);
+            rz = out[0];
+            if (!(rz > 0) || !std::isfinite(rz)) {
+                set_error("fem_solver_solve: preconditioner is not positive definite (r^T B r <= 0)");
+                return FEM_ERR_BREAKDOWN;
+            }
+            axpby_launch<double>(n, 1.0, z, 0.0, pp, S->s);
+        }
+        while (!converged && it < o.max_it) {
+            FEM_TRY(S->apply64(hi, pp, 1.0, nullptr, 0.0, q));   // q = A p
+            FEM_TRY(S->dots(1, n, pp, q, nullptr, nullptr, nullptr, nullptr, out));
+            const double pq = out[0];
+            if (!(pq > 0) || !std::isfinite(pq)) {
+                set_error("fem_solver_solve: CG breakdown (p^T A p <= 0 or not finite)");
+                return FEM_ERR_BREAKDOWN;
+            }
+            const double alpha = rz / pq;
+            cg_update_launch(n, alpha, pp, q, x, r, S->s);
+            ++it;
+            if (o.replace_every > 0 && it % o.replace_every == 0) FEM_TRY(S->apply64(hi, x, -1.0, b, 1.0, r));
+            FEM_TRY(S->dots(1, n, r, r, nullptr, nullptr, nullptr, nullptr, out));
+            rel = std::sqrt(out[0]) / nb;
+            record(it, rel);
+            if (!std::isfinite(rel)) {
+                set_error("fem_solver_solve: residual not finite");
+                return FEM_ERR_BREAKDOWN;
+            }
+            if (rel <= o.rtol) {
+                // confirm with the true residual; if it disagrees, continue from it
+                FEM_TRY(S->apply64(hi, x, -1.0, b, 1.0, q));
+                FEM_TRY(S->dots(1, n, q, q, nullptr, nullptr, nullptr, nullptr, out));
+                const double tr = std::sqrt(out[0]) / nb;
+                if (tr <= o.rtol) {
+                    converged = true;
+                    break;
+                }
+                axpby_launch<double>(n, 1.0, q, 0.0, r, S->s);
+            }
+            FEM_TRY(apply_preconditioner(S, r, z));
+            FEM_TRY(S->dots(2, n, r, z, q, z, nullptr, nullptr, out));
+            if (S->timing && S->o.preconditioner == FEM_PC_MG) accumulate_times(S);
+            const double rz_new = out[0], qz = out[1];
+            if (!(rz_new > 0) || !std::isfinite(rz_new)) {
+                set_error("fem_solver_solve: preconditioner is not positive definite (r^T B r <= 0)");
+                return FEM_ERR_BREAKDOWN;
+            }
+            const double beta = o.flexible ? (-alpha * qz / rz) : (rz_new / rz);
+            rz = rz_new;
+            axpby_launch<double>(n, 1.0, z, beta, pp, S->s);
+        }
+        // true residual at exit
+        FEM_TRY(S->apply64(hi, x, -1.0, b, 1.0, q));
+        FEM_TRY(S->dots(1, n, q, q, nullptr, nullptr, nullptr, nullptr, out));
+        rel_true = std::sqrt(out[0]) / nb;
+        if (!converged) status = FEM_WARN_NOT_CONVERGED;
+    }
+    const double t1 = now_ms();
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->iterations = it;
+        stats->coarse_iterations = 0;
+        stats->rel_residual_true = rel_true;
+        stats->solve_ms = t1 - t0;
+        stats->coarse_ms = S->coarse_ms;
+        for (int l = 0; l < S->m->nlev && l < 8; ++l) {
+            stats->level_ms[l] = S->level_ms[l];
+            stats->lambda_max[l] = S->lmax.size() > (size_t)l ? S->lmax[l] : 0.0;
+        }
+    }
+    if (status == FEM_WARN_NOT_CONVERGED)
+        set_error("fem_solver_solve: max_it reached before rtol (relative residual " + std::to_string(rel_true) + ")");
+    return status;
+}
+
+fem_status fem_mg_cg_solve(const fem_mesh* m, const double* k, const double* b, double* x, const fem_solve_opts* o,
+                           void* ws, size_t ws_bytes, fem_solve_stats* stats, void* stream) {
+    fem_solver* S = nullptr;
+    fem_status st = fem_solver_create(m, o, ws, ws_bytes, &S);
+    if (st) return st;
+    const double t0 = now_ms();
+    st = fem_solver_setup(S, k, stream);
+    const double t1 = now_ms();
+    if (st == FEM_OK) {
+        st = fem_solver_solve(S, b, x, stats, stream);
+        if (stats) stats->setup_ms = t1 - t0;
+    }
+    fem_solver_destroy(S);
+    return st;
+}
+
+}  // extern "C"

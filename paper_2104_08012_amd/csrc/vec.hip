@@ -1,0 +1,464 @@
+// Vector kernels of the multigrid-CG solver: deterministic dot products, axpy forms, the fused
+// Chebyshev update, precision casts, coefficient injection, and the dense coarse-grid kernels
+// (probing assembly, blocked Gauss-Jordan inversion, matrix-vector product).
+#include "vec.hpp"
+
+namespace fem {
+
+namespace {
+constexpr int VT = 256;
+
+inline unsigned grid_for(int64_t n, int per_thread = 1) {
+    int64_t g = (n + (int64_t)VT * per_thread - 1) / ((int64_t)VT * per_thread);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 0x7fffffff));
+}
+
+// ---------------- deterministic dot products ----------------
+// Stage 1: block b sums the elements i = b*chunk .. (b+1)*chunk-1 with a fixed per-thread stride
+// and a fixed LDS tree; stage 2: one block sums the partials in a fixed tree.  The result does
+// not depend on timing, only on n and the fixed grid.
+constexpr int DOT_BLOCKS = 1024;
+
+template <typename T, int NPAIR>
+__global__ void __launch_bounds__(VT) k_dot_partial(int64_t n, DotPairs<T> pr, double* partial) {
+    __shared__ double sh[NPAIR][VT];
+    const int64_t chunk = (n + DOT_BLOCKS - 1) / DOT_BLOCKS;
+    const int64_t lo = blockIdx.x * chunk, hi = (lo + chunk < n) ? lo + chunk : n;
+    double acc[NPAIR];
+#pragma unroll
+    for (int p = 0; p < NPAIR; ++p) acc[p] = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += VT) {
+#pragma unroll
+        for (int p = 0; p < NPAIR; ++p) acc[p] += (double)pr.x[p][i] * (double)pr.y[p][i];
+    }
+#pragma unroll
+    for (int p = 0; p < NPAIR; ++p) sh[p][threadIdx.x] = acc[p];
+    __syncthreads();
+    for (int s = VT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+#pragma unroll
+            for (int p = 0; p < NPAIR; ++p) sh[p][threadIdx.x] += sh[p][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < NPAIR) partial[threadIdx.x * DOT_BLOCKS + blockIdx.x] = sh[threadIdx.x][0];
+}
+
+template <int NPAIR>
+__global__ void __launch_bounds__(VT) k_dot_final(const double* partial, double* out) {
+    __shared__ double sh[NPAIR][VT];
+#pragma unroll
+    for (int p = 0; p < NPAIR; ++p) {
+        double a = 0.0;
+        for (int i = threadIdx.x; i < DOT_BLOCKS; i += VT) a += partial[p * DOT_BLOCKS + i];
+        sh[p][threadIdx.x] = a;
+    }
+    __syncthreads();
+    for (int s = VT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+#pragma unroll
+            for (int p = 0; p < NPAIR; ++p) sh[p][threadIdx.x] += sh[p][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < NPAIR) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// ---------------- elementwise ----------------
+template <typename T>
+__global__ void k_axpby(int64_t n, double a, const T* __restrict__ x, double b, T* y) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i < n) y[i] = (T)(a * (double)x[i] + b * (double)y[i]);
+}
+
+// x += alpha p ; r -= alpha q  (FP64 CG update)
+__global__ void k_cg_update(int64_t n, double alpha, const double* __restrict__ p, const double* __restrict__ q,
+                            double* __restrict__ x, double* __restrict__ r) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i < n) {
+        x[i] += alpha * p[i];
+        r[i] -= alpha * q[i];
+    }
+}
+
+// Chebyshev step: d = c1 d + c2 dinv r ; x = (init ? d : x + d)
+template <typename T>
+__global__ void k_cheb(int64_t n, T c1, T c2, const T* __restrict__ dinv, const T* __restrict__ r,
+                       T* __restrict__ d, T* __restrict__ x, int init) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i < n) {
+        const T dn = c1 * d[i] + c2 * dinv[i] * r[i];
+        d[i] = dn;
+        x[i] = init ? dn : x[i] + dn;
+    }
+}
+
+// first Chebyshev step: d = c2 dinv r ; x = (init ? d : x + d)
+template <typename T>
+__global__ void k_cheb0(int64_t n, T c2, const T* __restrict__ dinv, const T* __restrict__ r,
+                        T* __restrict__ d, T* __restrict__ x, int init) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i < n) {
+        const T dn = c2 * dinv[i] * r[i];
+        d[i] = dn;
+        x[i] = init ? dn : x[i] + dn;
+    }
+}
+
+template <typename A, typename B>
+__global__ void k_cast(int64_t n, const A* __restrict__ x, B* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i < n) y[i] = (B)x[i];
+}
+
+template <typename T>
+__global__ void k_fill(int64_t n, T v, T* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i < n) y[i] = v;
+}
+
+// y = 1 / x (Jacobi scaling from the diagonal)
+template <typename T>
+__global__ void k_recip(int64_t n, const T* __restrict__ x, T* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i < n) y[i] = T(1) / x[i];
+}
+
+// y = x * s  (elementwise product)
+template <typename T>
+__global__ void k_mul(int64_t n, const T* __restrict__ x, const T* __restrict__ s, T* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i < n) y[i] = x[i] * s[i];
+}
+
+template <typename T>
+__global__ void k_div(int64_t n, const T* __restrict__ x, const T* __restrict__ s, T* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i < n) y[i] = x[i] / s[i];
+}
+
+// k on the vertex lattice of a coarser level by injection: k_c(i,j,k) = k_f(2^s i, 2^s j, 2^s k)
+template <typename T>
+__global__ void k_inject(int nc, int stride, int nf, const double* __restrict__ kf, T* __restrict__ kc) {
+    const int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x;
+    const int64_t n1 = nc + 1;
+    if (t >= n1 * n1 * n1) return;
+    const int i = (int)(t % n1), j = (int)((t / n1) % n1), k = (int)(t / (n1 * n1));
+    const int64_t f1 = nf + 1;
+    kc[t] = (T)kf[(int64_t)i * stride + f1 * ((int64_t)j * stride + f1 * (int64_t)k * stride)];
+}
+
+// Random start vector from a counter-based generator (SplitMix64 of the index), in [-1, 1),
+// zero on boundary dofs of the (L^3) lattice.
+__global__ void k_random(int64_t n, int L, uint64_t seed, double* __restrict__ v) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i >= n) return;
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+    const int I = (int)(i % L), J = (int)((i / L) % L), K = (int)(i / ((int64_t)L * L));
+    const bool bnd = I == 0 || J == 0 || K == 0 || I == L - 1 || J == L - 1 || K == L - 1;
+    v[i] = bnd ? 0.0 : 2.0 * u - 1.0;
+}
+
+// ---------------- dense coarse solve ----------------
+// Probing vector for colour (c0, c1, c2) of period S: ones at interior lattice points congruent
+// to the colour, zero elsewhere.
+__global__ void k_probe_fill(int L, int S, int c0, int c1, int c2, double* __restrict__ v) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    const int64_t N = (int64_t)L * L * L;
+    if (i >= N) return;
+    const int I = (int)(i % L), J = (int)((i / L) % L), K = (int)(i / ((int64_t)L * L));
+    const bool interior = I > 0 && J > 0 && K > 0 && I < L - 1 && J < L - 1 && K < L - 1;
+    v[i] = (interior && I % S == c0 && J % S == c1 && K % S == c2) ? 1.0 : 0.0;
+}
+
+// For every interior row i, the column j of the colour with |i - j|_inf <= p is unique (S = 2p+1)
+// and A_ij = (A v)_i.  Writes A_dense[row][col] over interior indices.
+__global__ void k_probe_extract(int L, int p, int S, int c0, int c1, int c2, const double* __restrict__ y,
+                                double* __restrict__ A) {
+    const int M = L - 2;
+    const int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (t >= (int64_t)M * M * M) return;
+    const int I = (int)(t % M) + 1, J = (int)((t / M) % M) + 1, K = (int)(t / ((int64_t)M * M)) + 1;
+    const int c[3] = {c0, c1, c2};
+    const int X[3] = {I, J, K};
+    int Y[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        int lo = X[d] - p;
+        int r = ((c[d] - lo) % S + S) % S;
+        Y[d] = lo + r;
+    }
+    if (Y[0] < 1 || Y[1] < 1 || Y[2] < 1 || Y[0] > L - 2 || Y[1] > L - 2 || Y[2] > L - 2) return;
+    const int64_t col = (Y[0] - 1) + (int64_t)M * ((Y[1] - 1) + (int64_t)M * (Y[2] - 1));
+    const int64_t g = I + (int64_t)L * (J + (int64_t)L * K);
+    A[t * (int64_t)M * M * M + col] = y[g];
+}
+
+// Invert one nb x nb diagonal block in place (Gauss-Jordan, no pivoting; the block of an SPD
+// matrix's Schur complement is SPD).  One workgroup; the block is staged in LDS.
+template <int NB>
+__global__ void __launch_bounds__(256) k_gj_pivot(int64_t ld, int64_t k0, int b, double* A) {
+    __shared__ double s[NB][NB + 1];
+    for (int e = threadIdx.x; e < b * b; e += 256) s[e / b][e % b] = A[(k0 + e / b) * ld + k0 + e % b];
+    __syncthreads();
+    for (int k = 0; k < b; ++k) {
+        const double piv = 1.0 / s[k][k];
+        __syncthreads();
+        // row k scaled, other rows eliminated, column k replaced (in-place Gauss-Jordan)
+        for (int e = threadIdx.x; e < b * b; e += 256) {
+            const int i = e / b, j = e % b;
+            if (i != k && j != k) s[i][j] -= s[i][k] * s[k][j] * piv;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < b; e += 256) {
+            if (e != k) {
+                s[k][e] *= piv;
+                s[e][k] *= -piv;
+            }
+        }
+        if (threadIdx.x == 0) s[k][k] = piv;
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < b * b; e += 256) A[(k0 + e / b) * ld + k0 + e % b] = s[e / b][e % b];
+}
+
+// Tiled FP64 GEMM  C = alpha * A B + beta * C  (row-major, leading dimensions lda/ldb/ldc),
+// 64 x 64 tiles of C per workgroup, 4 x 4 register blocks per thread, K in chunks of 16 staged in
+// LDS.  Rows of C in [rskip_lo, rskip_hi) and columns in [cskip_lo, cskip_hi) are left untouched.  Every workgroup reads
+// all of its A and B inputs before writing its C tile, so the blocked Gauss-Jordan sweep can run
+// in place: its row panel writes the rows it reads (each tile only its own columns), its column
+// panel the columns it reads (each tile only its own rows), and its trailing update never writes
+// the pivot rows or columns it reads.
+constexpr int GT = 64, GK = 16;
+
+__global__ void __launch_bounds__(256) k_gemm(int64_t M, int64_t N, int K, double alpha, const double* A, int64_t lda,
+                                              const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                                              int64_t rskip_lo, int64_t rskip_hi, int64_t cskip_lo, int64_t cskip_hi) {
+    const int64_t i0 = (int64_t)blockIdx.y * GT, j0 = (int64_t)blockIdx.x * GT;
+    __shared__ double As[GK][GT + 1];
+    __shared__ double Bs[GK][GT + 1];
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    double acc[4][4] = {};
+    for (int kk = 0; kk < K; kk += GK) {
+        for (int e = threadIdx.x; e < GK * GT; e += 256) {
+            const int r = e / GK, c = e % GK;
+            const int64_t gi = i0 + r;
+            As[c][r] = (gi < M && kk + c < K) ? A[gi * lda + kk + c] : 0.0;
+            const int rr = e / GT, cc = e % GT;
+            const int64_t gj = j0 + cc;
+            Bs[rr][cc] = (gj < N && kk + rr < K) ? B[(int64_t)(kk + rr) * ldb + gj] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < GK; ++c) {
+            double a[4], bb[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = As[c][ty * 4 + u];
+                bb[u] = Bs[c][tx * 4 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * bb[v];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t gi = i0 + ty * 4 + u;
+        if (gi >= M || (gi >= rskip_lo && gi < rskip_hi)) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t gj = j0 + tx * 4 + v;
+            if (gj >= N || (gj >= cskip_lo && gj < cskip_hi)) continue;
+            double* c = &C[gi * ldc + gj];
+            *c = (beta == 0.0) ? alpha * acc[u][v] : alpha * acc[u][v] + beta * *c;
+        }
+    }
+}
+
+// y_lattice = Ainv * x_interior: one workgroup per row, fixed-order reduction.  The input is
+// read from the level vector at the interior lattice points; the output is written to the
+// level vector (boundary entries set to zero by k_zero_boundary).
+__global__ void __launch_bounds__(256) k_dense_gemv(int L, const double* __restrict__ Ainv, const double* __restrict__ xc,
+                                                    double* __restrict__ yl, const double* __restrict__ xl) {
+    const int M = L - 2;
+    const int64_t m = (int64_t)M * M * M;
+    const int64_t row = blockIdx.x;
+    __shared__ double sh[256];
+    double acc = 0.0;
+    const double* a = Ainv + row * m;
+    for (int64_t j = threadIdx.x; j < m; j += 256) acc += a[j] * xc[j];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int I = (int)(row % M) + 1, J = (int)((row / M) % M) + 1, K = (int)(row / ((int64_t)M * M)) + 1;
+        yl[I + (int64_t)L * (J + (int64_t)L * K)] = sh[0];
+    }
+    (void)xl;
+}
+
+// gather interior entries of a lattice vector into a compact vector
+__global__ void k_gather_interior(int L, const double* __restrict__ xl, double* __restrict__ xc) {
+    const int M = L - 2;
+    const int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (t >= (int64_t)M * M * M) return;
+    const int I = (int)(t % M) + 1, J = (int)((t / M) % M) + 1, K = (int)(t / ((int64_t)M * M)) + 1;
+    xc[t] = xl[I + (int64_t)L * (J + (int64_t)L * K)];
+}
+
+template <typename T>
+__global__ void k_zero_boundary(int L, T* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    const int64_t N = (int64_t)L * L * L;
+    if (i >= N) return;
+    const int I = (int)(i % L), J = (int)((i / L) % L), K = (int)(i / ((int64_t)L * L));
+    if (I == 0 || J == 0 || K == 0 || I == L - 1 || J == L - 1 || K == L - 1) y[i] = T(0);
+}
+
+}  // namespace
+
+// ---------------- launchers ----------------
+template <typename T>
+void dot_launch(int npair, int64_t n, const DotPairs<T>& pr, double* partial, double* out, hipStream_t s) {
+    if (npair == 1) {
+        hipLaunchKernelGGL((k_dot_partial<T, 1>), dim3(DOT_BLOCKS), dim3(VT), 0, s, n, pr, partial);
+        hipLaunchKernelGGL((k_dot_final<1>), dim3(1), dim3(VT), 0, s, partial, out);
+    } else if (npair == 2) {
+        hipLaunchKernelGGL((k_dot_partial<T, 2>), dim3(DOT_BLOCKS), dim3(VT), 0, s, n, pr, partial);
+        hipLaunchKernelGGL((k_dot_final<2>), dim3(1), dim3(VT), 0, s, partial, out);
+    } else {
+        hipLaunchKernelGGL((k_dot_partial<T, 3>), dim3(DOT_BLOCKS), dim3(VT), 0, s, n, pr, partial);
+        hipLaunchKernelGGL((k_dot_final<3>), dim3(1), dim3(VT), 0, s, partial, out);
+    }
+}
+template void dot_launch<double>(int, int64_t, const DotPairs<double>&, double*, double*, hipStream_t);
+template void dot_launch<float>(int, int64_t, const DotPairs<float>&, double*, double*, hipStream_t);
+size_t dot_partial_doubles() { return 3 * DOT_BLOCKS; }
+
+template <typename T>
+void axpby_launch(int64_t n, double a, const T* x, double b, T* y, hipStream_t s) {
+    hipLaunchKernelGGL((k_axpby<T>), dim3(grid_for(n)), dim3(VT), 0, s, n, a, x, b, y);
+}
+template void axpby_launch<double>(int64_t, double, const double*, double, double*, hipStream_t);
+template void axpby_launch<float>(int64_t, double, const float*, double, float*, hipStream_t);
+
+void cg_update_launch(int64_t n, double alpha, const double* p, const double* q, double* x, double* r, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_update, dim3(grid_for(n)), dim3(VT), 0, s, n, alpha, p, q, x, r);
+}
+
+template <typename T>
+void cheb_launch(int64_t n, double c1, double c2, const T* dinv, const T* r, T* d, T* x, bool first, bool init,
+                 hipStream_t s) {
+    if (first)
+        hipLaunchKernelGGL((k_cheb0<T>), dim3(grid_for(n)), dim3(VT), 0, s, n, (T)c2, dinv, r, d, x, init ? 1 : 0);
+    else
+        hipLaunchKernelGGL((k_cheb<T>), dim3(grid_for(n)), dim3(VT), 0, s, n, (T)c1, (T)c2, dinv, r, d, x, init ? 1 : 0);
+}
+template void cheb_launch<double>(int64_t, double, double, const double*, const double*, double*, double*, bool, bool, hipStream_t);
+template void cheb_launch<float>(int64_t, double, double, const float*, const float*, float*, float*, bool, bool, hipStream_t);
+
+template <typename A, typename B>
+void cast_launch(int64_t n, const A* x, B* y, hipStream_t s) {
+    hipLaunchKernelGGL((k_cast<A, B>), dim3(grid_for(n)), dim3(VT), 0, s, n, x, y);
+}
+template void cast_launch<double, float>(int64_t, const double*, float*, hipStream_t);
+template void cast_launch<float, double>(int64_t, const float*, double*, hipStream_t);
+template void cast_launch<double, double>(int64_t, const double*, double*, hipStream_t);
+template void cast_launch<float, float>(int64_t, const float*, float*, hipStream_t);
+
+template <typename T>
+void fill_launch(int64_t n, T v, T* y, hipStream_t s) {
+    hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(n)), dim3(VT), 0, s, n, v, y);
+}
+template void fill_launch<double>(int64_t, double, double*, hipStream_t);
+template void fill_launch<float>(int64_t, float, float*, hipStream_t);
+
+template <typename T>
+void recip_launch(int64_t n, const T* x, T* y, hipStream_t s) {
+    hipLaunchKernelGGL((k_recip<T>), dim3(grid_for(n)), dim3(VT), 0, s, n, x, y);
+}
+template void recip_launch<double>(int64_t, const double*, double*, hipStream_t);
+template void recip_launch<float>(int64_t, const float*, float*, hipStream_t);
+
+template <typename T>
+void mul_launch(int64_t n, const T* x, const T* sc, T* y, hipStream_t s) {
+    hipLaunchKernelGGL((k_mul<T>), dim3(grid_for(n)), dim3(VT), 0, s, n, x, sc, y);
+}
+template void mul_launch<double>(int64_t, const double*, const double*, double*, hipStream_t);
+
+template <typename T>
+void div_launch(int64_t n, const T* x, const T* sc, T* y, hipStream_t s) {
+    hipLaunchKernelGGL((k_div<T>), dim3(grid_for(n)), dim3(VT), 0, s, n, x, sc, y);
+}
+template void div_launch<double>(int64_t, const double*, const double*, double*, hipStream_t);
+
+template <typename T>
+void inject_launch(int nc, int stride, int nf, const double* kf, T* kc, hipStream_t s) {
+    const int64_t n1 = nc + 1;
+    hipLaunchKernelGGL((k_inject<T>), dim3(grid_for(n1 * n1 * n1)), dim3(VT), 0, s, nc, stride, nf, kf, kc);
+}
+template void inject_launch<double>(int, int, int, const double*, double*, hipStream_t);
+template void inject_launch<float>(int, int, int, const double*, float*, hipStream_t);
+
+void random_launch(int64_t n, int L, uint64_t seed, double* v, hipStream_t s) {
+    hipLaunchKernelGGL(k_random, dim3(grid_for(n)), dim3(VT), 0, s, n, L, seed, v);
+}
+
+void probe_fill_launch(int L, int S, int c0, int c1, int c2, double* v, hipStream_t s) {
+    const int64_t N = (int64_t)L * L * L;
+    hipLaunchKernelGGL(k_probe_fill, dim3(grid_for(N)), dim3(VT), 0, s, L, S, c0, c1, c2, v);
+}
+void probe_extract_launch(int L, int p, int S, int c0, int c1, int c2, const double* y, double* A, hipStream_t s) {
+    const int64_t M = L - 2;
+    hipLaunchKernelGGL(k_probe_extract, dim3(grid_for(M * M * M)), dim3(VT), 0, s, L, p, S, c0, c1, c2, y, A);
+}
+
+// In-place inversion of an SPD matrix by the blocked Gauss-Jordan sweep, pivot blocks of 64:
+//   P = A_kk^-1;  A_kj = P A_kj (j outside k);  A_ij -= A_ik A_kj (i, j outside k);
+//   A_ik = -A_ik P (i outside k);  A_kk = P.
+fem_status dense_invert(int64_t n, double* A, double* tmp, hipStream_t s) {
+    (void)tmp;
+    const int NB = 64;
+    const unsigned tn = (unsigned)((n + GT - 1) / GT);
+    for (int64_t k0 = 0; k0 < n; k0 += NB) {
+        const int b = (int)std::min<int64_t>(NB, n - k0);
+        double* Akk = A + k0 * n + k0;
+        hipLaunchKernelGGL((k_gj_pivot<64>), dim3(1), dim3(256), 0, s, n, k0, b, A);
+        // row panel: rows k (b of them), all columns outside the block
+        hipLaunchKernelGGL(k_gemm, dim3(tn, 1), dim3(256), 0, s, (int64_t)b, n, b, 1.0, (const double*)Akk, n,
+                           (const double*)(A + k0 * n), n, 0.0, A + k0 * n, n, (int64_t)0, (int64_t)0, k0, k0 + b);
+        // trailing update on all rows/columns outside the block
+        hipLaunchKernelGGL(k_gemm, dim3(tn, tn), dim3(256), 0, s, n, n, b, -1.0, (const double*)(A + k0), n,
+                           (const double*)(A + k0 * n), n, 1.0, A, n, k0, k0 + b, k0, k0 + b);
+        // column panel: all rows outside the block, columns k
+        hipLaunchKernelGGL(k_gemm, dim3(1, tn), dim3(256), 0, s, n, (int64_t)b, b, -1.0, (const double*)(A + k0), n,
+                           (const double*)Akk, n, 0.0, A + k0, n, k0, k0 + b, (int64_t)0, (int64_t)0);
+    }
+    return check_launch("dense inversion");
+}
+
+void dense_solve_launch(int L, const double* Ainv, const double* xl, double* xc, double* yl, hipStream_t s) {
+    const int64_t M = L - 2, m = M * M * M;
+    hipLaunchKernelGGL(k_gather_interior, dim3(grid_for(m)), dim3(VT), 0, s, L, xl, xc);
+    const int64_t N = (int64_t)L * L * L;
+    hipLaunchKernelGGL((k_zero_boundary<double>), dim3(grid_for(N)), dim3(VT), 0, s, L, yl);
+    hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)m), dim3(256), 0, s, L, Ainv, xc, yl, xl);
+}
+
+template <typename T>
+void zero_boundary_launch(int L, T* y, hipStream_t s) {
+    const int64_t N = (int64_t)L * L * L;
+    hipLaunchKernelGGL((k_zero_boundary<T>), dim3(grid_for(N)), dim3(VT), 0, s, L, y);
+}
+template void zero_boundary_launch<double>(int, double*, hipStream_t);
+template void zero_boundary_launch<float>(int, float*, hipStream_t);
+
+}  // namespace fem

@@ -1,0 +1,50 @@
+// Launchers of the solver's vector and dense kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "ops.hpp"
+
+namespace fem {
+
+template <typename T>
+struct DotPairs {
+    const T* x[3];
+    const T* y[3];
+};
+
+// out[p] = sum_i x_p[i] y_p[i] for p < npair (npair <= 3), accumulated in FP64 with a fixed
+// reduction order; partial holds dot_partial_doubles() doubles.
+template <typename T>
+void dot_launch(int npair, int64_t n, const DotPairs<T>& pr, double* partial, double* out, hipStream_t s);
+size_t dot_partial_doubles();
+
+template <typename T>
+void axpby_launch(int64_t n, double a, const T* x, double b, T* y, hipStream_t s);
+void cg_update_launch(int64_t n, double alpha, const double* p, const double* q, double* x, double* r, hipStream_t s);
+// d = c1 d + c2 dinv r (first: d = c2 dinv r); x = d (init) or x += d
+template <typename T>
+void cheb_launch(int64_t n, double c1, double c2, const T* dinv, const T* r, T* d, T* x, bool first, bool init,
+                 hipStream_t s);
+template <typename A, typename B>
+void cast_launch(int64_t n, const A* x, B* y, hipStream_t s);
+template <typename T>
+void fill_launch(int64_t n, T v, T* y, hipStream_t s);
+template <typename T>
+void recip_launch(int64_t n, const T* x, T* y, hipStream_t s);
+template <typename T>
+void mul_launch(int64_t n, const T* x, const T* sc, T* y, hipStream_t s);
+template <typename T>
+void div_launch(int64_t n, const T* x, const T* sc, T* y, hipStream_t s);
+template <typename T>
+void inject_launch(int nc, int stride, int nf, const double* kf, T* kc, hipStream_t s);
+void random_launch(int64_t n, int L, uint64_t seed, double* v, hipStream_t s);
+void probe_fill_launch(int L, int S, int c0, int c1, int c2, double* v, hipStream_t s);
+void probe_extract_launch(int L, int p, int S, int c0, int c1, int c2, const double* y, double* A, hipStream_t s);
+fem_status dense_invert(int64_t n, double* A, double* tmp, hipStream_t s);
+void dense_solve_launch(int L, const double* Ainv, const double* xl, double* xc, double* yl, hipStream_t s);
+template <typename T>
+void zero_boundary_launch(int L, T* y, hipStream_t s);
+
+}  // namespace fem

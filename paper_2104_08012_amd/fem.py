@@ -184,6 +184,7 @@ class SolveOptions:
     replace_every: int = 25
     flexible: bool | None = None   # default: Polak-Ribiere beta in mixed precision
     history_cap: int = 1000
+    preconditioner: str = "mg"     # "mg" or "jacobi"
 
     def to_c(self):
         o = L.SolveOpts()
@@ -207,6 +208,7 @@ class SolveOptions:
         hist = (C.c_double * max(1, self.history_cap))()
         o.history = C.cast(hist, C.POINTER(C.c_double))
         o.history_cap = self.history_cap
+        o.preconditioner = L.FEM_PC_JACOBI if self.preconditioner == "jacobi" else L.FEM_PC_MG
         keep.append(hist)
         return o, keep, hist
 

@@ -1,0 +1,128 @@
+"""GPU parity of the multigrid-CG solver against the oracle, through the C ABI.
+
+* One FP64 V-cycle against the oracle's V-cycle with the same lambda_max (1e-12): exercises the
+  Chebyshev smoother, transfers, rediscretised coefficient and exact coarse solve together.
+* Solutions to rtol 1e-10 against the oracle's reference solution (1e-8), FP64 and mixed.
+* Jacobi-CG on the P1 8^3 workload (iteration bound 60 for 1e-10).
+* Failure handling: max_it reached, NaN right-hand side, negative coefficient, bad arguments.
+* Determinism and warm start.
+"""
+import numpy as np
+import pytest
+
+import fem_inputs
+from oracle import assemble, solvers
+from tests.gpu_util import banner, make_pair, rel
+
+torch = pytest.importorskip("torch")
+
+
+def _t(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda:0")
+
+
+def _rhs(lev):
+    b = assemble.mass(lev) @ fem_inputs.sin3_f(lev.dof_xyz())
+    b[lev.boundary] = 0
+    return b
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n0,r,p,jit,kvar", [(2, 2, 2, 0.1, True), (2, 2, 1, 0.0, False), (2, 1, 3, 0.1, True),
+                                             (3, 1, 2, 0.0, True)])
+def test_vcycle_matches_oracle(n0, r, p, jit, kvar):
+    banner(f"vcycle n0={n0} r={r} p={p} kvar={kvar}")
+    from paper_2104_08012_amd import fem
+    mesh, levels = make_pair(n0, r, p, jit)
+    k = fem_inputs.k_exp_fourier(levels[-1].vert_xyz) if kvar else None
+    omg = solvers.MGHierarchy(levels, k)
+    lm = [0.0] + [L.lmax for L in omg.levels[1:]]
+    opts = fem.SolveOptions(lambda_max=lm)
+    S = fem.Solver(mesh, opts).setup(_t(k) if kvar else None)
+    x = fem_inputs.uniform_vector(levels[-1].n_dofs, 0)
+    x[levels[-1].boundary] = 0
+    z = S.vcycle(_t(x))
+    torch.cuda.synchronize()
+    assert rel(z.cpu().numpy(), omg.vcycle(x)) <= 1e-12
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n0,r,p,jit,kvar,prec", [
+    (2, 2, 2, 0.1, False, "fp64"), (2, 2, 2, 0.1, True, "mixed"), (2, 2, 1, 0.0, False, "mixed"),
+    (2, 1, 3, 0.1, True, "fp64"), (2, 1, 3, 0.0, True, "mixed"), (4, 1, 2, 0.15, True, "fp64")])
+def test_solution_parity(n0, r, p, jit, kvar, prec):
+    banner(f"solve n0={n0} r={r} p={p} kvar={kvar} {prec}")
+    from paper_2104_08012_amd import fem
+    mesh, levels = make_pair(n0, r, p, jit)
+    lev = levels[-1]
+    k = fem_inputs.k_exp_fourier(lev.vert_xyz) if kvar else None
+    A = assemble.apply_bc(assemble.stiffness(lev, k), lev.boundary)
+    b = _rhs(lev)
+    u_ref = solvers.direct_solve(A, b, rtol=1e-14)
+    S = fem.Solver(mesh, fem.SolveOptions(rtol=1e-10, precision=prec)).setup(_t(k) if kvar else None)
+    u, res = S.solve(_t(b))
+    torch.cuda.synchronize()
+    assert res.rel_residual_true <= 1e-10
+    assert rel(u.cpu().numpy(), u_ref) <= 1e-8
+    assert res.iterations <= 40
+
+
+@pytest.mark.gpu
+def test_jacobi_cg_p1_8():
+    banner("jacobi cg p1 8^3")
+    from paper_2104_08012_amd import fem
+    mesh, levels = make_pair(8, 0, 1, 0.0)
+    lev = levels[0]
+    A = assemble.apply_bc(assemble.stiffness(lev), lev.boundary)
+    b = assemble.load_vector(lev, fem_inputs.sin3_f, 6)
+    b[lev.boundary] = 0
+    S = fem.Solver(mesh, fem.SolveOptions(rtol=1e-10, preconditioner="jacobi")).setup()
+    u, res = S.solve(_t(b))
+    assert res.iterations <= 60
+    assert res.rel_residual_true <= 1e-10
+    assert rel(u.cpu().numpy(), solvers.direct_solve(A, b)) <= 1e-8
+
+
+@pytest.mark.gpu
+def test_failure_modes():
+    banner("failure modes")
+    from paper_2104_08012_amd import fem
+    from paper_2104_08012_amd._lib import FEM_ERR_BREAKDOWN, FEM_WARN_NOT_CONVERGED, FemError
+    mesh, levels = make_pair(2, 2, 2, 0.0)
+    lev = levels[-1]
+    b = _t(_rhs(lev))
+    S = fem.Solver(mesh, fem.SolveOptions(rtol=1e-12, max_it=1)).setup()
+    x, res = S.solve(b, allow_not_converged=True)
+    assert res.status == FEM_WARN_NOT_CONVERGED and res.iterations == 1
+    with pytest.raises(FemError) as e:
+        S.solve(b)
+    assert e.value.status == FEM_WARN_NOT_CONVERGED
+    bn = b.clone()
+    bn[5] = float("nan")
+    with pytest.raises(FemError) as e:
+        S.solve(bn)
+    assert e.value.status == FEM_ERR_BREAKDOWN
+    kneg = -torch.ones(lev.n_vertices, dtype=torch.float64, device="cuda:0")
+    S2 = fem.Solver(mesh, fem.SolveOptions(rtol=1e-10, preconditioner="jacobi")).setup(kneg)
+    with pytest.raises(FemError) as e:
+        S2.solve(b)
+    assert e.value.status == FEM_ERR_BREAKDOWN
+    with pytest.raises(FemError):
+        fem.Solver(mesh, fem.SolveOptions(rtol=-1.0))
+
+
+@pytest.mark.gpu
+def test_determinism_and_warm_start():
+    banner("determinism / warm start")
+    from paper_2104_08012_amd import fem
+    mesh, levels = make_pair(2, 2, 2, 0.1)
+    lev = levels[-1]
+    b = _t(_rhs(lev))
+    S = fem.Solver(mesh, fem.SolveOptions(rtol=1e-10)).setup()
+    u1, r1 = S.solve(b)
+    u2, r2 = S.solve(b)
+    assert torch.equal(u1, u2) and r1.iterations == r2.iterations and r1.history == r2.history
+    S4 = fem.Solver(mesh, fem.SolveOptions(rtol=1e-4)).setup()
+    x, ra = S4.solve(b)
+    x, rb = S.solve(b, x=x)
+    assert rb.rel_residual_true <= 1e-10 and rb.iterations < r1.iterations
