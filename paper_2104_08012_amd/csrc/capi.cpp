@@ -92,9 +92,7 @@ fem_status fem_mesh_upload(fem_mesh* m, void* dev, size_t bytes, void* stream) {
     };
     hipError_t e = hipSuccess;
     for (const auto& t : m->red) {
-        if (e == hipSuccess) e = put(t.d_off, t.off.data(), t.off.size() * 4);
-        if (e == hipSuccess) e = put(t.d_ent, t.ent.data(), t.ent.size() * 4);
-        if (e == hipSuccess) e = put(t.d_slot, t.slot.data(), t.slot.size() * 4);
+        if (e == hipSuccess) e = put(t.d_first, t.first.data(), t.first.size() * 4);
     }
     for (const auto& T : m->tab) {
         if (e == hipSuccess) e = put(T.d64, T.t64.data(), T.t64.size() * 8);

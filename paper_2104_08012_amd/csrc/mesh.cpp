@@ -9,8 +9,10 @@
 //
 // Layout for the kernels:
 //  * cells are ordered brick by brick: bricks of B^3 cubes (B = 4, 2 or 1, the largest that
-//    divides n), bricks x-fastest, cubes inside a brick x-fastest, the 6 tetrahedra of a cube
-//    consecutive.  Cell index c = brick * 6 B^3 + cube_local * 6 + t.
+//    divides n), bricks x-fastest; inside a brick the cells are grouped by tetrahedron type t
+//    (the axis order of the path), cubes x-fastest within a group:
+//    c = brick * 6 B^3 + t * B^3 + cube_local, so that threads handling consecutive cubes read
+//    consecutive entries of every per-cell array.
 //  * cell-to-dof map: structure of arrays, map[i * C + c] for local node i, int32 with the sign
 //    bit set on boundary dofs.
 //  * geometric factor G = |det J| J^-1 J^-T: structure of arrays, 6 entries (00,11,22,01,02,12),
@@ -38,7 +40,7 @@ static void build_red(RedTable& t, int po, int B) {
     std::vector<std::vector<int32_t>> lists(t.Q);
     t.q_of.assign((size_t)t.NC * nl, -1);
     for (int cl = 0; cl < t.NC; ++cl) {
-        const int cube = cl / 6, tt = cl % 6;
+        const int B3 = B * B * B, cube = cl % B3, tt = cl / B3;
         const int lx = cube % B, ly = (cube / B) % B, lz = cube / (B * B);
         int V[4][3];
         V[0][0] = lx; V[0][1] = ly; V[0][2] = lz;
@@ -70,6 +72,11 @@ static void build_red(RedTable& t, int po, int B) {
     }
     t.off[t.Q] = (int32_t)t.ent.size();
     t.QB = nslot;
+    t.first.assign(t.Q, 0);
+    for (int q = 0; q < t.Q; ++q) {
+        const int e0 = t.ent[t.off[q]];
+        t.first[q] = ((e0 / t.NC) << 16) | (e0 % t.NC);
+    }
 }
 
 static int find_red(fem_mesh& m, int po, int B) {
@@ -84,8 +91,8 @@ static int find_red(fem_mesh& m, int po, int B) {
 static void cell_vertices(const HostLevel& L, int64_t c, int V[4][3]) {
     const int64_t brick = c / L.NC;
     const int cl = (int)(c % L.NC);
-    const int cube = cl / 6, t = cl % 6;
-    const int B = L.B;
+    const int B = L.B, B3 = B * B * B;
+    const int cube = cl % B3, t = cl / B3;
     const int bx = (int)(brick % L.nb), by = (int)((brick / L.nb) % L.nb), bz = (int)(brick / ((int64_t)L.nb * L.nb));
     V[0][0] = bx * B + cube % B;
     V[0][1] = by * B + (cube / B) % B;
@@ -159,7 +166,7 @@ static void build_level(HostLevel& L, const std::vector<std::array<int, 4>>& mi)
             L.G32[(size_t)e * C + c] = (float)g6[e];
         }
         // orientation of the path tetrahedron on the uniform lattice: sign of the permutation
-        const int t = (int)((c % L.NC) % 6);
+        const int t = (int)((c % L.NC) / ((int64_t)L.B * L.B * L.B));
         const double sgn = (t == 0 || t == 3 || t == 4) ? 1.0 : -1.0;
         const double h = 1.0 / n;
         if (!(det * sgn > 0.05 * h * h * h)) {
@@ -305,9 +312,7 @@ fem_status build_mesh(const fem_mesh_desc& d, fem_mesh& m) {
         return o;
     };
     for (auto& t : m.red) {
-        t.d_off = take(t.off.size() * 4);
-        t.d_ent = take(t.ent.size() * 4);
-        t.d_slot = take(t.slot.size() * 4);
+        t.d_first = take(t.first.size() * 4);
     }
     for (auto& T : m.tab) {
         T.d64 = take(T.t64.size() * 8);

@@ -2,6 +2,7 @@
 // gradient): fill the kernel arguments from the mesh's device tables and dispatch the template
 // instance for the degree, brick size, coefficient kind and precision.
 #include "ops.hpp"
+#include "cube.hpp"
 #include "scatter.hpp"
 
 namespace fem {
@@ -10,7 +11,12 @@ namespace {
 
 template <int KIND, typename T, int P, int B, bool KV>
 void launch_main(const SArgs<T>& a, int64_t nbricks, hipStream_t s) {
-    hipLaunchKernelGGL((k_brick<KIND, P, B, KV, T>), dim3((unsigned)nbricks), dim3(brick_threads(B)), 0, s, a);
+    if constexpr (KIND == K_APPLY && P <= 2 && B == 4) {
+        // one thread per cube for the low degrees (see cube.hpp)
+        hipLaunchKernelGGL((k_cube_apply<P, B, KV, T>), dim3((unsigned)nbricks), dim3(2 * B * B * B), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_brick<KIND, P, B, KV, T>), dim3((unsigned)nbricks), dim3(brick_threads(B)), 0, s, a);
+    }
 }
 
 template <int KIND, typename T, int P, int B>
@@ -36,18 +42,18 @@ void launch_p(int P, int B, bool kv, const SArgs<T>& a, int64_t nbricks, hipStre
 }
 
 template <typename T, int PO>
-void launch_fix_b(int B, const SArgs<T>& a, int64_t c0, int64_t c1, int64_t tot, hipStream_t s) {
-    const unsigned grid = (unsigned)((tot + 255) / 256);
-    if (B == 4) hipLaunchKernelGGL((k_fixup<PO, 4, T>), dim3(grid), dim3(256), 0, s, a, c0, c1, tot);
-    else if (B == 2) hipLaunchKernelGGL((k_fixup<PO, 2, T>), dim3(grid), dim3(256), 0, s, a, c0, c1, tot);
-    else hipLaunchKernelGGL((k_fixup<PO, 1, T>), dim3(grid), dim3(256), 0, s, a, c0, c1, tot);
+void launch_fix_b(int B, const SArgs<T>& a, const FixGeom& fg, hipStream_t s) {
+    const unsigned grid = (fg.total + 255) / 256;
+    if (B == 4) hipLaunchKernelGGL((k_fixup<PO, 4, T>), dim3(grid), dim3(256), 0, s, a, fg);
+    else if (B == 2) hipLaunchKernelGGL((k_fixup<PO, 2, T>), dim3(grid), dim3(256), 0, s, a, fg);
+    else hipLaunchKernelGGL((k_fixup<PO, 1, T>), dim3(grid), dim3(256), 0, s, a, fg);
 }
 
 template <typename T>
-void launch_fix(int PO, int B, const SArgs<T>& a, int64_t c0, int64_t c1, int64_t tot, hipStream_t s) {
-    if (PO == 1) launch_fix_b<T, 1>(B, a, c0, c1, tot, s);
-    else if (PO == 2) launch_fix_b<T, 2>(B, a, c0, c1, tot, s);
-    else launch_fix_b<T, 3>(B, a, c0, c1, tot, s);
+void launch_fix(int PO, int B, const SArgs<T>& a, const FixGeom& fg, hipStream_t s) {
+    if (PO == 1) launch_fix_b<T, 1>(B, a, fg, s);
+    else if (PO == 2) launch_fix_b<T, 2>(B, a, fg, s);
+    else launch_fix_b<T, 3>(B, a, fg, s);
 }
 
 template <typename T>
@@ -86,6 +92,7 @@ fem_status run_kind(const fem_mesh& m, int level, bool kvar, const ScatterIO<T>&
     a.fine_mi = dptr<int32_t>(m, m.d_fine_mi);
     a.owner = (KIND == K_RESTRICT) ? dptr<uint32_t>(m, L.d_owner) : nullptr;
     a.slots = const_cast<T*>(dptr<T>(m, L.d_slots));
+    a.gfirst = dptr<int32_t>(m, m.red[L.red].d_first);
     a.mask_cols = io.mask_cols;
     a.Lin = (KIND == K_RESTRICT) ? m.lev[level + 1].L : 0;
     a.x = io.x;
@@ -100,7 +107,16 @@ fem_status run_kind(const fem_mesh& m, int level, bool kvar, const ScatterIO<T>&
     launch_p<KIND, T>(m.p, L.B, kvar, a, L.nbricks, s);
     const int64_t Lo = a.Lout, nb = L.nb, np = Lo - nb - 1;
     const int64_t c0 = (nb + 1) * Lo * Lo, c1 = (nb + 1) * np * Lo, c2 = (nb + 1) * np * np;
-    launch_fix<T>(po, L.B, a, c0, c1, c0 + c1 + c2, s);
+    FixGeom fg;
+    fg.cnt0 = (uint32_t)c0;
+    fg.cnt01 = (uint32_t)(c0 + c1);
+    fg.total = (uint32_t)(c0 + c1 + c2);
+    fg.L = make_div((uint32_t)Lo);
+    fg.LL = make_div((uint32_t)(Lo * Lo));
+    fg.np = make_div((uint32_t)std::max<int64_t>(np, 1));
+    fg.npL = make_div((uint32_t)std::max<int64_t>(np * Lo, 1));
+    fg.npnp = make_div((uint32_t)std::max<int64_t>(np * np, 1));
+    launch_fix<T>(po, L.B, a, fg, s);
     return check_launch("scatter kernel");
 }
 

@@ -41,6 +41,7 @@ struct SArgs {
     const int32_t* fine_mi;          // restriction: barycentric multi-index of each fine point
     const uint32_t* owner;           // restriction: SoA owner masks of the coarse cells
     T* slots;                        // interface partials, box_slots(PO B) per brick
+    const int32_t* gfirst;           // per brick closure point: first (node, cell) reaching it
     int mask_cols;                   // gather boundary dofs as zero
     int Lin;                         // restriction: fine lattice size
     const T* x;                      // input field (u for the gradient)
@@ -66,7 +67,7 @@ __device__ __forceinline__ int brick_of_block(int bid, int nblocks) {
 // Integer vertex coordinates of a cell from its brick and local index.
 template <int B>
 __device__ __forceinline__ void cell_vertices(int bx, int by, int bz, int cl, int V[4][3]) {
-    const int cube = cl / 6, t = cl - 6 * (cl / 6);
+    const int cube = cl % (B * B * B), t = cl / (B * B * B);
     V[0][0] = bx * B + cube % B;
     V[0][1] = by * B + (cube / B) % B;
     V[0][2] = bz * B + cube / (B * B);
@@ -294,7 +295,7 @@ __device__ __forceinline__ void reduce_type(const SArgs<T>& a, const T* ys, int 
         for (int e = 0; e < CNT; ++e) {
             const int X = ka + INC.dx[TY][e], Y = kb + INC.dy[TY][e], Z = kc + INC.dz[TY][e];
             if (X >= 0 && X < B && Y >= 0 && Y < B && Z >= 0 && Z < B)
-                acc += ys[INC.i[TY][e] * NC + (X + B * (Y + B * Z)) * 6 + INC.t[TY][e]];
+                acc += ys[INC.i[TY][e] * NC + INC.t[TY][e] * (B * B * B) + (X + B * (Y + B * Z))];
         }
         const int la = ta + PO * ka, lb = tb + PO * kb, lc = tc + PO * kc;
         if (la == 0 || la == PB || lb == 0 || lb == PB || lc == 0 || lc == PB) {
@@ -333,63 +334,75 @@ __global__ void __launch_bounds__(brick_threads(B)) k_brick(SArgs<T> a) {
     reduce_all<PO, B, T>(a, ys, brick, bx, by, bz, std::make_integer_sequence<int, PO * PO * PO>{});
 }
 
-template <int PB>
-__device__ __forceinline__ int nonplane(int u) {
-    return (u / (PB - 1)) * PB + (u % (PB - 1)) + 1;
+// Exact unsigned division of n < 2^32 by a runtime divisor d >= 1 via the high half of a 64x64
+// product with M = floor((2^64 - 1) / d) + 1 (M = 0 encodes d = 1).
+struct Div {
+    uint64_t m;
+    uint32_t d;
+};
+inline Div make_div(uint32_t d) { return Div{d == 1 ? 0ull : (~0ull / d) + 1ull, d}; }
+__device__ __forceinline__ uint32_t udiv(uint32_t n, Div v) {
+    return v.m == 0 ? n : (uint32_t)__umul64hi((uint64_t)n, v.m);
 }
 
+struct FixGeom {
+    uint32_t cnt0, cnt01, total;   // family boundaries: x planes, + y planes, + z planes
+    Div L, LL, np, npL, npnp;
+};
+
 template <int PO, int B, typename T>
-__global__ void __launch_bounds__(256) k_fixup(SArgs<T> a, int64_t cnt0, int64_t cnt1, int64_t total) {
-    constexpr int PB = PO * B;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= total) return;
-    const int L = a.Lout, nb = a.nb;
-    const int np = L - nb - 1;   // lattice coordinates that are not on a brick plane
-    int I, J, K;
-    if (t < cnt0) {
-        const int64_t LL = (int64_t)L * L;
-        I = (int)(t / LL) * PB;
-        const int64_t r = t % LL;
-        J = (int)(r % L);
-        K = (int)(r / L);
-    } else if (t < cnt0 + cnt1) {
-        const int64_t u = t - cnt0, per = (int64_t)np * L;
-        J = (int)(u / per) * PB;
-        const int64_t r = u % per;
-        if constexpr (PB > 1) I = nonplane<PB>((int)(r % np)); else I = 0;
-        K = (int)(r / np);
+__global__ void __launch_bounds__(256) k_fixup(SArgs<T> a, FixGeom fg) {
+    constexpr int PB = PO * B, QB = box_slots<PB>();
+    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+    if (t >= fg.total) return;
+    const uint32_t L = fg.L.d, nb = (uint32_t)a.nb, np = fg.np.d;
+    uint32_t I, J, K;
+    if (t < fg.cnt0) {
+        const uint32_t pl = udiv(t, fg.LL), r = t - pl * fg.LL.d;
+        I = pl * PB;
+        K = udiv(r, fg.L);
+        J = r - K * L;
+    } else if (t < fg.cnt01) {
+        const uint32_t u = t - fg.cnt0;
+        const uint32_t pl = udiv(u, fg.npL), r = u - pl * fg.npL.d;
+        J = pl * PB;
+        K = udiv(r, fg.np);
+        const uint32_t iu = r - K * np;
+        if constexpr (PB > 1) I = (iu / (PB - 1)) * PB + iu % (PB - 1) + 1; else I = iu;
     } else {
-        const int64_t u = t - cnt0 - cnt1, per = (int64_t)np * np;
-        K = (int)(u / per) * PB;
-        const int64_t r = u % per;
+        const uint32_t u = t - fg.cnt01;
+        const uint32_t pl = udiv(u, fg.npnp), r = u - pl * fg.npnp.d;
+        K = pl * PB;
+        const uint32_t ju = udiv(r, fg.np), iu = r - ju * np;
         if constexpr (PB > 1) {
-            I = nonplane<PB>((int)(r % np));
-            J = nonplane<PB>((int)(r / np));
+            I = (iu / (PB - 1)) * PB + iu % (PB - 1) + 1;
+            J = (ju / (PB - 1)) * PB + ju % (PB - 1) + 1;
         } else {
-            I = J = 0;
+            I = iu;
+            J = ju;
         }
     }
     int cb[3][2], cloc[3][2], cn[3];
-    const int X[3] = {I, J, K};
+    const uint32_t X[3] = {I, J, K};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const int x = X[d];
-        if (x % PB == 0) {
+        const uint32_t x = X[d], q = x / PB, r = x - q * PB;
+        if (r == 0) {
             cn[d] = 0;
-            if (x / PB - 1 >= 0) { cb[d][cn[d]] = x / PB - 1; cloc[d][cn[d]] = PB; ++cn[d]; }
-            if (x / PB < nb) { cb[d][cn[d]] = x / PB; cloc[d][cn[d]] = 0; ++cn[d]; }
+            if (q >= 1) { cb[d][cn[d]] = (int)q - 1; cloc[d][cn[d]] = PB; ++cn[d]; }
+            if (q < nb) { cb[d][cn[d]] = (int)q; cloc[d][cn[d]] = 0; ++cn[d]; }
         } else {
             cn[d] = 1;
-            cb[d][0] = x / PB;
-            cloc[d][0] = x % PB;
+            cb[d][0] = (int)q;
+            cloc[d][0] = (int)r;
         }
     }
     T acc = T(0);
     for (int iz = 0; iz < cn[2]; ++iz)
         for (int iy = 0; iy < cn[1]; ++iy)
             for (int ix = 0; ix < cn[0]; ++ix) {
-                const int64_t brick = cb[0][ix] + (int64_t)nb * (cb[1][iy] + (int64_t)nb * cb[2][iz]);
-                acc += a.slots[brick * box_slots<PB>() + box_slot<PB>(cloc[0][ix], cloc[1][iy], cloc[2][iz])];
+                const uint32_t brick = (uint32_t)cb[0][ix] + nb * ((uint32_t)cb[1][iy] + nb * (uint32_t)cb[2][iz]);
+                acc += a.slots[(size_t)brick * QB + box_slot<PB>(cloc[0][ix], cloc[1][iy], cloc[2][iz])];
             }
     const int64_t g = I + (int64_t)L * (J + (int64_t)L * K);
     const bool bnd = I == 0 || J == 0 || K == 0 || I == L - 1 || J == L - 1 || K == L - 1;

@@ -1,0 +1,133 @@
+// Compile-time quadrature tabulations for the P1 and P2 stiffness kernels.
+//
+// The element integral int_K k grad(u).grad(v) is evaluated with a symmetric quadrature rule that
+// is exact for the integrand (degree 2p-2 for k = 1, 2p-1 for a P1 coefficient):
+//   P1:            the centroid, weight 1/6;
+//   P2, k = 1:     S31(a) with a = (5 - sqrt 5)/20, weights 1/24 (degree 2);
+//   P2, P1 k:      centroid (weight -2/15) and S31(1/6) (weights 3/40) (degree 3).
+// The reference gradients of the Lagrange basis at the points are computed here by constexpr
+// evaluation of the product form of the basis (phi_m = prod_i prod_{s<m_i} (p l_i - s)/(s+1)),
+// so the kernels see them as literals and drop the zero entries.  The host builds the same rules
+// independently (refelem.cpp) and checks their exactness; the two are compared at mesh creation.
+#pragma once
+#include "common.hpp"
+
+namespace fem {
+
+template <int P>
+struct NodeList {
+    static constexpr int NL = nloc_of(P);
+    int m[NL][4];
+    constexpr NodeList() : m{} {
+        int n = 0;
+        for (int v = 0; v < 4; ++v) {
+            for (int k = 0; k < 4; ++k) m[n][k] = (k == v) ? P : 0;
+            ++n;
+        }
+        const int ea[6] = {0, 0, 0, 1, 1, 2}, eb[6] = {1, 2, 3, 2, 3, 3};
+        for (int e = 0; e < 6; ++e)
+            for (int s = 1; s < P; ++s) {
+                for (int k = 0; k < 4; ++k) m[n][k] = 0;
+                m[n][ea[e]] = P - s;
+                m[n][eb[e]] = s;
+                ++n;
+            }
+        const int fa[4] = {0, 0, 0, 1}, fb[4] = {1, 1, 2, 2}, fc[4] = {2, 3, 3, 3};
+        if (P == 3)
+            for (int f = 0; f < 4; ++f) {
+                for (int k = 0; k < 4; ++k) m[n][k] = 0;
+                m[n][fa[f]] = m[n][fb[f]] = m[n][fc[f]] = 1;
+                ++n;
+            }
+    }
+};
+
+template <int P, bool KVAR>
+struct StiffTab {
+    static constexpr int NL = nloc_of(P), NQ = nq_of(P, KVAR);
+    double w[NQ];
+    double lam[NQ][4];
+    double D[NQ][3][NL];   // reference gradient d phi_i / d xi_d at point q
+
+    constexpr StiffTab() : w{}, lam{}, D{} {
+        // points (barycentric) and weights
+        if (P == 1) {
+            set_point(0, 0.25, 0.25, 0.25, 0.25, 1.0 / 6.0);
+        } else if (!KVAR) {
+            const double a = 0.13819660112501050975, b = 0.58541019662496847076;  // (5 -+ sqrt5)/20 ..
+            set_point(0, b, a, a, a, 1.0 / 24.0);
+            set_point(1, a, b, a, a, 1.0 / 24.0);
+            set_point(2, a, a, b, a, 1.0 / 24.0);
+            set_point(3, a, a, a, b, 1.0 / 24.0);
+        } else {
+            set_point(0, 0.25, 0.25, 0.25, 0.25, -2.0 / 15.0);
+            const double a = 1.0 / 6.0, b = 0.5;
+            set_point(1, b, a, a, a, 3.0 / 40.0);
+            set_point(2, a, b, a, a, 3.0 / 40.0);
+            set_point(3, a, a, b, a, 3.0 / 40.0);
+            set_point(4, a, a, a, b, 3.0 / 40.0);
+        }
+        const NodeList<P> nodes{};
+        const double dl[4][3] = {{-1, -1, -1}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+        for (int q = 0; q < NQ; ++q)
+            for (int i = 0; i < NL; ++i) {
+                double f[4] = {1, 1, 1, 1}, df[4] = {0, 0, 0, 0};
+                for (int k = 0; k < 4; ++k)
+                    for (int s = 0; s < nodes.m[i][k]; ++s) {
+                        const double a = (P * lam[q][k] - s) / (s + 1.0), da = P / (s + 1.0);
+                        df[k] = df[k] * a + f[k] * da;
+                        f[k] *= a;
+                    }
+                for (int d = 0; d < 3; ++d) {
+                    double g = 0.0;
+                    for (int k = 0; k < 4; ++k) {
+                        double prod = df[k];
+                        for (int j = 0; j < 4; ++j)
+                            if (j != k) prod *= f[j];
+                        g += prod * dl[k][d];
+                    }
+                    D[q][d][i] = g;
+                }
+            }
+    }
+    constexpr void set_point(int q, double l0, double l1, double l2, double l3, double wt) {
+        lam[q][0] = l0;
+        lam[q][1] = l1;
+        lam[q][2] = l2;
+        lam[q][3] = l3;
+        w[q] = wt;
+    }
+};
+
+// Local node i of the path tetrahedron t sits at cube-lattice point (pa, pb, pc) in [0, P]^3;
+// each cube point is listed with the first (t, i) that reaches it.
+template <int P>
+struct CubeNodes {
+    static constexpr int NL = nloc_of(P), PC = P + 1, NCP = PC * PC * PC;
+    int cp[6][NL];        // tetrahedron t, node i -> cube point index
+    int first_t[NCP], first_i[NCP];
+    constexpr CubeNodes() : cp{}, first_t{}, first_i{} {
+        const NodeList<P> nodes{};
+        for (int j = 0; j < NCP; ++j) first_t[j] = -1;
+        for (int t = 0; t < 6; ++t) {
+            const int s0 = perm_axis(t, 0), s1 = perm_axis(t, 1);
+            int V[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {1, 1, 1}};
+            V[1][s0] = 1;
+            V[2][s0] = 1;
+            V[2][s1] = 1;
+            for (int i = 0; i < NL; ++i) {
+                int X[3] = {0, 0, 0};
+                for (int v = 0; v < 4; ++v)
+                    for (int k = 0; k < 3; ++k) X[k] += nodes.m[i][v] * V[v][k];
+                const int j = X[0] + PC * (X[1] + PC * X[2]);
+                cp[t][i] = j;
+                if (first_t[j] < 0) {
+                    first_t[j] = t;
+                    first_i[j] = i;
+                }
+            }
+        }
+    }
+};
+
+}  // namespace fem
