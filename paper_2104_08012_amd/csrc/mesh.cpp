@@ -282,7 +282,12 @@ fem_status build_mesh(const fem_mesh_desc& d, fem_mesh& m) {
         L.red = find_red(m, p, L.B);
         L.red1 = find_red(m, 1, L.B);
         validate_level(L, m.red[L.red]);
-        L.slot_elems = L.nbricks * std::max(m.red[L.red].QB, m.red[L.red1].QB);
+        // interface slots: 8 side codes x the interface points of the degree-p and degree-1 lattices
+        auto iface = [&](int po) {
+            const int64_t Lo = (int64_t)po * L.n + 1, nb = L.nb, np = Lo - nb - 1;
+            return (nb + 1) * Lo * Lo + (nb + 1) * np * Lo + (nb + 1) * np * np;
+        };
+        L.slot_elems = 8 * std::max(iface(p), iface(1));
     }
     std::vector<std::array<int, 4>> pts;
     fine_points(p, pts);

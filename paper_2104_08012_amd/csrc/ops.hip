@@ -13,7 +13,7 @@ template <int KIND, typename T, int P, int B, bool KV>
 void launch_main(const SArgs<T>& a, int64_t nbricks, hipStream_t s) {
     if constexpr (KIND == K_APPLY && P <= 2 && B == 4) {
         // one thread per cube for the low degrees (see cube.hpp)
-        hipLaunchKernelGGL((k_cube_apply<P, B, KV, T>), dim3((unsigned)nbricks), dim3(2 * B * B * B), 0, s, a);
+        hipLaunchKernelGGL((k_cube_apply<P, B, KV, T>), dim3((unsigned)nbricks), dim3(B * B * B), 0, s, a);
     } else {
         hipLaunchKernelGGL((k_brick<KIND, P, B, KV, T>), dim3((unsigned)nbricks), dim3(brick_threads(B)), 0, s, a);
     }
@@ -104,9 +104,12 @@ fem_status run_kind(const fem_mesh& m, int level, bool kvar, const ScatterIO<T>&
     a.beta = (T)io.beta;
     a.row_mode = io.row_mode;
     a.xid = io.xid;
-    launch_p<KIND, T>(m.p, L.B, kvar, a, L.nbricks, s);
     const int64_t Lo = a.Lout, nb = L.nb, np = Lo - nb - 1;
     const int64_t c0 = (nb + 1) * Lo * Lo, c1 = (nb + 1) * np * Lo, c2 = (nb + 1) * np * np;
+    a.if_c0 = (uint32_t)c0;
+    a.if_c01 = (uint32_t)(c0 + c1);
+    a.if_tot = (uint32_t)(c0 + c1 + c2);
+    launch_p<KIND, T>(m.p, L.B, kvar, a, L.nbricks, s);
     FixGeom fg;
     fg.cnt0 = (uint32_t)c0;
     fg.cnt01 = (uint32_t)(c0 + c1);

@@ -40,7 +40,8 @@ struct SArgs {
     const T* aux;                    // mass: M_ref (nloc^2); restriction: P_loc (npts * nloc)
     const int32_t* fine_mi;          // restriction: barycentric multi-index of each fine point
     const uint32_t* owner;           // restriction: SoA owner masks of the coarse cells
-    T* slots;                        // interface partials, box_slots(PO B) per brick
+    T* slots;                        // interface partials: 8 arrays (side code) x if_tot points
+    uint32_t if_c0, if_c01, if_tot;  // interface points on x planes; + y planes; + z planes
     const int32_t* gfirst;           // per brick closure point: first (node, cell) reaching it
     int mask_cols;                   // gather boundary dofs as zero
     int Lin;                         // restriction: fine lattice size
@@ -92,6 +93,35 @@ __device__ __forceinline__ T gather(const T* __restrict__ x, int32_t m, int mask
 
 template <int KIND, int P, int B, bool KVAR, typename T>
 struct Producer;
+
+// Interface points (lattice points on a brick plane, coordinate = 0 mod PB in some direction) are
+// numbered family by family: points on x planes (x fastest within (plane, z, y)... see below),
+// then points on y planes but no x plane, then points on z planes only:
+//   x planes: t = (I/PB) L^2 + K L + J
+//   y planes: t = c0 + (J/PB) np L + K np + iu           (iu: rank of I among non-plane values)
+//   z planes: t = c01 + (K/PB) np^2 + ju np + iu
+// with np = L - nb - 1 non-plane coordinates per direction.  A brick's contribution to point t
+// is stored at slots[code * if_tot + t], code = sum_d [the brick is the upper one along d] << d,
+// so each (point, brick) pair has its own slot and the fix-up reads them contiguously.
+template <int PB>
+__device__ __forceinline__ uint32_t iface_index(uint32_t I, uint32_t J, uint32_t K, uint32_t L, uint32_t nb,
+                                                uint32_t c0, uint32_t c01) {
+    const uint32_t np = L - nb - 1;
+    if (I % PB == 0) return (I / PB) * L * L + K * L + J;
+    const uint32_t iu = (I / PB) * (PB - 1) + I % PB - 1;
+    if (J % PB == 0) return c0 + (J / PB) * np * L + K * np + iu;
+    const uint32_t ju = (J / PB) * (PB - 1) + J % PB - 1;
+    return c01 + (K / PB) * np * np + ju * np + iu;
+}
+
+// store the brick's partial sum at closure point (la, lb, lc) of brick (bx, by, bz)
+template <int PB, typename T>
+__device__ __forceinline__ void put_slot(const SArgs<T>& a, int bx, int by, int bz, int la, int lb, int lc, T v) {
+    const uint32_t I = (uint32_t)(bx * PB + la), J = (uint32_t)(by * PB + lb), K = (uint32_t)(bz * PB + lc);
+    const uint32_t t = iface_index<PB>(I, J, K, (uint32_t)a.Lout, (uint32_t)a.nb, a.if_c0, a.if_c01);
+    const uint32_t code = (la == 0 ? 1u : 0u) | (lb == 0 ? 2u : 0u) | (lc == 0 ? 4u : 0u);
+    a.slots[(size_t)code * a.if_tot + t] = v;
+}
 
 // Stiffness action: y_K = sum_q w_q k_q D_q^T G D_q x_K.
 template <int P, int B, bool KVAR, typename T>
@@ -299,7 +329,7 @@ __device__ __forceinline__ void reduce_type(const SArgs<T>& a, const T* ys, int 
         }
         const int la = ta + PO * ka, lb = tb + PO * kb, lc = tc + PO * kc;
         if (la == 0 || la == PB || lb == 0 || lb == PB || lc == 0 || lc == PB) {
-            a.slots[(int64_t)brick * QB + box_slot<PB>(la, lb, lc)] = acc;
+            put_slot<PB, T>(a, bx, by, bz, la, lb, lc, acc);
         } else {
             const int64_t g = (bx * PB + la) + L * ((by * PB + lb) + L * (int64_t)(bz * PB + lc));
             finalize(a, g, acc, false);
@@ -401,8 +431,8 @@ __global__ void __launch_bounds__(256) k_fixup(SArgs<T> a, FixGeom fg) {
     for (int iz = 0; iz < cn[2]; ++iz)
         for (int iy = 0; iy < cn[1]; ++iy)
             for (int ix = 0; ix < cn[0]; ++ix) {
-                const uint32_t brick = (uint32_t)cb[0][ix] + nb * ((uint32_t)cb[1][iy] + nb * (uint32_t)cb[2][iz]);
-                acc += a.slots[(size_t)brick * QB + box_slot<PB>(cloc[0][ix], cloc[1][iy], cloc[2][iz])];
+                const uint32_t code = (cloc[0][ix] == 0 ? 1u : 0u) | (cloc[1][iy] == 0 ? 2u : 0u) | (cloc[2][iz] == 0 ? 4u : 0u);
+                acc += a.slots[(size_t)code * fg.total + t];
             }
     const int64_t g = I + (int64_t)L * (J + (int64_t)L * K);
     const bool bnd = I == 0 || J == 0 || K == 0 || I == L - 1 || J == L - 1 || K == L - 1;
