@@ -27,6 +27,7 @@
 
 #include "common.hpp"
 #include "incidence.hpp"
+#include "tabulate.hpp"
 
 namespace fem {
 
@@ -123,13 +124,14 @@ __device__ __forceinline__ void put_slot(const SArgs<T>& a, int bx, int by, int 
     a.slots[(size_t)code * a.if_tot + t] = v;
 }
 
-// Stiffness action: y_K = sum_q w_q k_q D_q^T G D_q x_K.
+// Stiffness action: y_K = sum_q w_q k_q D_q^T G D_q x_K (compile-time tabulation, zero entries
+// of D generate no instructions).
 template <int P, int B, bool KVAR, typename T>
 struct Producer<K_APPLY, P, B, KVAR, T> {
-    static constexpr int NL = nloc_of(P), NQ = nq_of(P, KVAR), ST = 5 + 3 * NL;
+    static constexpr int NL = nloc_of(P), NQ = nq_of(P, KVAR);
     __device__ __forceinline__ static void run(const SArgs<T>& a, int64_t c, int cl, int bx, int by, int bz,
                                                T* out) {
-        const T* __restrict__ tab = a.tab;
+        constexpr StiffTab<P, KVAR> TB{};
         const int64_t C = a.C;
         const T g00 = a.G[c], g11 = a.G[C + c], g22 = a.G[2 * C + c];
         const T g01 = a.G[3 * C + c], g02 = a.G[4 * C + c], g12 = a.G[5 * C + c];
@@ -148,21 +150,28 @@ struct Producer<K_APPLY, P, B, KVAR, T> {
         for (int i = 0; i < NL; ++i) out[i] = T(0);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            const T* __restrict__ tq = tab + q * ST;
             T gx = T(0), gy = T(0), gz = T(0);
 #pragma unroll
             for (int i = 0; i < NL; ++i) {
-                gx += tq[5 + i] * xs[i];
-                gy += tq[5 + NL + i] * xs[i];
-                gz += tq[5 + 2 * NL + i] * xs[i];
+                if (TB.D[q][0][i] != 0.0) gx += T(TB.D[q][0][i]) * xs[i];
+                if (TB.D[q][1][i] != 0.0) gy += T(TB.D[q][1][i]) * xs[i];
+                if (TB.D[q][2][i] != 0.0) gz += T(TB.D[q][2][i]) * xs[i];
             }
-            T s = tq[0];
-            if constexpr (KVAR) s *= tq[1] * kv[0] + tq[2] * kv[1] + tq[3] * kv[2] + tq[4] * kv[3];
+            T s = T(TB.w[q]);
+            if constexpr (KVAR)
+                s *= T(TB.lam[q][0]) * kv[0] + T(TB.lam[q][1]) * kv[1] + T(TB.lam[q][2]) * kv[2] +
+                     T(TB.lam[q][3]) * kv[3];
             const T wx = s * (g00 * gx + g01 * gy + g02 * gz);
             const T wy = s * (g01 * gx + g11 * gy + g12 * gz);
             const T wz = s * (g02 * gx + g12 * gy + g22 * gz);
 #pragma unroll
-            for (int i = 0; i < NL; ++i) out[i] += tq[5 + i] * wx + tq[5 + NL + i] * wy + tq[5 + 2 * NL + i] * wz;
+            for (int i = 0; i < NL; ++i) {
+                T v = out[i];
+                if (TB.D[q][0][i] != 0.0) v += T(TB.D[q][0][i]) * wx;
+                if (TB.D[q][1][i] != 0.0) v += T(TB.D[q][1][i]) * wy;
+                if (TB.D[q][2][i] != 0.0) v += T(TB.D[q][2][i]) * wz;
+                out[i] = v;
+            }
         }
     }
 };

@@ -1,14 +1,17 @@
-// Compile-time quadrature tabulations for the P1 and P2 stiffness kernels.
+// Compile-time quadrature tabulations for the stiffness kernels.
 //
 // The element integral int_K k grad(u).grad(v) is evaluated with a symmetric quadrature rule that
 // is exact for the integrand (degree 2p-2 for k = 1, 2p-1 for a P1 coefficient):
 //   P1:            the centroid, weight 1/6;
 //   P2, k = 1:     S31(a) with a = (5 - sqrt 5)/20, weights 1/24 (degree 2);
-//   P2, P1 k:      centroid (weight -2/15) and S31(1/6) (weights 3/40) (degree 3).
+//   P2, P1 k:      centroid (weight -2/15) and S31(1/6) (weights 3/40) (degree 3);
+//   P3, k = 1:     centroid (-74/5625), S31(1/14) (343/45000), S22((1 - sqrt(5/14))/4) (56/2250)
+//                  (degree 4, 11 points);
+//   P3, P1 k:      S31(a1), S31(a2), S22(b), 14 points (degree 5), parameters to double precision.
 // The reference gradients of the Lagrange basis at the points are computed here by constexpr
 // evaluation of the product form of the basis (phi_m = prod_i prod_{s<m_i} (p l_i - s)/(s+1)),
 // so the kernels see them as literals and drop the zero entries.  The host builds the same rules
-// independently (refelem.cpp) and checks their exactness; the two are compared at mesh creation.
+// independently (refelem.cpp) and checks their exactness; tests/tab_check.cpp compares the two.
 #pragma once
 #include "common.hpp"
 
@@ -53,6 +56,16 @@ struct StiffTab {
         // points (barycentric) and weights
         if (P == 1) {
             set_point(0, 0.25, 0.25, 0.25, 0.25, 1.0 / 6.0);
+        } else if (P == 3 && !KVAR) {
+            set_point(0, 0.25, 0.25, 0.25, 0.25, -74.0 / 5625.0);
+            int q = 1;
+            q = s31(q, 1.0 / 14.0, 343.0 / 45000.0);
+            s22(q, 0.1005964238332008, 56.0 / 2250.0);
+        } else if (P == 3) {
+            int q = 0;
+            q = s31(q, 0.092735250310891248, 0.012248840519393664);
+            q = s31(q, 0.31088591926330061, 0.018781320953002674);
+            s22(q, 0.045503704125649434, 0.0070910034628468826);
         } else if (!KVAR) {
             const double a = 0.13819660112501050975, b = 0.58541019662496847076;  // (5 -+ sqrt5)/20 ..
             set_point(0, b, a, a, a, 1.0 / 24.0);
@@ -89,6 +102,27 @@ struct StiffTab {
                     D[q][d][i] = g;
                 }
             }
+    }
+    // the 4 points (b,a,a,a) permuted, b = 1 - 3a
+    constexpr int s31(int q, double a, double wt) {
+        const double b = 1.0 - 3.0 * a;
+        set_point(q, b, a, a, a, wt);
+        set_point(q + 1, a, b, a, a, wt);
+        set_point(q + 2, a, a, b, a, wt);
+        set_point(q + 3, a, a, a, b, wt);
+        return q + 4;
+    }
+    // the 6 points with a at the coordinate pairs (0,1),(0,2),(0,3),(1,2),(1,3),(2,3), b = 1/2 - a
+    constexpr int s22(int q, double a, double wt) {
+        const double b = 0.5 - a;
+        const int pr[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+        for (int k = 0; k < 6; ++k) {
+            double l[4] = {b, b, b, b};
+            l[pr[k][0]] = a;
+            l[pr[k][1]] = a;
+            set_point(q + k, l[0], l[1], l[2], l[3], wt);
+        }
+        return q + 6;
     }
     constexpr void set_point(int q, double l0, double l1, double l2, double l3, double wt) {
         lam[q][0] = l0;
