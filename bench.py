@@ -1,32 +1,39 @@
 """Benchmark of the hot path on one MI355X.
 
-Workload (default): P2 Lagrange Poisson on the unit cube, 16^3 x 6 tetrahedra refined twice to
-64^3 x 6 (1,572,864 cells, 2,146,689 dofs), manufactured solution sin(pi x) sin(pi y) sin(pi z)
-(right-hand side M f_I with f = 3 pi^2 u), homogeneous Dirichlet conditions, 3-level geometric
-multigrid (Chebyshev degree 2) preconditioning CG to relative residual 1e-8.  Synthetic, seeded
-inputs; nothing is read from disk.
+Default workload ("p2-64"): P2 Lagrange Poisson on the unit cube, 16^3 x 6 tetrahedra refined
+twice to 64^3 x 6 (1,572,864 cells, 2,146,689 dofs), manufactured solution
+sin(pi x) sin(pi y) sin(pi z) (right-hand side M f with f = 3 pi^2 u, boundary rows zero),
+homogeneous Dirichlet conditions, 3-level geometric multigrid (Chebyshev degree 2 / Jacobi)
+preconditioning CG to relative residual 1e-8.  Synthetic, seeded inputs; nothing is read from
+disk.
 
 One step = one pass of the hot path:
-  1. y = A x, the matrix-free P2 stiffness action in FP64 (Infinity Cache flushed first by reading
+  1. y = A x, the matrix-free stiffness action in FP64 (Infinity Cache flushed first by reading
      2 GiB: "cold"),
   2. the same action in FP32 (cold),
   3. the MG-CG solve to 1e-8 in FP64 (x0 = 0),
-  4. the MG-CG solve to 1e-8 with the FP32 smoother / FP64 outer loop (x0 = 0),
+  4. the MG-CG solve to 1e-8 with FP32 smoothing / transfers and FP64 outer CG (x0 = 0),
   5. the adjoint gradient kernel dJ/dk (u and lambda from steps 3 and 4).
 Setup (mesh upload, Jacobi diagonals, Lanczos estimates, coarse inverse) is outside the timed
 region and reported separately.
 
 value = operator-action GDoF/s of step 1: n_dofs / (mean duration of the action, from HIP events
-on the stream the kernels run on, over the timed steps).  roofline.achieved uses the algorithmic
-bytes of one action, B = 2 N 8 + 4 C nloc + 6 C 8 (x read and y write, int32 cell-to-dof map,
-per-cell geometric factors).
+recorded on the stream the action's kernels run on, over the timed steps).  roofline.achieved
+uses the algorithmic bytes of one action, B = 2 N s + 4 C nloc + 6 C s (+ N_v s for a P1
+coefficient): x read and y write, the int32 cell-to-dof map and the per-cell geometric factors.
+
+Other workloads (--workload): "p3-48-vark" (P3, k = exp(g), 6^3 refined 3x to 48^3, 4-level
+MG-CG, mixed precision as the solver of record), "p2-128" (P2 from 4^3 refined 5x to 128^3; the
+outer cycle uses the 3 finest levels and its 32^3 coarse level is solved by nested FP64 MG-PCG),
+"adjoint-p2-32" (P2 state on 32^3, P1 k: forward solve, misfit, adjoint solve and gradient),
+"p1-8-jacobi" (P1 8^3, Jacobi-CG to 1e-10) and "sweep-128" (the action alone, P1/P2/P3 x
+FP64/FP32 on 128^3 x 6 tetrahedra).
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -35,157 +42,220 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 METRIC = ("operator-action GDoF/s (% HBM roofline); MG-CG time to rel residual 1e-8, "
           "mixed vs FP64")
+
+WORKLOADS = {
+    "p2-64": dict(kind="solve", n0=16, refine=2, p=2, kvar=False, used=0, rhs="sin", rtol=1e-8),
+    "p3-48-vark": dict(kind="solve", n0=6, refine=3, p=3, kvar=True, used=0, rhs="one", rtol=1e-8),
+    "p2-128": dict(kind="solve", n0=4, refine=5, p=2, kvar=False, used=3, rhs="sin", rtol=1e-8),
+    "adjoint-p2-32": dict(kind="adjoint", n0=8, refine=2, p=2, kvar=True),
+    "p1-8-jacobi": dict(kind="jacobi", n0=8, refine=0, p=1, kvar=False, rtol=1e-10),
+    "sweep-128": dict(kind="sweep", n=128),
+}
+
+
+def nloc_of(p):
+    return (p + 1) * (p + 2) * (p + 3) // 6
+
+
+def nq_of(p, kvar):
+    return {1: 1, 2: 5 if kvar else 4, 3: 14 if kvar else 11}[p]
 
 
 def balg_bytes(C, N, nloc, s, NV=0):
     return 2 * N * s + 4 * C * nloc + 6 * C * s + NV * s
 
 
+def flops_per_cell(p, kvar):
+    """Algorithmic flops of the tabulated-gradient contraction: per quadrature point a gradient
+    (3 nloc multiply-adds), the geometric transform and weight (~20 flops) and the transposed
+    product (3 nloc multiply-adds)."""
+    nq, nl = nq_of(p, kvar), nloc_of(p)
+    return 12 * nq * nl + 20 * nq
+
+
 def kernel_sources_sha():
     h = hashlib.sha256()
-    for f in ("scatter.hpp", "incidence.hpp", "ops.hip"):
+    for f in ("cube.hpp", "scatter.hpp", "tabulate.hpp", "incidence.hpp", "common.hpp", "ops.hip"):
         with open(os.path.join(ROOT, "paper_2104_08012_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(workload_key):
-    """HBM traffic per action from the committed rocprofv3 counter summary, if it was taken on
-    the current kernel sources."""
+def traffic_from_profiles(key):
+    """HBM bytes per action from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel sources."""
     path = os.path.join(ROOT, "profiles", "apply_traffic.json")
     try:
         with open(path) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    e = d.get(workload_key)
+    e = d.get(key)
     if not e or e.get("kernel_sources_sha") != kernel_sources_sha():
         return None
     return e.get("traffic_bytes")
 
 
-def cpu_baseline(n0=16, n_refine=2, p=2, max_seconds=30.0):
-    """The oracle's matrix-free FP64 action (numpy, one thread) on the same mesh."""
+def roofline(p, kvar, C, N, NV, s, t, key):
+    """Roofline entry of the action: HBM-bound for P1/P2; for P3 the larger of the HBM fraction
+    and the fraction of the vector ALU peak (FP64 78.6, FP32 157.3 TFLOP/s)."""
+    nl = nloc_of(p)
+    B = balg_bytes(C, N, nl, s, NV if kvar else 0)
+    gbs = B / t / 1e9
+    out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(key),
+           "bytes_per_action": B}
+    F = flops_per_cell(p, kvar) * C
+    tf = F / t / 1e12
+    peak = FP64_PEAK_TFLOPS if s == 8 else FP32_PEAK_TFLOPS
+    if tf / peak > gbs / HBM_PEAK_GBS:
+        out.update({"bound": "alu", "achieved": round(tf, 2), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(tf / peak, 4), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                    "flops_per_action": F})
+    else:
+        out["alu_frac"] = round(tf / peak, 4)
+    return out
+
+
+def cpu_baseline(n, p, kvar, max_seconds=30.0):
+    """The oracle's matrix-free FP64 action (numpy, one thread).  Levels above 2^21 cells are
+    sampled by a 64^3 mesh of the same degree (the oracle's cost is linear in the cells)."""
     os.environ.setdefault("OMP_NUM_THREADS", "1")
-    import numpy as np
     import fem_inputs
     from oracle import assemble
     from oracle import mesh as om
+    n_s = n if 6 * n ** 3 <= (1 << 21) else 64
     t0 = time.perf_counter()
-    lev = om.single_level(n0 * 2 ** n_refine, p)
+    lev = om.single_level(n_s, p)
     x = fem_inputs.uniform_vector(lev.n_dofs, 0)
+    k = fem_inputs.k_exp_fourier(lev.vert_xyz) if kvar else None
     t_build = time.perf_counter() - t0
     reps, t_apply = 0, 0.0
     while reps < 3 and t_apply < max_seconds:
         t1 = time.perf_counter()
-        assemble.matfree_action(lev, x)
+        assemble.matfree_action(lev, x, k)
         t_apply += time.perf_counter() - t1
         reps += 1
     per = t_apply / reps
-    return {"value": lev.n_dofs / per / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{reps} full FP64 applications of the oracle's numpy matrix-free action on the "
-                       f"same {lev.n_dofs}-dof P2 mesh ({per:.2f} s each, mesh build {t_build:.1f} s, "
+    what = "the same" if n_s == n else f"a {n_s}^3 x 6 sample of the"
+    return {"value": round(lev.n_dofs / per / 1e9, 6), "unit": "GDoF/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{reps} FP64 applications of the oracle's numpy matrix-free action on {what} "
+                       f"P{p} mesh ({lev.n_dofs} dofs, {per:.2f} s each, mesh build {t_build:.1f} s, "
                        "single thread)")}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n0", type=int, default=16)
-    ap.add_argument("--refine", type=int, default=2)
-    ap.add_argument("--degree", type=int, default=2)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-solve", action="store_true", help="time the action only")
-    args = ap.parse_args()
+class Timer:
+    """HIP events recorded on torch's current stream, which is the stream the library's kernels
+    are launched on."""
 
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
-              f"WORLD_SIZE {world}); the multi-GPU decomposition is described in DESIGN.md",
-              file=sys.stderr)
-        sys.exit(2)
+    def __init__(self, torch):
+        self.torch = torch
+        self.pending = []
 
+    def start(self):
+        e0 = self.torch.cuda.Event(enable_timing=True)
+        e0.record()
+        return e0
+
+    def stop(self, e0, key, rec):
+        e1 = self.torch.cuda.Event(enable_timing=True)
+        e1.record()
+        self.pending.append((e0, e1, key, rec))
+
+    def collect(self):
+        self.torch.cuda.synchronize()
+        for e0, e1, key, rec in self.pending:
+            if rec is not None:
+                rec.setdefault(key, []).append(e0.elapsed_time(e1) * 1e-3)
+        self.pending.clear()
+
+
+def mean(v):
+    return sum(v) / len(v)
+
+
+def header(args, name, config, steps_wall):
+    return {"metric": METRIC, "value": None, "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(steps_wall / args.steps * 1e3, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic", "config": dict(workload=name, **config)}
+
+
+def rhs_for(mesh, kind, torch, dev, np, fem_inputs):
+    info = mesh.levels[-1]
+    p = mesh.degree
+    xyz = mesh.dof_lattice().astype(np.float64) / (p * info["n"])
+    if kind == "sin":
+        f = torch.as_tensor(fem_inputs.sin3_f(xyz), device=dev)
+        u_exact = torch.as_tensor(fem_inputs.sin3_u(xyz), device=dev)
+    else:
+        f = torch.ones(info["n_dofs"], dtype=torch.float64, device=dev)
+        u_exact = None
+    return mesh.mass(f, bc="zero_rows"), u_exact
+
+
+def run_solve(args, name, w):
     import numpy as np
     import torch
     import fem_inputs
     from paper_2104_08012_amd import fem
 
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    p = args.degree
+    p, kvar = w["p"], w["kvar"]
     t_setup0 = time.perf_counter()
-    mesh = fem.Mesh(args.n0, args.refine, p, device=dev)
+    mesh = fem.Mesh(w["n0"], w["refine"], p, device=dev)
     info = mesh.levels[-1]
     N, C, NV = info["n_dofs"], info["n_cells"], info["n_vertices"]
-    nloc = (p + 1) * (p + 2) * (p + 3) // 6
     x64 = torch.as_tensor(fem_inputs.uniform_vector(N, 0), device=dev)
     x32 = x64.float()
-    y64 = torch.empty_like(x64)
-    y32 = torch.empty_like(x32)
-    # reading 2 GiB evicts the 256 MB Infinity Cache with clean lines (writing a buffer instead would
-    # leave dirty lines whose write-back would be charged to the timed kernel)
+    y64, y32 = torch.empty_like(x64), torch.empty_like(x32)
+    k64 = torch.as_tensor(fem_inputs.k_exp_fourier(mesh.vertex_coords()), device=dev) if kvar else None
+    k32 = k64.float() if kvar else None
+    # reading 2 GiB evicts the 256 MB Infinity Cache with clean lines (writing a buffer instead
+    # would leave dirty lines whose write-back would be charged to the timed kernel)
     flush = torch.ones(1 << 29, dtype=torch.float32, device=dev)
-
-    solve = not args.no_solve
-    if solve:
-        lat = mesh.dof_lattice()
-        xyz = lat.astype(np.float64) / (p * info["n"])
-        f = torch.as_tensor(fem_inputs.sin3_f(xyz), device=dev)
-        b = mesh.mass(f, bc="zero_rows")
-        s64 = fem.Solver(mesh, fem.SolveOptions(rtol=1e-8, precision="fp64"))
-        ts = time.perf_counter()
-        s64.setup()
-        setup64 = time.perf_counter() - ts
-        smx = fem.Solver(mesh, fem.SolveOptions(rtol=1e-8, precision="mixed"))
-        ts = time.perf_counter()
-        smx.setup()
-        setupmx = time.perf_counter() - ts
-        u_sin = torch.as_tensor(fem_inputs.sin3_u(xyz), device=dev)
+    b, u_exact = rhs_for(mesh, w["rhs"], torch, dev, np, fem_inputs)
+    used = w["used"]
+    o64 = fem.SolveOptions(rtol=w["rtol"], precision="fp64", n_levels_used=used)
+    omx = fem.SolveOptions(rtol=w["rtol"], precision="mixed", n_levels_used=used)
+    ts = time.perf_counter()
+    s64 = fem.Solver(mesh, o64).setup(k64)
+    setup64 = time.perf_counter() - ts
+    ts = time.perf_counter()
+    smx = fem.Solver(mesh, omx).setup(k64)
+    setupmx = time.perf_counter() - ts
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup0
-
-    ev = lambda: torch.cuda.Event(enable_timing=True)
-    rec = {"apply64": [], "apply32": [], "solve64": [], "solvemx": [], "grad": [],
-           "it64": [], "itmx": [], "res64": [], "resmx": []}
+    tm = Timer(torch)
+    rec, last = {}, {}
 
     def step(record):
+        r = rec if record else None
         flush.sum()
-        e0, e1 = ev(), ev()
-        e0.record()
-        mesh.apply(x64, out=y64)
-        e1.record()
+        e = tm.start()
+        mesh.apply(x64, k64, out=y64)
+        tm.stop(e, "apply64", r)
         flush.sum()
-        e2, e3 = ev(), ev()
-        e2.record()
-        mesh.apply(x32, out=y32)
-        e3.record()
-        if solve:
-            t0 = time.perf_counter()
-            u64, r64 = s64.solve(b)
-            t1 = time.perf_counter()
-            umx, rmx = smx.solve(b)
-            t2 = time.perf_counter()
-            e4, e5 = ev(), ev()
-            e4.record()
-            g = mesh.adjoint_grad_k(u64, umx)
-            e5.record()
-        torch.cuda.synchronize()
+        e = tm.start()
+        mesh.apply(x32, k32, out=y32)
+        tm.stop(e, "apply32", r)
+        t0 = time.perf_counter()
+        u64, r64 = s64.solve(b)
+        t1 = time.perf_counter()
+        umx, rmx = smx.solve(b)
+        t2 = time.perf_counter()
+        e = tm.start()
+        mesh.adjoint_grad_k(u64, umx)
+        tm.stop(e, "grad", r)
+        tm.collect()
         if record:
-            rec["apply64"].append(e0.elapsed_time(e1) * 1e-3)
-            rec["apply32"].append(e2.elapsed_time(e3) * 1e-3)
-            if solve:
-                rec["solve64"].append(t1 - t0)
-                rec["solvemx"].append(t2 - t1)
-                rec["grad"].append(e4.elapsed_time(e5) * 1e-3)
-                rec["it64"].append(r64.iterations)
-                rec["itmx"].append(rmx.iterations)
-                rec["res64"].append(r64.rel_residual_true)
-                rec["resmx"].append(rmx.rel_residual_true)
-                rec["u64"], rec["umx"], rec["r64"], rec["rmx"] = u64, umx, r64, rmx
+            rec.setdefault("solve64", []).append(t1 - t0)
+            rec.setdefault("solvemx", []).append(t2 - t1)
+            last.update(u64=u64, umx=umx, r64=r64, rmx=rmx)
 
     for _ in range(args.warmup):
         step(False)
@@ -196,63 +266,214 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    t_apply = sum(rec["apply64"]) / len(rec["apply64"])
-    t_apply32 = sum(rec["apply32"]) / len(rec["apply32"])
-    B64 = balg_bytes(C, N, nloc, 8)
-    B32 = balg_bytes(C, N, nloc, 4)
-    achieved = B64 / t_apply / 1e9
-    wl_key = f"P{p}_n{args.n0}x{2 ** args.refine}_f64"
-    out = {
-        "metric": METRIC,
-        "value": round(N / t_apply / 1e9, 3),
-        "unit": "GDoF/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(wall / args.steps * 1e3, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": (f"P{p} Poisson -lap(u)=f, unit cube {args.n0}^3x6 tets refined {args.refine}x to "
-                         f"{info['n']}^3x6 ({C} cells, {N} dofs), sin MMS, "
-                         f"{mesh.n_levels}-level MG-CG (Chebyshev-2/Jacobi) to 1e-8; FP64 matrix-free action"),
-            "cells": C, "dofs": N, "degree": p, "levels": mesh.n_levels,
-        },
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_from_profiles(wl_key),
-                     "bytes_per_action": B64},
-        "apply_ms_fp64_cold": round(t_apply * 1e3, 4),
-        "apply_ms_fp32_cold": round(t_apply32 * 1e3, 4),
-        "apply_fp32_gdofs": round(N / t_apply32 / 1e9, 3),
-        "apply_fp32_hbm_frac": round(B32 / t_apply32 / 1e9 / HBM_PEAK_GBS, 4),
+    ta64, ta32 = mean(rec["apply64"]), mean(rec["apply32"])
+    key = f"P{p}{'k' if kvar else ''}_n{info['n']}"
+    out = header(args, name, {
+        "description": (f"P{p} Poisson -div(k grad u)=f, unit cube {w['n0']}^3x6 tets refined {w['refine']}x "
+                        f"to {info['n']}^3x6 ({C} cells, {N} dofs), "
+                        + ("k = exp(g), g a 16-mode Fourier P1 field, f = 1" if kvar else "k = 1, sin MMS")
+                        + f"; {mesh.n_levels if not used else used}-level MG-CG (Chebyshev-2/Jacobi) to "
+                        f"{w['rtol']:g}" + (", nested FP64 MG-PCG coarse solve" if used else "")),
+        "cells": C, "dofs": N, "degree": p, "levels": mesh.n_levels, "levels_in_outer_cycle": used or mesh.n_levels,
+        "coefficient": "P1 exp(g)" if kvar else "1"}, wall)
+    out["value"] = round(N / ta64 / 1e9, 3)
+    out["roofline"] = roofline(p, kvar, C, N, NV, 8, ta64, key + "_f64")
+    m64, mmx = mean(rec["solve64"]), mean(rec["solvemx"])
+    u64, umx, r64, rmx = last["u64"], last["umx"], last["r64"], last["rmx"]
+    nl = mesh.n_levels
+    out.update({
+        "apply_ms_fp64_cold": round(ta64 * 1e3, 4),
+        "apply_ms_fp32_cold": round(ta32 * 1e3, 4),
+        "apply_fp32_gdofs": round(N / ta32 / 1e9, 3),
+        "apply_fp32_roofline": roofline(p, kvar, C, N, NV, 4, ta32, key + "_f32"),
+        "mgcg_fp64_ms": round(m64 * 1e3, 3), "mgcg_mixed_ms": round(mmx * 1e3, 3),
+        "mixed_speedup": round(m64 / mmx, 3),
+        "mgcg_fp64_iterations": r64.iterations, "mgcg_mixed_iterations": rmx.iterations,
+        "mgcg_fp64_rel_residual": r64.rel_residual_true, "mgcg_mixed_rel_residual": rmx.rel_residual_true,
+        "mgcg_fp64_coarse_iterations": r64.coarse_iterations,
+        "mgcg_mixed_coarse_iterations": rmx.coarse_iterations,
+        "mixed_vs_fp64_solution_rel_diff": (torch.linalg.norm(u64 - umx) / torch.linalg.norm(u64)).item(),
+        "mgcg_fp64_coarse_ms": round(r64.coarse_ms, 3),
+        "mgcg_mixed_coarse_ms": round(rmx.coarse_ms, 3),
+        "mgcg_fp64_level_ms": [round(v, 3) for v in r64.level_ms[:nl]],
+        "mgcg_mixed_level_ms": [round(v, 3) for v in rmx.level_ms[:nl]],
+        "lambda_max": [round(v, 6) for v in r64.lambda_max[:nl]],
         "setup_s": round(setup_s, 3),
-    }
-    if solve:
-        m64 = sum(rec["solve64"]) / len(rec["solve64"])
-        mmx = sum(rec["solvemx"]) / len(rec["solvemx"])
-        u64, umx = rec["u64"], rec["umx"]
-        diff = (torch.linalg.norm(u64 - umx) / torch.linalg.norm(u64)).item()
-        out.update({
-            "mgcg_fp64_ms": round(m64 * 1e3, 3), "mgcg_mixed_ms": round(mmx * 1e3, 3),
-            "mixed_speedup": round(m64 / mmx, 3),
-            "mgcg_fp64_iterations": rec["it64"][-1], "mgcg_mixed_iterations": rec["itmx"][-1],
-            "mgcg_fp64_rel_residual": rec["res64"][-1], "mgcg_mixed_rel_residual": rec["resmx"][-1],
-            "mixed_vs_fp64_solution_rel_diff": diff,
-            "mgcg_fp64_coarse_ms": round(rec["r64"].coarse_ms, 3),
-            "mgcg_fp64_level_ms": [round(v, 3) for v in rec["r64"].level_ms[:mesh.n_levels]],
-            "mgcg_mixed_coarse_ms": round(rec["rmx"].coarse_ms, 3),
-            "lambda_max": [round(v, 6) for v in rec["r64"].lambda_max[:mesh.n_levels]],
-            "solver_setup_s": {"fp64": round(setup64, 3), "mixed": round(setupmx, 3)},
-            "adjoint_grad_kernel_ms": round(sum(rec["grad"]) / len(rec["grad"]) * 1e3, 4),
-        })
-        uh = u64
-        out["discretisation_rel_l2_nodal"] = (torch.linalg.norm(uh - u_sin) / torch.linalg.norm(u_sin)).item()
+        "solver_setup_s": {"fp64": round(setup64, 3), "mixed": round(setupmx, 3)},
+        "adjoint_grad_kernel_ms": round(mean(rec["grad"]) * 1e3, 4),
+    })
+    if u_exact is not None:
+        out["discretisation_rel_l2_nodal"] = (torch.linalg.norm(u64 - u_exact) / torch.linalg.norm(u_exact)).item()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.n0, args.refine, p)
+        out["cpu_baseline"] = cpu_baseline(info["n"], p, kvar)
+    return out
+
+
+def run_adjoint(args, name, w):
+    import numpy as np
+    import torch
+    import fem_inputs
+    from paper_2104_08012_amd import fem
+    from paper_2104_08012_amd.autograd import PoissonSolve, l2_misfit
+
+    dev = torch.device("cuda:0")
+    p = w["p"]
+    mesh = fem.Mesh(w["n0"], w["refine"], p, device=dev)
+    info = mesh.levels[-1]
+    N, C, NV = info["n_dofs"], info["n_cells"], info["n_vertices"]
+    vxyz = mesh.vertex_coords()
+    b = mesh.mass(torch.ones(N, dtype=torch.float64, device=dev), bc="zero_rows")     # f = 1
+    S = fem.Solver(mesh, fem.SolveOptions(rtol=1e-10, max_it=100))
+    k_ref = torch.as_tensor(fem_inputs.k_exp_fourier(vxyz, seed=2), device=dev)
+    u_ref = PoissonSolve.apply(k_ref, b, S)
+    lat = mesh.dof_lattice()
+    bnd = torch.as_tensor(((lat == 0) | (lat == p * info["n"])).any(axis=1), device=dev)
+    u_obs = u_ref + 0.01 * u_ref.abs().max() * torch.as_tensor(fem_inputs.noise(N), device=dev)
+    u_obs[bnd] = 0
+    k0 = torch.as_tensor(fem_inputs.k_exp_fourier(vxyz, seed=1), device=dev)
+    x64 = torch.as_tensor(fem_inputs.uniform_vector(N, 0), device=dev)
+    y64 = torch.empty_like(x64)
+    flush = torch.ones(1 << 29, dtype=torch.float32, device=dev)
+    tm = Timer(torch)
+    rec = {}
+
+    def step(record):
+        r = rec if record else None
+        flush.sum()
+        e = tm.start()
+        mesh.apply(x64, k0, out=y64)
+        tm.stop(e, "apply64", r)
+        t0 = time.perf_counter()
+        k = k0.clone().requires_grad_(True)
+        J = l2_misfit(PoissonSolve.apply(k, b, S), u_obs, mesh)
+        J.backward()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        u = PoissonSolve.apply(k0, b, S)
+        e = tm.start()
+        g = mesh.adjoint_grad_k(u, u_obs)
+        tm.stop(e, "grad", r)
+        tm.collect()
+        if record:
+            rec.setdefault("jgrad", []).append(t1 - t0)
+            rec["J"], rec["gnorm"] = J.item(), torch.linalg.norm(k.grad).item()
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    wall = time.perf_counter() - t0
+    ta = mean(rec["apply64"])
+    out = header(args, name, {
+        "description": (f"adjoint gradient: P{p} state on {w['n0']}^3x6 refined {w['refine']}x to {info['n']}^3x6 "
+                        f"({N} dofs), P1 k ({NV} vertices), J = 1/2 ||u - u_obs||^2_L2, u_obs = solution for a "
+                        "seeded k_ref + 1% noise; forward + adjoint MG-CG (1e-10) + dJ/dk kernel, FP64"),
+        "cells": C, "dofs": N, "degree": p, "levels": mesh.n_levels, "vertices": NV}, wall)
+    out["value"] = round(N / ta / 1e9, 3)
+    out["roofline"] = roofline(p, True, C, N, NV, 8, ta, f"P{p}k_n{info['n']}_f64")
+    tg = mean(rec["grad"])
+    gbytes = C * nloc_of(p) * 4 + 2 * N * 8 + NV * 8 + C * 6 * 8
+    out.update({"J_plus_gradJ_ms": round(mean(rec["jgrad"]) * 1e3, 3),
+                "adjoint_grad_kernel_ms": round(tg * 1e3, 4),
+                "adjoint_grad_hbm_frac": round(gbytes / tg / 1e9 / HBM_PEAK_GBS, 4),
+                "J": rec["J"], "grad_norm": rec["gnorm"]})
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(info["n"], p, True)
+    return out
+
+
+def run_jacobi(args, name, w):
+    import numpy as np
+    import torch
+    import fem_inputs
+    from paper_2104_08012_amd import fem
+
+    dev = torch.device("cuda:0")
+    p = w["p"]
+    mesh = fem.Mesh(w["n0"], 0, p, device=dev)
+    info = mesh.levels[-1]
+    N = info["n_dofs"]
+    b, u_exact = rhs_for(mesh, "sin", torch, dev, np, fem_inputs)
+    S = fem.Solver(mesh, fem.SolveOptions(rtol=w["rtol"], preconditioner="jacobi")).setup()
+    rec = {}
+    for i in range(args.warmup + args.steps):
+        t0 = time.perf_counter()
+        u, r = S.solve(b)
+        torch.cuda.synchronize()
+        if i >= args.warmup:
+            rec.setdefault("t", []).append(time.perf_counter() - t0)
+    wall = sum(rec["t"])
+    out = header(args, name, {"description": f"P1 8^3x6 ({N} dofs), sin MMS, Jacobi-CG to {w['rtol']:g}, FP64",
+                              "dofs": N, "degree": p}, wall)
+    out.update({"value": None, "solve_ms": round(mean(rec["t"]) * 1e3, 3), "iterations": r.iterations,
+                "rel_residual": r.rel_residual_true,
+                "discretisation_rel_l2_nodal": (torch.linalg.norm(u - u_exact) / torch.linalg.norm(u_exact)).item()})
+    return out
+
+
+def run_sweep(args, name, w):
+    import torch
+    import fem_inputs
+    from paper_2104_08012_amd import fem
+
+    dev = torch.device("cuda:0")
+    n = w["n"]
+    flush = torch.ones(1 << 29, dtype=torch.float32, device=dev)
+    rows = []
+    wall = 0.0
+    for p in (1, 2, 3):
+        mesh = fem.Mesh(n, 0, p, device=dev)
+        info = mesh.levels[-1]
+        N, C, NV = info["n_dofs"], info["n_cells"], info["n_vertices"]
+        for dt, s in ((torch.float64, 8), (torch.float32, 4)):
+            x = torch.as_tensor(fem_inputs.uniform_vector(N, 0), device=dev).to(dt)
+            y = torch.empty_like(x)
+            tm = Timer(torch)
+            rec = {}
+            t0 = time.perf_counter()
+            for i in range(args.warmup + args.steps):
+                flush.sum()
+                e = tm.start()
+                mesh.apply(x, out=y)
+                tm.stop(e, "t", rec if i >= args.warmup else None)
+                tm.collect()
+            wall += time.perf_counter() - t0
+            t = mean(rec["t"])
+            rows.append({"degree": p, "dtype": "f64" if s == 8 else "f32", "dofs": N, "cells": C,
+                         "ms_cold": round(t * 1e3, 4), "gdofs": round(N / t / 1e9, 3),
+                         "roofline": roofline(p, False, C, N, NV, s, t, f"P{p}_n{n}_{'f64' if s == 8 else 'f32'}")})
+            del x, y
+        del mesh
+        torch.cuda.empty_cache()
+    out = header(args, name, {"description": f"matrix-free action alone, k = 1, {n}^3x6 tets (12,582,912 cells), "
+                                             "P1/P2/P3 x FP64/FP32, Infinity Cache flushed before each",
+                              "cells": 6 * n ** 3}, wall)
+    p2 = [r for r in rows if r["degree"] == 2 and r["dtype"] == "f64"][0]
+    out.update({"value": p2["gdofs"], "roofline": p2["roofline"], "sweep": rows})
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="p2-64", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU decomposition is a design note, not an implemented path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    w = WORKLOADS[args.workload]
+    run = {"solve": run_solve, "adjoint": run_adjoint, "jacobi": run_jacobi, "sweep": run_sweep}[w["kind"]]
+    out = run(args, args.workload, w)
     print(json.dumps(out), flush=True)
 
 

@@ -115,7 +115,7 @@ fem_status fem_mesh_upload(fem_mesh* m, void* dev, size_t bytes, void* stream) {
         return FEM_ERR_HIP;
     }
     int dev_id = -1;
-    hipGetDevice(&dev_id);
+    if (hipGetDevice(&dev_id) != hipSuccess) dev_id = -1;
     m->dev = base;
     m->device = dev_id;
     return FEM_OK;

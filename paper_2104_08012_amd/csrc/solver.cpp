@@ -10,9 +10,11 @@
 //   * Transfers: prolongation interpolates the coarse function at the fine nodes; restriction is
 //     its transpose with boundary rows zeroed; level operators are rediscretised with the
 //     coefficient injected at the coarse vertices.
-//   * Coarsest level: exact FP64 solve with the dense inverse of the interior block, assembled by
-//     probing the matrix-free operator with (2p+1)^3 colour vectors and inverted by a blocked
-//     Gauss-Jordan sweep.
+//   * Coarsest level used: exact FP64 solve with the dense inverse of the interior block,
+//     assembled by probing the matrix-free operator with (2p+1)^3 colour vectors and inverted by a
+//     blocked Gauss-Jordan sweep.  When that level is too large for a dense inverse it is solved
+//     by a nested FP64 MG-PCG over the levels below it, to a relative residual of coarse_rtol
+//     (deepening the hierarchy under an expensive coarse level, as the paper does in Section 4).
 //   * Outer CG in FP64: x0 given (usually 0), stop when the true residual satisfies
 //     ||b - A x|| / ||b|| <= rtol.  Mixed precision keeps CG vectors, the outer operator, all
 //     inner products and the coarse solve in FP64 and runs the smoother, the level residuals and
@@ -24,6 +26,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -33,6 +36,8 @@ using namespace fem;
 
 namespace {
 
+constexpr int64_t kDenseMax = 40000;   // interior dofs of a level inverted densely
+
 struct LevelWs {
     size_t x = 0, b = 0, r = 0, d = 0, dinv = 0, k64 = 0, k32 = 0, b64 = 0, x64 = 0;
 };
@@ -40,15 +45,41 @@ struct LevelWs {
 struct Layout {
     std::vector<LevelWs> lev;
     size_t cg_r = 0, cg_z = 0, cg_p = 0, cg_q = 0, partial = 0, scal = 0, dense = 0, dense_xc = 0, jac_diag = 0;
+    size_t inner = 0, inner_bytes = 0;
     size_t total = 0;
-    int lo = 0, hi = 0, mixed = 0;
+    int top = 0, lo = 0, hi = 0, mixed = 0, nested = 0;
     int64_t dense_n = 0;
 };
 
-fem_status make_layout(const fem_mesh& m, const fem_solve_opts& o, bool with_k, Layout& L) {
-    L.hi = m.nlev - 1;
-    const int used = (o.n_levels_used <= 0 || o.n_levels_used > m.nlev) ? m.nlev : o.n_levels_used;
-    L.lo = m.nlev - used;
+int64_t interior_dofs(const fem_mesh& m, int l) {
+    const int64_t M = m.lev[l].L - 2;
+    return M * M * M;
+}
+
+// Options of the nested coarse solver: FP64 MG-PCG over all levels below, to coarse_rtol.
+fem_solve_opts inner_opts(const fem_solve_opts& o) {
+    fem_solve_opts in = o;
+    in.rtol = o.coarse_rtol;
+    in.max_it = 200;
+    in.precision = FEM_PREC_FP64;
+    in.n_levels_used = 0;
+    in.coarse_method = FEM_COARSE_AUTO;
+    in.replace_every = 0;
+    in.flexible = 0;
+    in.history = nullptr;
+    in.history_cap = 0;
+    in.preconditioner = FEM_PC_MG;
+    return in;
+}
+
+// Workspace layout of a solver whose finest level is `top` (the mesh's finest for the public
+// solver, the outer coarse level for a nested one).
+fem_status make_layout(const fem_mesh& m, const fem_solve_opts& o, int top, Layout& L) {
+    L.top = top;
+    L.hi = top;
+    const int avail = top + 1;
+    const int used = (o.n_levels_used <= 0 || o.n_levels_used > avail) ? avail : o.n_levels_used;
+    L.lo = top - used + 1;
     L.mixed = o.precision == FEM_PREC_MIXED;
     const size_t ts = L.mixed ? 4 : 8;
     size_t off = 0;
@@ -58,13 +89,11 @@ fem_status make_layout(const fem_mesh& m, const fem_solve_opts& o, bool with_k, 
         return r;
     };
     L.lev.assign(m.nlev, LevelWs{});
-    for (int l = 0; l < m.nlev; ++l) {
+    for (int l = 0; l <= top; ++l) {
         const int64_t N = m.lev[l].N, NV = m.lev[l].NV;
         LevelWs& w = L.lev[l];
-        if (with_k) {
-            w.k64 = take(NV * 8);
-            if (L.mixed) w.k32 = take(NV * 4);
-        }
+        w.k64 = take(NV * 8);
+        if (L.mixed) w.k32 = take(NV * 4);
         if (l < L.lo) continue;
         w.x = take(N * ts);
         w.b = take(N * ts);
@@ -85,25 +114,38 @@ fem_status make_layout(const fem_mesh& m, const fem_solve_opts& o, bool with_k, 
     L.scal = take(64 * 8);
     if (o.preconditioner == FEM_PC_JACOBI) {
         L.jac_diag = take(Nf * 8);
-        L.dense_n = 0;
         L.total = off;
         return FEM_OK;
     }
-    const HostLevel& C = m.lev[L.lo];
-    const int64_t M = C.L - 2;
-    L.dense_n = M * M * M;
+    const int64_t nI = interior_dofs(m, L.lo);
     const int method = o.coarse_method;
-    if (method == FEM_COARSE_NESTED) {
-        set_error("nested coarse solver is not available in this build");
+    const bool want_nested = method == FEM_COARSE_NESTED || (method == FEM_COARSE_AUTO && nI > kDenseMax);
+    if (want_nested && L.lo == 0) {
+        if (method == FEM_COARSE_NESTED) {
+            set_error("nested coarse solve needs a mesh level below the coarsest level used");
+            return FEM_ERR_UNSUPPORTED;
+        }
+        set_error("coarsest mesh level has " + std::to_string(nI) + " interior dofs, more than the " +
+                  std::to_string(kDenseMax) + " of the dense coarse solve; build the mesh with more refinements");
         return FEM_ERR_UNSUPPORTED;
     }
-    if (L.dense_n > 40000) {
-        set_error("coarsest level too large for the dense coarse solve (" + std::to_string(L.dense_n) +
-                  " interior dofs > 40000); use more levels");
+    if (!want_nested && nI > kDenseMax) {
+        set_error("dense coarse solve limited to " + std::to_string(kDenseMax) + " interior dofs (level has " +
+                  std::to_string(nI) + ")");
         return FEM_ERR_UNSUPPORTED;
     }
-    L.dense = take((size_t)L.dense_n * L.dense_n * 8);
-    L.dense_xc = take(std::max<int64_t>(L.dense_n, 1) * 8);
+    L.nested = want_nested ? 1 : 0;
+    if (L.nested) {
+        Layout in;
+        const fem_status st = make_layout(m, inner_opts(o), L.lo, in);
+        if (st) return st;
+        L.inner = take(in.total);
+        L.inner_bytes = in.total;
+    } else {
+        L.dense_n = nI;
+        L.dense = take((size_t)nI * nI * 8);
+        L.dense_xc = take(std::max<int64_t>(nI, 1) * 8);
+    }
     L.total = off;
     return FEM_OK;
 }
@@ -149,7 +191,16 @@ double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& 
     return mx;
 }
 
+// Event and free calls whose failure leaves nothing to undo.
+void ignore(hipError_t) {}
+
 }  // namespace
+
+#define FEM_TRY(expr)                   \
+    do {                                \
+        const fem_status _st = (expr);  \
+        if (_st != FEM_OK) return _st;  \
+    } while (0)
 
 struct fem_solver {
     const fem_mesh* m = nullptr;
@@ -167,9 +218,17 @@ struct fem_solver {
     int coarse_iters = 0;
     std::vector<hipEvent_t> ev;   // per level: pre start/end, post start/end; coarse start/end
     bool timing = true;
+    std::unique_ptr<fem_solver> inner;   // nested coarse solver over levels 0..L.lo
+
+    ~fem_solver() {
+        for (auto& e : ev) ignore(hipEventDestroy(e));
+        if (hscal) ignore(hipHostFree(hscal));
+    }
 
     template <typename T>
     T* p(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+
+    fem_status init(const fem_mesh* mesh, const fem_solve_opts& opts, int top, char* wsp, size_t bytes);
 
     fem_status apply64(int l, const double* x, double alpha, const double* z, double beta, double* y) {
         ScatterIO<double> io;
@@ -188,8 +247,8 @@ struct fem_solver {
     fem_status applyT(int l, const T* x, double alpha, const T* z, double beta, T* y);
 
     fem_status dots(int npair, int64_t n, const double* x0, const double* y0, const double* x1, const double* y1,
-                    const double* x2, const double* y2, double* out) {
-        DotPairs<double> pr{{x0, x1, x2}, {y0, y1, y2}};
+                    double* out) {
+        DotPairs<double> pr{{x0, x1, nullptr}, {y0, y1, nullptr}};
         dot_launch<double>(npair, n, pr, p<double>(L.partial), p<double>(L.scal), s);
         hipError_t e = hipMemcpyAsync(hscal, p<double>(L.scal), npair * sizeof(double), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -200,13 +259,54 @@ struct fem_solver {
         for (int i = 0; i < npair; ++i) out[i] = hscal[i];
         return FEM_OK;
     }
+    fem_status dot(int64_t n, const double* x, const double* y, double& out) {
+        double o2[2];
+        FEM_TRY(dots(1, n, x, y, nullptr, nullptr, o2));
+        out = o2[0];
+        return FEM_OK;
+    }
 
     template <typename T>
     fem_status vcycle(int l, const T* b, T* x);
-    fem_status coarse_solve_from(const double* b64, double* x64);
-    fem_status setup(const double* k);
+    fem_status coarse_solve(const double* b64, double* x64);
+    fem_status setup(const double* k_top);
     fem_status lanczos(int l, double& lm);
+    fem_status precondition(const double* r, double* z);
+    fem_status cg(const double* b, double* x, int& iters, double& rel_true, bool& converged);
+    void accumulate_times();
 };
+
+fem_status fem_solver::init(const fem_mesh* mesh, const fem_solve_opts& opts, int top, char* wsp, size_t bytes) {
+    m = mesh;
+    o = opts;
+    FEM_TRY(make_layout(*m, o, top, L));
+    if (bytes < L.total) {
+        set_error("solver workspace smaller than fem_solve_workspace_bytes");
+        return FEM_ERR_WORKSPACE;
+    }
+    ws = wsp;
+    ws_bytes = bytes;
+    if (hipHostMalloc((void**)&hscal, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        hscal = nullptr;
+        set_error("solver: pinned host allocation failed");
+        return FEM_ERR_HIP;
+    }
+    const int nl = m->nlev;
+    ev.assign(4 * nl + 2, nullptr);
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            set_error("solver: event creation failed");
+            return FEM_ERR_HIP;
+        }
+    level_ms.assign(nl, 0.0);
+    if (L.nested) {
+        inner.reset(new fem_solver());
+        FEM_TRY(inner->init(m, inner_opts(o), L.lo, ws + L.inner, L.inner_bytes));
+        inner->timing = false;
+    }
+    return FEM_OK;
+}
 
 template <>
 fem_status fem_solver::applyT<double>(int l, const double* x, double alpha, const double* z, double beta, double* y) {
@@ -227,33 +327,42 @@ fem_status fem_solver::applyT<float>(int l, const float* x, double alpha, const 
     return run_scatter<float>(*m, l, K_APPLY, kvar, io, s);
 }
 
-fem_status fem_solver::coarse_solve_from(const double* b64, double* x64) {
+// x64 = A_lo^-1 b64 on the coarsest level used (dense inverse, or nested MG-PCG from x = 0).
+fem_status fem_solver::coarse_solve(const double* b64, double* x64) {
+    if (inner) {
+        inner->s = s;
+        fill_launch<double>(m->lev[L.lo].N, 0.0, x64, s);
+        int its = 0;
+        double rel = 0.0;
+        bool conv = false;
+        FEM_TRY(inner->cg(b64, x64, its, rel, conv));
+        coarse_iters += its;
+        if (!conv) {
+            set_error("nested coarse solve stopped at relative residual " + std::to_string(rel) + " > coarse_rtol");
+            return FEM_ERR_BREAKDOWN;
+        }
+        return FEM_OK;
+    }
     const HostLevel& C = m->lev[L.lo];
     dense_solve_launch(C.L, p<double>(L.dense), b64, p<double>(L.dense_xc), x64, s);
     return check_launch("coarse solve");
 }
-
-#define FEM_TRY(expr)                   \
-    do {                                \
-        const fem_status _st = (expr);  \
-        if (_st != FEM_OK) return _st;  \
-    } while (0)
 
 template <typename T>
 fem_status fem_solver::vcycle(int l, const T* b, T* x) {
     const int nl = (int)m->lev.size();
     hipEvent_t* e = timing ? &ev[4 * l] : nullptr;
     if (l == L.lo) {
-        if (timing) hipEventRecord(ev[4 * nl], s);
+        if (timing) ignore(hipEventRecord(ev[4 * nl], s));
         if (L.mixed) {
             const int64_t n = m->lev[l].N;
             cast_launch<T, double>(n, b, p<double>(L.lev[l].b64), s);
-            FEM_TRY(coarse_solve_from(p<double>(L.lev[l].b64), p<double>(L.lev[l].x64)));
+            FEM_TRY(coarse_solve(p<double>(L.lev[l].b64), p<double>(L.lev[l].x64)));
             cast_launch<double, T>(n, p<double>(L.lev[l].x64), x, s);
         } else {
-            FEM_TRY(coarse_solve_from(reinterpret_cast<const double*>(b), reinterpret_cast<double*>(x)));
+            FEM_TRY(coarse_solve(reinterpret_cast<const double*>(b), reinterpret_cast<double*>(x)));
         }
-        if (timing) hipEventRecord(ev[4 * nl + 1], s);
+        if (timing) ignore(hipEventRecord(ev[4 * nl + 1], s));
         return FEM_OK;
     }
     const HostLevel& H = m->lev[l];
@@ -266,7 +375,7 @@ fem_status fem_solver::vcycle(int l, const T* b, T* x) {
     const double lm = lmax[l];
     const double a = o.cheb_lo * lm, bb = o.cheb_hi * lm;
     const double theta = 0.5 * (bb + a), delta = 0.5 * (bb - a), sigma = theta / delta;
-    if (timing) hipEventRecord(e[0], s);
+    if (timing) ignore(hipEventRecord(e[0], s));
     // pre-smoothing from x = 0; r tracks b - A x
     double rho = 1.0 / sigma;
     cheb_launch<T>(n, 0.0, 1.0 / theta, dinv, b, d, x, true, true, s);
@@ -287,9 +396,9 @@ fem_status fem_solver::vcycle(int l, const T* b, T* x) {
         io.row_mode = ROW_ZERO;
         FEM_TRY(run_scatter<T>(*m, l - 1, K_RESTRICT, false, io, s));
     }
-    if (timing) hipEventRecord(e[1], s);
+    if (timing) ignore(hipEventRecord(e[1], s));
     FEM_TRY(vcycle<T>(l - 1, bc, xc));
-    if (timing) hipEventRecord(e[2], s);
+    if (timing) ignore(hipEventRecord(e[2], s));
     FEM_TRY(run_prolong<T>(*m, l, xc, x, s));
     // post-smoothing from x
     FEM_TRY(applyT<T>(l, x, -1.0, b, 1.0, r));
@@ -301,7 +410,7 @@ fem_status fem_solver::vcycle(int l, const T* b, T* x) {
         cheb_launch<T>(n, rn * rho, 2.0 * rn / delta, dinv, r, d, x, false, false, s);
         rho = rn;
     }
-    if (timing) hipEventRecord(e[3], s);
+    if (timing) ignore(hipEventRecord(e[3], s));
     return FEM_OK;
 }
 
@@ -323,28 +432,28 @@ fem_status fem_solver::lanczos(int l, double& lm) {
     }
     random_launch(n, H.L, 0x5eed0005ull + (uint64_t)l, v, s);
     fill_launch<double>(n, 0.0, vp, s);
-    double out[3];
+    double nv = 0.0;
     mul_launch<double>(n, v, dg, wv, s);
-    FEM_TRY(dots(1, n, v, wv, nullptr, nullptr, nullptr, nullptr, out));
-    if (!(out[0] > 0)) {
+    FEM_TRY(dot(n, v, wv, nv));
+    if (!(nv > 0)) {
         set_error("Lanczos start vector has zero D-norm");
         return FEM_ERR_BREAKDOWN;
     }
-    axpby_launch<double>(n, 0.0, v, 1.0 / std::sqrt(out[0]), v, s);
+    axpby_launch<double>(n, 0.0, v, 1.0 / std::sqrt(nv), v, s);
     std::vector<double> al, be;
     double beta = 0.0;
     const int steps = std::max(2, o.eig_iters);
     for (int it = 0; it < steps; ++it) {
         FEM_TRY(apply64(l, v, 1.0, nullptr, 0.0, wv));                // w = A v
-        FEM_TRY(dots(1, n, wv, v, nullptr, nullptr, nullptr, nullptr, out));
-        const double alpha = out[0];                                   // (D^-1 A v)^T D v
+        double alpha = 0.0;
+        FEM_TRY(dot(n, wv, v, alpha));                                 // (D^-1 A v)^T D v
         al.push_back(alpha);
         div_launch<double>(n, wv, dg, wv, s);                          // w = D^-1 A v
         axpby_launch<double>(n, -alpha, v, 1.0, wv, s);
         if (beta != 0.0) axpby_launch<double>(n, -beta, vp, 1.0, wv, s);
         mul_launch<double>(n, wv, dg, vp, s);                          // v_prev is free here
-        FEM_TRY(dots(1, n, wv, vp, nullptr, nullptr, nullptr, nullptr, out));
-        const double b2 = out[0];
+        double b2 = 0.0;
+        FEM_TRY(dot(n, wv, vp, b2));
         if (!(b2 > 0) || it == steps - 1) break;
         beta = std::sqrt(b2);
         be.push_back(beta);
@@ -360,81 +469,212 @@ fem_status fem_solver::lanczos(int l, double& lm) {
     return FEM_OK;
 }
 
-fem_status fem_solver::setup(const double* k) {
-    const double t0 = now_ms();
-    kvar = k != nullptr;
-    const int nl = m->nlev;
-    if (o.preconditioner == FEM_PC_JACOBI) {
-        if (kvar) inject_launch<double>(m->lev[L.hi].n, 1, m->lev[L.hi].n, k, p<double>(L.lev[L.hi].k64), s);
-        ScatterIO<double> io;
-        io.k = kvar ? p<double>(L.lev[L.hi].k64) : nullptr;
-        io.y = p<double>(L.jac_diag);
-        io.row_mode = ROW_ONE;
-        FEM_TRY(run_scatter<double>(*m, L.hi, K_DIAG, kvar, io, s));
-        lmax.assign(nl, 0.0);
-        if (hipStreamSynchronize(s) != hipSuccess) return check_launch("solver setup");
-        ready = true;
-        return check_launch("solver setup");
-    }
+// k_top: the coefficient on the vertex lattice of this solver's finest level (NULL for k = 1).
+fem_status fem_solver::setup(const double* k_top) {
+    kvar = k_top != nullptr;
+    const int nl = m->nlev, top = L.top;
+    lmax.assign(nl, 0.0);
     // coefficient on every level by injection
     if (kvar) {
-        for (int l = 0; l < nl; ++l) {
-            const int stride = 1 << (nl - 1 - l);
-            inject_launch<double>(m->lev[l].n, stride, m->lev[nl - 1].n, k, p<double>(L.lev[l].k64), s);
-            if (L.mixed) inject_launch<float>(m->lev[l].n, stride, m->lev[nl - 1].n, k, p<float>(L.lev[l].k32), s);
+        for (int l = 0; l <= top; ++l) {
+            const int stride = 1 << (top - l);
+            inject_launch<double>(m->lev[l].n, stride, m->lev[top].n, k_top, p<double>(L.lev[l].k64), s);
+            if (L.mixed) inject_launch<float>(m->lev[l].n, stride, m->lev[top].n, k_top, p<float>(L.lev[l].k32), s);
         }
     }
-    // Jacobi scaling per level
-    for (int l = L.lo + 1; l <= L.hi; ++l) {
-        const int64_t n = m->lev[l].N;
-        double* dg = p<double>(L.cg_q);
+    if (o.preconditioner == FEM_PC_JACOBI) {
         ScatterIO<double> io;
-        io.k = kvar ? p<double>(L.lev[l].k64) : nullptr;
-        io.y = dg;
+        io.k = kvar ? p<double>(L.lev[top].k64) : nullptr;
+        io.y = p<double>(L.jac_diag);
         io.row_mode = ROW_ONE;
-        FEM_TRY(run_scatter<double>(*m, l, K_DIAG, kvar, io, s));
-        if (L.mixed) {
-            recip_launch<double>(n, dg, dg, s);
-            cast_launch<double, float>(n, dg, p<float>(L.lev[l].dinv), s);
-        } else {
-            recip_launch<double>(n, dg, p<double>(L.lev[l].dinv), s);
+        FEM_TRY(run_scatter<double>(*m, top, K_DIAG, kvar, io, s));
+    } else {
+        // Jacobi scaling per smoothed level
+        for (int l = L.lo + 1; l <= L.hi; ++l) {
+            const int64_t n = m->lev[l].N;
+            double* dg = p<double>(L.cg_q);
+            ScatterIO<double> io;
+            io.k = kvar ? p<double>(L.lev[l].k64) : nullptr;
+            io.y = dg;
+            io.row_mode = ROW_ONE;
+            FEM_TRY(run_scatter<double>(*m, l, K_DIAG, kvar, io, s));
+            if (L.mixed) {
+                recip_launch<double>(n, dg, dg, s);
+                cast_launch<double, float>(n, dg, p<float>(L.lev[l].dinv), s);
+            } else {
+                recip_launch<double>(n, dg, p<double>(L.lev[l].dinv), s);
+            }
         }
-    }
-    // lambda_max per smoothed level
-    lmax.assign(nl, 0.0);
-    for (int l = L.lo + 1; l <= L.hi; ++l) {
-        if (o.lambda_max_override && o.lambda_max_override[l] > 0) {
-            lmax[l] = o.lambda_max_override[l];
-        } else {
-            FEM_TRY(lanczos(l, lmax[l]));
+        // lambda_max per smoothed level
+        for (int l = L.lo + 1; l <= L.hi; ++l) {
+            if (o.lambda_max_override && o.lambda_max_override[l] > 0) lmax[l] = o.lambda_max_override[l];
+            else FEM_TRY(lanczos(l, lmax[l]));
         }
-    }
-    // coarse operator: dense interior block by probing, then its inverse
-    {
-        const HostLevel& C = m->lev[L.lo];
-        const int P = C.p, S = 2 * P + 1;
-        double* A = p<double>(L.dense);
-        const int64_t nd = L.dense_n;
-        fill_launch<double>(nd * nd, 0.0, A, s);
-        double* v = p<double>(L.cg_r);
-        double* y = p<double>(L.cg_z);
-        for (int c2 = 0; c2 < S; ++c2)
-            for (int c1 = 0; c1 < S; ++c1)
-                for (int c0 = 0; c0 < S; ++c0) {
-                    probe_fill_launch(C.L, S, c0, c1, c2, v, s);
-                    FEM_TRY(apply64(L.lo, v, 1.0, nullptr, 0.0, y));
-                    probe_extract_launch(C.L, P, S, c0, c1, c2, y, A, s);
-                }
-        FEM_TRY(dense_invert(nd, A, nullptr, s));
+        if (inner) {
+            inner->s = s;
+            FEM_TRY(inner->setup(kvar ? p<double>(L.lev[L.lo].k64) : nullptr));
+            for (int l = 0; l <= L.lo; ++l) lmax[l] = inner->lmax[l];
+        } else {
+            // coarse operator: dense interior block by probing, then its inverse
+            const HostLevel& C = m->lev[L.lo];
+            const int P = C.p, S = 2 * P + 1;
+            double* A = p<double>(L.dense);
+            const int64_t nd = L.dense_n;
+            fill_launch<double>(nd * nd, 0.0, A, s);
+            double* v = p<double>(L.cg_r);
+            double* y = p<double>(L.cg_z);
+            for (int c2 = 0; c2 < S; ++c2)
+                for (int c1 = 0; c1 < S; ++c1)
+                    for (int c0 = 0; c0 < S; ++c0) {
+                        probe_fill_launch(C.L, S, c0, c1, c2, v, s);
+                        FEM_TRY(apply64(L.lo, v, 1.0, nullptr, 0.0, y));
+                        probe_extract_launch(C.L, P, S, c0, c1, c2, y, A, s);
+                    }
+            FEM_TRY(dense_invert(nd, A, nullptr, s));
+        }
     }
     const hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         set_error(std::string("solver setup: ") + hipGetErrorString(e));
         return FEM_ERR_HIP;
     }
+    FEM_TRY(check_launch("solver setup"));
     ready = true;
-    (void)t0;
-    return check_launch("solver setup");
+    return FEM_OK;
+}
+
+// Adds the V-cycle's per-level times of the last preconditioner application (events recorded on
+// the stream; called after a host synchronisation).
+void fem_solver::accumulate_times() {
+    const int nl = m->nlev;
+    for (int l = L.lo + 1; l <= L.hi; ++l) {
+        float a = 0.f, b = 0.f;
+        if (hipEventElapsedTime(&a, ev[4 * l], ev[4 * l + 1]) == hipSuccess &&
+            hipEventElapsedTime(&b, ev[4 * l + 2], ev[4 * l + 3]) == hipSuccess)
+            level_ms[l] += a + b;
+    }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev[4 * nl], ev[4 * nl + 1]) == hipSuccess) {
+        coarse_ms += ms;
+        level_ms[L.lo] += ms;
+    }
+}
+
+fem_status fem_solver::precondition(const double* r, double* z) {
+    const int hi = L.hi;
+    if (o.preconditioner == FEM_PC_JACOBI) {
+        div_launch<double>(m->lev[hi].N, r, p<double>(L.jac_diag), z, s);
+        return check_launch("Jacobi preconditioner");
+    }
+    if (L.mixed) {
+        const int64_t n = m->lev[hi].N;
+        float* b = p<float>(L.lev[hi].b);
+        float* x = p<float>(L.lev[hi].x);
+        cast_launch<double, float>(n, r, b, s);
+        FEM_TRY(vcycle<float>(hi, b, x));
+        cast_launch<float, double>(n, x, z, s);
+        return FEM_OK;
+    }
+    return vcycle<double>(hi, r, z);
+}
+
+// Preconditioned CG on this solver's finest level; x holds the initial guess and returns the
+// iterate.  converged reports whether the true relative residual reached o.rtol.
+fem_status fem_solver::cg(const double* b, double* x, int& it, double& rel_true, bool& converged) {
+    const int hi = L.hi;
+    const int64_t n = m->lev[hi].N;
+    double* r = p<double>(L.cg_r);
+    double* z = p<double>(L.cg_z);
+    double* pp = p<double>(L.cg_p);
+    double* q = p<double>(L.cg_q);
+    double out[2];
+    it = 0;
+    converged = false;
+    rel_true = 0.0;
+    auto record = [&](int i, double v) {
+        if (o.history && i < o.history_cap) o.history[i] = v;
+    };
+    const bool tmg = timing && o.preconditioner == FEM_PC_MG;
+    double bb = 0.0;
+    FEM_TRY(dot(n, b, b, bb));
+    const double nb = std::sqrt(bb);
+    if (!std::isfinite(nb)) {
+        set_error("solver: right-hand side is not finite");
+        return FEM_ERR_BREAKDOWN;
+    }
+    if (nb == 0.0) {
+        fill_launch<double>(n, 0.0, x, s);
+        record(0, 0.0);
+        converged = true;
+        return check_launch("solver");
+    }
+    FEM_TRY(apply64(hi, x, -1.0, b, 1.0, r));                 // r = b - A x
+    double rr = 0.0;
+    FEM_TRY(dot(n, r, r, rr));
+    double rel = std::sqrt(rr) / nb;
+    record(0, rel);
+    double rz = 0.0;
+    if (rel <= o.rtol) {
+        converged = true;
+    } else {
+        FEM_TRY(precondition(r, z));
+        FEM_TRY(dot(n, r, z, rz));
+        if (tmg) accumulate_times();
+        if (!(rz > 0) || !std::isfinite(rz)) {
+            set_error("solver: preconditioner is not positive definite (r^T B r <= 0)");
+            return FEM_ERR_BREAKDOWN;
+        }
+        axpby_launch<double>(n, 1.0, z, 0.0, pp, s);
+    }
+    while (!converged && it < o.max_it) {
+        FEM_TRY(apply64(hi, pp, 1.0, nullptr, 0.0, q));        // q = A p
+        double pq = 0.0;
+        FEM_TRY(dot(n, pp, q, pq));
+        if (!(pq > 0) || !std::isfinite(pq)) {
+            set_error("solver: CG breakdown (p^T A p <= 0 or not finite)");
+            return FEM_ERR_BREAKDOWN;
+        }
+        const double alpha = rz / pq;
+        cg_update_launch(n, alpha, pp, q, x, r, s);
+        ++it;
+        if (o.replace_every > 0 && it % o.replace_every == 0) FEM_TRY(apply64(hi, x, -1.0, b, 1.0, r));
+        FEM_TRY(dot(n, r, r, rr));
+        rel = std::sqrt(rr) / nb;
+        record(it, rel);
+        if (!std::isfinite(rel)) {
+            set_error("solver: residual not finite");
+            return FEM_ERR_BREAKDOWN;
+        }
+        if (rel <= o.rtol) {
+            // confirm with the true residual; if it disagrees, continue from it
+            FEM_TRY(apply64(hi, x, -1.0, b, 1.0, q));
+            double tt = 0.0;
+            FEM_TRY(dot(n, q, q, tt));
+            if (std::sqrt(tt) / nb <= o.rtol) {
+                converged = true;
+                break;
+            }
+            axpby_launch<double>(n, 1.0, q, 0.0, r, s);
+        }
+        FEM_TRY(precondition(r, z));
+        FEM_TRY(dots(2, n, r, z, q, z, out));                  // q still holds A p
+        if (tmg) accumulate_times();
+        const double rz_new = out[0], qz = out[1];
+        if (!(rz_new > 0) || !std::isfinite(rz_new)) {
+            set_error("solver: preconditioner is not positive definite (r^T B r <= 0)");
+            return FEM_ERR_BREAKDOWN;
+        }
+        const double beta = o.flexible ? (-alpha * qz / rz) : (rz_new / rz);
+        rz = rz_new;
+        axpby_launch<double>(n, 1.0, z, beta, pp, s);
+    }
+    // true residual at exit
+    FEM_TRY(apply64(hi, x, -1.0, b, 1.0, q));
+    double tt = 0.0;
+    FEM_TRY(dot(n, q, q, tt));
+    rel_true = std::sqrt(tt) / nb;
+    if (!converged) converged = rel_true <= o.rtol;
+    return FEM_OK;
 }
 
 extern "C" {
@@ -467,7 +707,8 @@ static fem_status check_opts(const fem_mesh* m, const fem_solve_opts* o) {
     }
     if (!(o->rtol > 0) || o->max_it < 1 || o->cheb_degree < 1 || o->cheb_degree > 16 || !(o->cheb_hi > o->cheb_lo) ||
         !(o->cheb_lo > 0) || (o->precision != FEM_PREC_FP64 && o->precision != FEM_PREC_MIXED) ||
-        o->n_levels_used < 0 || o->eig_iters < 0 || o->eig_iters > 64 ||
+        o->n_levels_used < 0 || o->eig_iters < 0 || o->eig_iters > 64 || !(o->coarse_rtol > 0) ||
+        o->coarse_method < FEM_COARSE_AUTO || o->coarse_method > FEM_COARSE_NESTED ||
         (o->preconditioner != FEM_PC_MG && o->preconditioner != FEM_PC_JACOBI)) {
         set_error("solver: invalid options");
         return FEM_ERR_INVALID_ARG;
@@ -483,7 +724,7 @@ fem_status fem_solve_workspace_bytes(const fem_mesh* m, const fem_solve_opts* o,
         return FEM_ERR_INVALID_ARG;
     }
     Layout L;
-    st = make_layout(*m, *o, true, L);
+    st = make_layout(*m, *o, m->nlev - 1, L);
     if (st) return st;
     *bytes = L.total;
     return FEM_OK;
@@ -505,40 +746,16 @@ fem_status fem_solver_create(const fem_mesh* m, const fem_solve_opts* o, void* w
         return FEM_ERR_INVALID_ARG;
     }
     fem_solver* S = new fem_solver();
-    S->m = m;
-    S->o = *o;
-    S->o.history = o->history;
-    st = make_layout(*m, *o, true, S->L);
+    st = S->init(m, *o, m->nlev - 1, (char*)ws, ws_bytes);
     if (st) {
         delete S;
         return st;
     }
-    if (ws_bytes < S->L.total) {
-        delete S;
-        set_error("fem_solver_create: workspace smaller than fem_solve_workspace_bytes");
-        return FEM_ERR_WORKSPACE;
-    }
-    S->ws = (char*)ws;
-    S->ws_bytes = ws_bytes;
-    if (hipHostMalloc((void**)&S->hscal, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-        delete S;
-        set_error("fem_solver_create: pinned host allocation failed");
-        return FEM_ERR_HIP;
-    }
-    const int nl = m->nlev;
-    S->ev.resize(4 * nl + 2);
-    for (auto& e : S->ev) hipEventCreate(&e);
-    S->level_ms.assign(nl, 0.0);
     *out = S;
     return FEM_OK;
 }
 
-void fem_solver_destroy(fem_solver* S) {
-    if (!S) return;
-    for (auto& e : S->ev) hipEventDestroy(e);
-    if (S->hscal) hipHostFree(S->hscal);
-    delete S;
-}
+void fem_solver_destroy(fem_solver* S) { delete S; }
 
 fem_status fem_solver_setup(fem_solver* S, const double* k, void* stream) {
     if (!S) {
@@ -548,42 +765,6 @@ fem_status fem_solver_setup(fem_solver* S, const double* k, void* stream) {
     S->s = (hipStream_t)stream;
     S->ready = false;
     return S->setup(k);
-}
-
-static void accumulate_times(fem_solver* S) {
-    const int nl = S->m->nlev;
-    float ms = 0.f;
-    for (int l = S->L.lo + 1; l <= S->L.hi; ++l) {
-        float a = 0.f, b = 0.f;
-        if (hipEventElapsedTime(&a, S->ev[4 * l], S->ev[4 * l + 1]) == hipSuccess &&
-            hipEventElapsedTime(&b, S->ev[4 * l + 2], S->ev[4 * l + 3]) == hipSuccess)
-            S->level_ms[l] += a + b;
-    }
-    if (hipEventElapsedTime(&ms, S->ev[4 * nl], S->ev[4 * nl + 1]) == hipSuccess) {
-        S->coarse_ms += ms;
-        S->level_ms[S->L.lo] += ms;
-    }
-    // the coarser levels' time is nested in each level's pre/post gap; subtract nothing (the
-    // pre and post segments exclude the recursion)
-}
-
-static fem_status apply_preconditioner(fem_solver* S, const double* r, double* z) {
-    const int hi = S->L.hi;
-    if (S->o.preconditioner == FEM_PC_JACOBI) {
-        const int64_t n = S->m->lev[hi].N;
-        div_launch<double>(n, r, S->p<double>(S->L.jac_diag), z, S->s);
-        return check_launch("Jacobi preconditioner");
-    }
-    if (S->L.mixed) {
-        const int64_t n = S->m->lev[hi].N;
-        float* b = S->p<float>(S->L.lev[hi].b);
-        float* x = S->p<float>(S->L.lev[hi].x);
-        cast_launch<double, float>(n, r, b, S->s);
-        FEM_TRY(S->vcycle<float>(hi, b, x));
-        cast_launch<float, double>(n, x, z, S->s);
-        return FEM_OK;
-    }
-    return S->vcycle<double>(hi, r, z);
 }
 
 fem_status fem_solver_vcycle(fem_solver* S, const double* r, double* z, void* stream) {
@@ -598,7 +779,7 @@ fem_status fem_solver_vcycle(fem_solver* S, const double* r, double* z, void* st
     S->s = (hipStream_t)stream;
     const bool t = S->timing;
     S->timing = false;
-    const fem_status st = apply_preconditioner(S, r, z);
+    const fem_status st = S->precondition(r, z);
     S->timing = t;
     if (st) return st;
     return check_launch("fem_solver_vcycle");
@@ -615,103 +796,24 @@ fem_status fem_solver_solve(fem_solver* S, const double* b, double* x, fem_solve
     }
     S->s = (hipStream_t)stream;
     const double t0 = now_ms();
-    const int hi = S->L.hi;
-    const int64_t n = S->m->lev[hi].N;
-    double* r = S->p<double>(S->L.cg_r);
-    double* z = S->p<double>(S->L.cg_z);
-    double* pp = S->p<double>(S->L.cg_p);
-    double* q = S->p<double>(S->L.cg_q);
     S->coarse_ms = 0.0;
+    S->coarse_iters = 0;
     std::fill(S->level_ms.begin(), S->level_ms.end(), 0.0);
-    const fem_solve_opts& o = S->o;
-    double out[3];
-    FEM_TRY(S->dots(1, n, b, b, nullptr, nullptr, nullptr, nullptr, out));
-    const double nb = std::sqrt(out[0]);
     int it = 0;
-    fem_status status = FEM_OK;
-    double rel = 0.0, rel_true = 0.0;
-    auto record = [&](int i, double v) {
-        if (o.history && i < o.history_cap) o.history[i] = v;
-    };
-    if (!std::isfinite(nb)) {
-        set_error("fem_solver_solve: right-hand side is not finite");
-        return FEM_ERR_BREAKDOWN;
-    }
-    if (nb == 0.0) {
-        fill_launch<double>(n, 0.0, x, S->s);
-        hipStreamSynchronize(S->s);
-        record(0, 0.0);
-    } else {
-        FEM_TRY(S->apply64(hi, x, -1.0, b, 1.0, r));            // r = b - A x
-        FEM_TRY(S->dots(1, n, r, r, nullptr, nullptr, nullptr, nullptr, out));
-        rel = std::sqrt(out[0]) / nb;
-        record(0, rel);
-        bool converged = rel <= o.rtol;
-        double rz = 0.0;
-        if (!converged) {
-            FEM_TRY(apply_preconditioner(S, r, z));
-            FEM_TRY(S->dots(1, n, r, z, nullptr, nullptr, nullptr, nullptr, out));
-            if (S->timing && S->o.preconditioner == FEM_PC_MG) accumulate_times(S);
-            rz = out[0];
-            if (!(rz > 0) || !std::isfinite(rz)) {
-                set_error("fem_solver_solve: preconditioner is not positive definite (r^T B r <= 0)");
-                return FEM_ERR_BREAKDOWN;
-            }
-            axpby_launch<double>(n, 1.0, z, 0.0, pp, S->s);
-        }
-        while (!converged && it < o.max_it) {
-            FEM_TRY(S->apply64(hi, pp, 1.0, nullptr, 0.0, q));   // q = A p
-            FEM_TRY(S->dots(1, n, pp, q, nullptr, nullptr, nullptr, nullptr, out));
-            const double pq = out[0];
-            if (!(pq > 0) || !std::isfinite(pq)) {
-                set_error("fem_solver_solve: CG breakdown (p^T A p <= 0 or not finite)");
-                return FEM_ERR_BREAKDOWN;
-            }
-            const double alpha = rz / pq;
-            cg_update_launch(n, alpha, pp, q, x, r, S->s);
-            ++it;
-            if (o.replace_every > 0 && it % o.replace_every == 0) FEM_TRY(S->apply64(hi, x, -1.0, b, 1.0, r));
-            FEM_TRY(S->dots(1, n, r, r, nullptr, nullptr, nullptr, nullptr, out));
-            rel = std::sqrt(out[0]) / nb;
-            record(it, rel);
-            if (!std::isfinite(rel)) {
-                set_error("fem_solver_solve: residual not finite");
-                return FEM_ERR_BREAKDOWN;
-            }
-            if (rel <= o.rtol) {
-                // confirm with the true residual; if it disagrees, continue from it
-                FEM_TRY(S->apply64(hi, x, -1.0, b, 1.0, q));
-                FEM_TRY(S->dots(1, n, q, q, nullptr, nullptr, nullptr, nullptr, out));
-                const double tr = std::sqrt(out[0]) / nb;
-                if (tr <= o.rtol) {
-                    converged = true;
-                    break;
-                }
-                axpby_launch<double>(n, 1.0, q, 0.0, r, S->s);
-            }
-            FEM_TRY(apply_preconditioner(S, r, z));
-            FEM_TRY(S->dots(2, n, r, z, q, z, nullptr, nullptr, out));
-            if (S->timing && S->o.preconditioner == FEM_PC_MG) accumulate_times(S);
-            const double rz_new = out[0], qz = out[1];
-            if (!(rz_new > 0) || !std::isfinite(rz_new)) {
-                set_error("fem_solver_solve: preconditioner is not positive definite (r^T B r <= 0)");
-                return FEM_ERR_BREAKDOWN;
-            }
-            const double beta = o.flexible ? (-alpha * qz / rz) : (rz_new / rz);
-            rz = rz_new;
-            axpby_launch<double>(n, 1.0, z, beta, pp, S->s);
-        }
-        // true residual at exit
-        FEM_TRY(S->apply64(hi, x, -1.0, b, 1.0, q));
-        FEM_TRY(S->dots(1, n, q, q, nullptr, nullptr, nullptr, nullptr, out));
-        rel_true = std::sqrt(out[0]) / nb;
-        if (!converged) status = FEM_WARN_NOT_CONVERGED;
+    double rel_true = 0.0;
+    bool conv = false;
+    const fem_status st = S->cg(b, x, it, rel_true, conv);
+    if (st) return st;
+    const hipError_t e = hipStreamSynchronize(S->s);
+    if (e != hipSuccess) {
+        set_error(std::string("fem_solver_solve: ") + hipGetErrorString(e));
+        return FEM_ERR_HIP;
     }
     const double t1 = now_ms();
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
         stats->iterations = it;
-        stats->coarse_iterations = 0;
+        stats->coarse_iterations = S->coarse_iters;
         stats->rel_residual_true = rel_true;
         stats->solve_ms = t1 - t0;
         stats->coarse_ms = S->coarse_ms;
@@ -720,9 +822,11 @@ fem_status fem_solver_solve(fem_solver* S, const double* b, double* x, fem_solve
             stats->lambda_max[l] = S->lmax.size() > (size_t)l ? S->lmax[l] : 0.0;
         }
     }
-    if (status == FEM_WARN_NOT_CONVERGED)
+    if (!conv) {
         set_error("fem_solver_solve: max_it reached before rtol (relative residual " + std::to_string(rel_true) + ")");
-    return status;
+        return FEM_WARN_NOT_CONVERGED;
+    }
+    return FEM_OK;
 }
 
 fem_status fem_mg_cg_solve(const fem_mesh* m, const double* k, const double* b, double* x, const fem_solve_opts* o,

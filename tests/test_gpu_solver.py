@@ -4,6 +4,9 @@
   Chebyshev smoother, transfers, rediscretised coefficient and exact coarse solve together.
 * Solutions to rtol 1e-10 against the oracle's reference solution (1e-8), FP64 and mixed.
 * Jacobi-CG on the P1 8^3 workload (iteration bound 60 for 1e-10).
+* Nested coarse solve (FP64 MG-PCG over the levels below the coarsest level used): one V-cycle
+  against the oracle's V-cycle on the truncated hierarchy (exact coarse solve) to 1e-9, and
+  solutions against the oracle's reference solution (1e-8), FP64 and mixed.
 * Failure handling: max_it reached, NaN right-hand side, negative coefficient, bad arguments.
 * Determinism and warm start.
 """
@@ -65,6 +68,61 @@ def test_solution_parity(n0, r, p, jit, kvar, prec):
     assert res.rel_residual_true <= 1e-10
     assert rel(u.cpu().numpy(), u_ref) <= 1e-8
     assert res.iterations <= 40
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("p,kvar", [(2, True), (1, False)])
+def test_nested_coarse_vcycle(p, kvar):
+    banner(f"nested vcycle p={p} kvar={kvar}")
+    from paper_2104_08012_amd import fem
+    mesh, levels = make_pair(2, 2, p, 0.1)
+    k = fem_inputs.k_exp_fourier(levels[-1].vert_xyz) if kvar else None
+    omg = solvers.MGHierarchy(levels[1:], k)      # exact solve on level 1
+    lm = [0.0, 0.0, omg.levels[1].lmax]
+    opts = fem.SolveOptions(lambda_max=lm, n_levels_used=2, coarse_method="nested", coarse_rtol=1e-13)
+    S = fem.Solver(mesh, opts).setup(_t(k) if kvar else None)
+    x = fem_inputs.uniform_vector(levels[-1].n_dofs, 0)
+    x[levels[-1].boundary] = 0
+    z = S.vcycle(_t(x))
+    torch.cuda.synchronize()
+    assert rel(z.cpu().numpy(), omg.vcycle(x)) <= 1e-9
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_nested_coarse_solution(prec):
+    banner(f"nested solve p=2 {prec}")
+    from paper_2104_08012_amd import fem
+    mesh, levels = make_pair(2, 2, 2, 0.1)
+    lev = levels[-1]
+    k = fem_inputs.k_exp_fourier(lev.vert_xyz)
+    A = assemble.apply_bc(assemble.stiffness(lev, k), lev.boundary)
+    b = _rhs(lev)
+    u_ref = solvers.direct_solve(A, b, rtol=1e-14)
+    opts = fem.SolveOptions(rtol=1e-10, precision=prec, n_levels_used=2, coarse_method="nested")
+    S = fem.Solver(mesh, opts).setup(_t(k))
+    u, res = S.solve(_t(b))
+    torch.cuda.synchronize()
+    assert res.rel_residual_true <= 1e-10
+    assert rel(u.cpu().numpy(), u_ref) <= 1e-8
+    assert res.coarse_iterations > 0
+    # the same system with the dense coarse inverse on level 1
+    Sd = fem.Solver(mesh, fem.SolveOptions(rtol=1e-10, precision=prec, n_levels_used=2,
+                                           coarse_method="dense")).setup(_t(k))
+    ud, resd = Sd.solve(_t(b))
+    torch.cuda.synchronize()
+    assert resd.coarse_iterations == 0
+    assert rel(u.cpu().numpy(), ud.cpu().numpy()) <= 1e-8
+
+
+@pytest.mark.gpu
+def test_nested_needs_a_lower_level():
+    banner("nested on level 0 rejected")
+    from paper_2104_08012_amd import fem
+    from paper_2104_08012_amd._lib import FemError
+    mesh, _ = make_pair(2, 1, 1, 0.0)
+    with pytest.raises(FemError):
+        fem.Solver(mesh, fem.SolveOptions(coarse_method="nested"))
 
 
 @pytest.mark.gpu

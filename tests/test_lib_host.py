@@ -72,3 +72,34 @@ def test_mesh_device_bytes_scale():
     C = 6 * 8 ** 3
     # map (10 int32), G (6 f64 + 6 f32) per cell at least
     assert b >= C * (10 * 4 + 6 * 12) and b % 256 == 0
+
+
+def test_solver_workspace_coarse_choices():
+    """Coarse-level choice: dense inverse up to 40000 interior dofs, nested MG-PCG above (or on
+    request), and an error where neither applies."""
+    import ctypes as C
+    from paper_2104_08012_amd import fem
+    from paper_2104_08012_amd import _lib as L
+    m = fem.Mesh(2, 4, 2, upload=False)        # P2 on 2^3 .. 32^3 cubes; 32^3 has 63^3 interior dofs
+
+    def ws(**kw):
+        o, keep, _ = fem.SolveOptions(**kw).to_c()
+        nb = C.c_size_t()
+        st = L.lib().fem_solve_workspace_bytes(m.handle, C.byref(o), C.byref(nb))
+        return st, nb.value
+
+    st_d, b_d = ws()                                            # dense on level 0 (27 interior)
+    assert st_d == 0 and b_d % 256 == 0
+    st, _ = ws(n_levels_used=1, coarse_method="dense")          # 250047 interior: too large
+    assert st == L.FEM_ERR_UNSUPPORTED
+    st_n, b_n = ws(n_levels_used=1)                             # auto -> nested over levels 0..4
+    assert st_n == 0
+    st_n2, b_n2 = ws(n_levels_used=1, coarse_method="nested")
+    assert st_n2 == 0 and b_n2 == b_n
+    # nested: the full hierarchy's vectors twice over at most, never a dense 250047^2 block
+    n4 = m.levels[4]["n_dofs"]
+    assert 4 * n4 * 8 < b_n < 64 * n4 * 8
+    st, _ = ws(coarse_method="nested")                          # nothing below level 0
+    assert st == L.FEM_ERR_UNSUPPORTED
+    st_m, b_m = ws(n_levels_used=2, precision="mixed")          # 16^3 coarse: dense, 31^3 dofs
+    assert st_m == 0 and b_m > 31 ** 6 * 8
