@@ -462,6 +462,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="p2-64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 512 MiB device-to-device copy first: a dispatch of known size that "
+                         "calibrates hardware byte counters in profiler runs of this command")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -471,6 +474,12 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 26, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = WORKLOADS[args.workload]
     run = {"solve": run_solve, "adjoint": run_adjoint, "jacobi": run_jacobi, "sweep": run_sweep}[w["kind"]]
     out = run(args, args.workload, w)

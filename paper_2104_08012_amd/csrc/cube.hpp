@@ -2,16 +2,21 @@
 //
 // Same result and the same deterministic two-kernel scheme as k_brick (brick workgroups, interior
 // points written directly, brick-face points through interface slots and k_fixup), organised to
-// cut instructions on gfx950's 64-wide VALU:
-//  * a thread gathers the cube's (p+1)^3 distinct dofs once (8 for P1, 27 for P2) instead of 6 nloc
-//    per-cell gathers, through the structure-of-arrays cell-to-dof map of the first cell that
-//    reaches each point;
+// cut memory traffic and instructions on gfx950's 64-wide VALU:
+//  * a thread gathers the cube's (p+1)^3 distinct dofs once (8 for P1, 27 for P2) through a per-cube
+//    structure-of-arrays dof map (entry j of every cube contiguous), instead of 6 nloc per-cell
+//    gathers;
+//  * the geometry is computed in the kernel from the FP64 coordinates of the cube's 8 vertices:
+//    for each tetrahedron the edge vectors e1, e2, e3 from its first vertex, the cofactor rows
+//    c1 = e2 x e3, c2 = e3 x e1, c3 = e1 x e2 (so that J^-1 has rows c_a / det), det = e1 . c1,
+//    and G = |det| J^-1 J^-T = [c_a . c_b] / |det|.  No per-cell geometric factors are read;
 //  * the six cells' contributions accumulate in registers at the cube's lattice points (the
 //    node-to-point map is a compile-time table);
 //  * quadrature tabulations are literals, so zero gradient entries generate no instructions;
-//  * cubes are summed into the brick's closure in LDS in 8 phases by cube parity (cubes of one
-//    parity share no point), a fixed order, so the result is reproducible;
-//  * loads use 32-bit offsets from uniform bases.
+//  * the cubes' point values go to LDS once; then each closure point of the brick sums the values
+//    of the (up to 8) cubes containing it in a fixed order (so the result is reproducible), with
+//    consecutive lanes on consecutive points along x, so the stores to y are contiguous runs;
+//  * loads use 32-bit offsets from uniform bases (the host keeps such levels below 4 GiB per array).
 #pragma once
 #include "scatter.hpp"
 #include "tabulate.hpp"
@@ -24,8 +29,22 @@ __device__ __forceinline__ T ldg(const T* base, uint32_t idx) {
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)(idx * (uint32_t)sizeof(T)));
 }
 
+// Contributions along one axis to closure coordinate l of a brick (lattice spacing h/P, cubes
+// 0..B-1): the cube with l / P and local index l % P, and, where l is a cube boundary above the
+// first, also the cube below with local index P.  off = local index * sj * B^3 + cube * sc is the
+// axis's share of the LDS offset (sj, sc: strides of the local point and cube indices).
+template <int P, int B>
+__device__ __forceinline__ void axis_terms(int l, int sj, int sc, int off[2], bool valid[2]) {
+    constexpr int NT = B * B * B;
+    const int c0 = l / P, a0 = l % P;
+    valid[0] = c0 < B;
+    off[0] = a0 * sj * NT + c0 * sc;
+    valid[1] = a0 == 0 && c0 > 0;
+    off[1] = P * sj * NT + (c0 - 1) * sc;
+}
+
 #ifndef FEM_CUBE_MIN_WAVES
-#define FEM_CUBE_MIN_WAVES 1
+#define FEM_CUBE_MIN_WAVES 2
 #endif
 template <int P, int B, bool KVAR, typename T>
 __global__ void __launch_bounds__(B * B * B, FEM_CUBE_MIN_WAVES) k_cube_apply(SArgs<T> a) {
@@ -33,47 +52,73 @@ __global__ void __launch_bounds__(B * B * B, FEM_CUBE_MIN_WAVES) k_cube_apply(SA
     constexpr int NT = B * B * B, PB = P * B, QS = PB + 1, Q = QS * QS * QS;
     constexpr StiffTab<P, KVAR> TB{};
     constexpr CubeNodes<P> CN{};
-    __shared__ T acc[Q];
+    __shared__ T part[NCP * NT];   // cube point j of cube c at part[j * NT + c]
     const int brick = brick_of_block(blockIdx.x, gridDim.x);
     const int nb = a.nb;
     const int bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
     const int cube = threadIdx.x;
     const int lx = cube % B, ly = (cube / B) % B, lz = cube / (B * B);
-    for (int q = threadIdx.x; q < Q; q += NT) acc[q] = T(0);
 
-    const uint32_t C = (uint32_t)a.C;
-    const uint32_t c0 = (uint32_t)(brick * 6 * NT + cube);    // cell of tetrahedron t: c0 + t * NT
+    const uint32_t NCB = a.ncube;
+    const uint32_t cid = (uint32_t)(brick * NT + cube);
     // gather the cube's distinct dofs
     T xs[NCP];
 #pragma unroll
     for (int j = 0; j < NCP; ++j) {
-        const int32_t m = ldg(a.map, (uint32_t)CN.first_i[j] * C + c0 + (uint32_t)(CN.first_t[j] * NT));
+        const int32_t m = ldg(a.cmap, (uint32_t)j * NCB + cid);
         const T v = ldg(a.x, (uint32_t)m & 0x7fffffffu);
         xs[j] = (a.mask_cols && m < 0) ? T(0) : v;
     }
+    // corner coordinates relative to corner 0 (corner j at offset (j & 1, j >> 1 & 1, j >> 2))
+    const uint32_t n1 = (uint32_t)a.n + 1, NV = a.nv;
+    const uint32_t v0 = (uint32_t)(bx * B + lx) + n1 * ((uint32_t)(by * B + ly) + n1 * (uint32_t)(bz * B + lz));
+    double D[8][3];
+    {
+        const double p0x = ldg(a.vxyz, v0), p0y = ldg(a.vxyz, NV + v0), p0z = ldg(a.vxyz, 2 * NV + v0);
+#pragma unroll
+        for (int j = 1; j < 8; ++j) {
+            const uint32_t v = v0 + (uint32_t)(j & 1) + n1 * ((uint32_t)((j >> 1) & 1) + n1 * (uint32_t)(j >> 2));
+            D[j][0] = ldg(a.vxyz, v) - p0x;
+            D[j][1] = ldg(a.vxyz, NV + v) - p0y;
+            D[j][2] = ldg(a.vxyz, 2 * NV + v) - p0z;
+        }
+    }
     T kc[8];
     if constexpr (KVAR) {
-        const int n1 = a.n + 1;
-        const int vx = bx * B + lx, vy = by * B + ly, vz = bz * B + lz;
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-            kc[j] = ldg(a.k, (uint32_t)((vx + (j & 1)) + n1 * ((vy + ((j >> 1) & 1)) + n1 * (vz + (j >> 2)))));
+            kc[j] = ldg(a.k, v0 + (uint32_t)(j & 1) + n1 * ((uint32_t)((j >> 1) & 1) + n1 * (uint32_t)(j >> 2)));
     }
     T ys[NCP];
 #pragma unroll
     for (int j = 0; j < NCP; ++j) ys[j] = T(0);
 #pragma unroll
     for (int t = 0; t < 6; ++t) {
-        const uint32_t c = c0 + (uint32_t)(t * NT);
-        const T g00 = ldg(a.G, c), g11 = ldg(a.G, C + c), g22 = ldg(a.G, 2 * C + c);
-        const T g01 = ldg(a.G, 3 * C + c), g02 = ldg(a.G, 4 * C + c), g12 = ldg(a.G, 5 * C + c);
+        // path tetrahedron: v0 = corner 0, v1 = e_s0, v2 = e_s0 + e_s1, v3 = corner 7
+        const int s0 = perm_axis(t, 0), s1 = perm_axis(t, 1);
+        const int j1 = 1 << s0, j2 = (1 << s0) | (1 << s1);
+        const double* e1 = D[j1];
+        const double* e2 = D[j2];
+        const double* e3 = D[7];
+        const double c1x = e2[1] * e3[2] - e2[2] * e3[1], c1y = e2[2] * e3[0] - e2[0] * e3[2],
+                     c1z = e2[0] * e3[1] - e2[1] * e3[0];
+        const double c2x = e3[1] * e1[2] - e3[2] * e1[1], c2y = e3[2] * e1[0] - e3[0] * e1[2],
+                     c2z = e3[0] * e1[1] - e3[1] * e1[0];
+        const double c3x = e1[1] * e2[2] - e1[2] * e2[1], c3y = e1[2] * e2[0] - e1[0] * e2[2],
+                     c3z = e1[0] * e2[1] - e1[1] * e2[0];
+        const double det = e1[0] * c1x + e1[1] * c1y + e1[2] * c1z;
+        const double inv = 1.0 / fabs(det);
+        const T g00 = T((c1x * c1x + c1y * c1y + c1z * c1z) * inv);
+        const T g11 = T((c2x * c2x + c2y * c2y + c2z * c2z) * inv);
+        const T g22 = T((c3x * c3x + c3y * c3y + c3z * c3z) * inv);
+        const T g01 = T((c1x * c2x + c1y * c2y + c1z * c2z) * inv);
+        const T g02 = T((c1x * c3x + c1y * c3y + c1z * c3z) * inv);
+        const T g12 = T((c2x * c3x + c2y * c3y + c2z * c3z) * inv);
         T kt[4];
         if constexpr (KVAR) {
-            // vertex v of the path tetrahedron at cube corner: v0 = 0, v1 = e_s0, v2 = e_s0 + e_s1, v3 = 7
-            const int s0 = perm_axis(t, 0), s1 = perm_axis(t, 1);
             kt[0] = kc[0];
-            kt[1] = kc[1 << s0];
-            kt[2] = kc[(1 << s0) | (1 << s1)];
+            kt[1] = kc[j1];
+            kt[2] = kc[j2];
             kt[3] = kc[7];
         }
 #pragma unroll
@@ -103,36 +148,33 @@ __global__ void __launch_bounds__(B * B * B, FEM_CUBE_MIN_WAVES) k_cube_apply(SA
             }
         }
     }
+#pragma unroll
+    for (int j = 0; j < NCP; ++j) part[j * NT + cube] = ys[j];
     __syncthreads();
-    // cubes of equal parity share no lattice point: add them into the closure phase by phase
-    const int par = (lx & 1) | ((ly & 1) << 1) | ((lz & 1) << 2);
-    const int base = (P * lx) + QS * ((P * ly) + QS * (P * lz));
-#pragma unroll
-    for (int ph = 0; ph < 8; ++ph) {
-        if (par == ph) {
-#pragma unroll
-            for (int j = 0; j < NCP; ++j) {
-                const int off = (j % PC) + QS * (((j / PC) % PC) + QS * (j / (PC * PC)));
-                acc[base + off] += ys[j];
-            }
-        }
-        __syncthreads();
-    }
-    // write the closure row by row (rows along x): interior points of interior rows go to y as
-    // a contiguous run, brick-face points to their interface slots
+    // closure points in x-fastest order, so that consecutive lanes write consecutive dofs: each
+    // point sums the values of the (up to 8) cubes that contain it in a fixed order, then goes to
+    // y if it lies strictly inside the brick, else to its interface slot
     const int64_t L = a.Lout;
-    for (int r = threadIdx.x; r < QS * QS; r += NT) {
-        const int lb = r % QS, lc = r / QS;
-        const T* row = &acc[QS * r];
-        if (lc == 0 || lc == PB || lb == 0 || lb == PB) {
+    for (int q = threadIdx.x; q < Q; q += NT) {
+        const int la = q % QS, lb = (q / QS) % QS, lc = q / (QS * QS);
+        int ox[2], oy[2], oz[2];
+        bool vx[2], vy[2], vz[2];
+        axis_terms<P, B>(la, 1, 1, ox, vx);
+        axis_terms<P, B>(lb, PC, B, oy, vy);
+        axis_terms<P, B>(lc, PC * PC, B * B, oz, vz);
+        T acc = T(0);
 #pragma unroll
-            for (int la = 0; la < QS; ++la) put_slot<PB, T>(a, bx, by, bz, la, lb, lc, row[la]);
+        for (int iz = 0; iz < 2; ++iz)
+#pragma unroll
+            for (int iy = 0; iy < 2; ++iy)
+#pragma unroll
+                for (int ix = 0; ix < 2; ++ix)
+                    if (vx[ix] && vy[iy] && vz[iz]) acc += part[ox[ix] + oy[iy] + oz[iz]];
+        if (la == 0 || la == PB || lb == 0 || lb == PB || lc == 0 || lc == PB) {
+            put_slot<PB, T>(a, bx, by, bz, la, lb, lc, acc);
         } else {
-            put_slot<PB, T>(a, bx, by, bz, 0, lb, lc, row[0]);
-            put_slot<PB, T>(a, bx, by, bz, PB, lb, lc, row[PB]);
-            const int64_t g0 = (bx * PB) + L * ((by * PB + lb) + L * (int64_t)(bz * PB + lc));
-#pragma unroll
-            for (int la = 1; la < PB; ++la) finalize(a, g0 + la, row[la], false);
+            const int64_t g = (bx * PB + la) + L * ((by * PB + lb) + L * (int64_t)(bz * PB + lc));
+            finalize(a, g, acc, false);
         }
     }
 }

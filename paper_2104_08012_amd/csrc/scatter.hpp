@@ -54,6 +54,9 @@ struct SArgs {
     T alpha, beta;
     int row_mode;                    // RowMode for boundary rows of the output
     const T* xid;                    // values of identity rows
+    const int32_t* cmap;             // cube kernel: SoA (p+1)^3 * ncube dofs of each cube, or null
+    const double* vxyz;              // cube kernel: vertex coordinates SoA x[nv], y[nv], z[nv]
+    uint32_t ncube, nv;
 };
 
 constexpr int brick_threads(int B) { return B == 4 ? 384 : 64; }
