@@ -43,6 +43,27 @@ __device__ __forceinline__ void axis_terms(int l, int sj, int sc, int off[2], bo
     off[1] = P * sj * NT + (c0 - 1) * sc;
 }
 
+// Sum over the cubes containing closure point (la, lb, lc): up to two terms per axis, in the
+// order (z, y, x) lower term first; absent terms read the zero entry at the end of part.
+template <int P, int B, typename T>
+__device__ __forceinline__ T closure_sum(const T* part, int la, int lb, int lc) {
+    constexpr int PC = P + 1, NT = B * B * B, ZERO = PC * PC * PC * NT;
+    int ox[2], oy[2], oz[2];
+    bool vx[2], vy[2], vz[2];
+    axis_terms<P, B>(la, 1, 1, ox, vx);
+    axis_terms<P, B>(lb, PC, B, oy, vy);
+    axis_terms<P, B>(lc, PC * PC, B * B, oz, vz);
+    T acc = T(0);
+#pragma unroll
+    for (int iz = 0; iz < 2; ++iz)
+#pragma unroll
+        for (int iy = 0; iy < 2; ++iy)
+#pragma unroll
+            for (int ix = 0; ix < 2; ++ix)
+                acc += part[(vx[ix] && vy[iy] && vz[iz]) ? ox[ix] + oy[iy] + oz[iz] : ZERO];
+    return acc;
+}
+
 #ifndef FEM_CUBE_MIN_WAVES
 #define FEM_CUBE_MIN_WAVES 2
 #endif
@@ -52,7 +73,7 @@ __global__ void __launch_bounds__(B * B * B, FEM_CUBE_MIN_WAVES) k_cube_apply(SA
     constexpr int NT = B * B * B, PB = P * B, QS = PB + 1, Q = QS * QS * QS;
     constexpr StiffTab<P, KVAR> TB{};
     constexpr CubeNodes<P> CN{};
-    __shared__ T part[NCP * NT];   // cube point j of cube c at part[j * NT + c]
+    __shared__ T part[NCP * NT + 1];   // cube point j of cube c at part[j * NT + c]; last: zero
     const int brick = brick_of_block(blockIdx.x, gridDim.x);
     const int nb = a.nb;
     const int bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
@@ -107,7 +128,8 @@ __global__ void __launch_bounds__(B * B * B, FEM_CUBE_MIN_WAVES) k_cube_apply(SA
         const double c3x = e1[1] * e2[2] - e1[2] * e2[1], c3y = e1[2] * e2[0] - e1[0] * e2[2],
                      c3z = e1[0] * e2[1] - e1[1] * e2[0];
         const double det = e1[0] * c1x + e1[1] * c1y + e1[2] * c1z;
-        const double inv = 1.0 / fabs(det);
+        constexpr double kScale = (P == 2 && !KVAR) ? 1.0 / 120.0 : 1.0;   // P1 mass factor, vertex form
+        const double inv = kScale / fabs(det);
         const T g00 = T((c1x * c1x + c1y * c1y + c1z * c1z) * inv);
         const T g11 = T((c2x * c2x + c2y * c2y + c2z * c2z) * inv);
         const T g22 = T((c3x * c3x + c3y * c3y + c3z * c3z) * inv);
@@ -121,61 +143,109 @@ __global__ void __launch_bounds__(B * B * B, FEM_CUBE_MIN_WAVES) k_cube_apply(SA
             kt[2] = kc[j2];
             kt[3] = kc[7];
         }
+        if constexpr (P == 2 && !KVAR) {
+            // reference gradient at the vertices, w_v = G g_v, mixed by the P1 mass matrix
+            // (the factor 1/120 is in G), then the transposed product
+            constexpr VertexGrad<P> VG{};
+            T hx[4], hy[4], hz[4];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            T gx = T(0), gy = T(0), gz = T(0);
+            for (int v = 0; v < 4; ++v) {
+                T gx = T(0), gy = T(0), gz = T(0);
 #pragma unroll
-            for (int i = 0; i < NL; ++i) {
-                const T xv = xs[CN.cp[t][i]];
-                if (TB.D[q][0][i] != 0.0) gx += T(TB.D[q][0][i]) * xv;
-                if (TB.D[q][1][i] != 0.0) gy += T(TB.D[q][1][i]) * xv;
-                if (TB.D[q][2][i] != 0.0) gz += T(TB.D[q][2][i]) * xv;
+                for (int i = 0; i < NL; ++i) {
+                    const T xv = xs[CN.cp[t][i]];
+                    if (VG.D[v][0][i] != 0.0) gx += T(VG.D[v][0][i]) * xv;
+                    if (VG.D[v][1][i] != 0.0) gy += T(VG.D[v][1][i]) * xv;
+                    if (VG.D[v][2][i] != 0.0) gz += T(VG.D[v][2][i]) * xv;
+                }
+                hx[v] = g00 * gx + g01 * gy + g02 * gz;
+                hy[v] = g01 * gx + g11 * gy + g12 * gz;
+                hz[v] = g02 * gx + g12 * gy + g22 * gz;
             }
-            T s = T(TB.w[q]);
-            if constexpr (KVAR)
-                s *= T(TB.lam[q][0]) * kt[0] + T(TB.lam[q][1]) * kt[1] + T(TB.lam[q][2]) * kt[2] +
-                     T(TB.lam[q][3]) * kt[3];
-            const T wx = s * (g00 * gx + g01 * gy + g02 * gz);
-            const T wy = s * (g01 * gx + g11 * gy + g12 * gz);
-            const T wz = s * (g02 * gx + g12 * gy + g22 * gz);
+            const T sx = hx[0] + hx[1] + hx[2] + hx[3], sy = hy[0] + hy[1] + hy[2] + hy[3],
+                    sz = hz[0] + hz[1] + hz[2] + hz[3];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                hx[v] += sx;
+                hy[v] += sy;
+                hz[v] += sz;
+            }
 #pragma unroll
             for (int i = 0; i < NL; ++i) {
                 T acc_i = ys[CN.cp[t][i]];
-                if (TB.D[q][0][i] != 0.0) acc_i += T(TB.D[q][0][i]) * wx;
-                if (TB.D[q][1][i] != 0.0) acc_i += T(TB.D[q][1][i]) * wy;
-                if (TB.D[q][2][i] != 0.0) acc_i += T(TB.D[q][2][i]) * wz;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    if (VG.D[v][0][i] != 0.0) acc_i += T(VG.D[v][0][i]) * hx[v];
+                    if (VG.D[v][1][i] != 0.0) acc_i += T(VG.D[v][1][i]) * hy[v];
+                    if (VG.D[v][2][i] != 0.0) acc_i += T(VG.D[v][2][i]) * hz[v];
+                }
                 ys[CN.cp[t][i]] = acc_i;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                T gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll
+                for (int i = 0; i < NL; ++i) {
+                    const T xv = xs[CN.cp[t][i]];
+                    if (TB.D[q][0][i] != 0.0) gx += T(TB.D[q][0][i]) * xv;
+                    if (TB.D[q][1][i] != 0.0) gy += T(TB.D[q][1][i]) * xv;
+                    if (TB.D[q][2][i] != 0.0) gz += T(TB.D[q][2][i]) * xv;
+                }
+                T s = T(TB.w[q]);
+                if constexpr (KVAR)
+                    s *= T(TB.lam[q][0]) * kt[0] + T(TB.lam[q][1]) * kt[1] + T(TB.lam[q][2]) * kt[2] +
+                         T(TB.lam[q][3]) * kt[3];
+                const T wx = s * (g00 * gx + g01 * gy + g02 * gz);
+                const T wy = s * (g01 * gx + g11 * gy + g12 * gz);
+                const T wz = s * (g02 * gx + g12 * gy + g22 * gz);
+#pragma unroll
+                for (int i = 0; i < NL; ++i) {
+                    T acc_i = ys[CN.cp[t][i]];
+                    if (TB.D[q][0][i] != 0.0) acc_i += T(TB.D[q][0][i]) * wx;
+                    if (TB.D[q][1][i] != 0.0) acc_i += T(TB.D[q][1][i]) * wy;
+                    if (TB.D[q][2][i] != 0.0) acc_i += T(TB.D[q][2][i]) * wz;
+                    ys[CN.cp[t][i]] = acc_i;
+                }
             }
         }
     }
 #pragma unroll
     for (int j = 0; j < NCP; ++j) part[j * NT + cube] = ys[j];
+    if (cube == 0) part[NCP * NT] = T(0);
     __syncthreads();
-    // closure points in x-fastest order, so that consecutive lanes write consecutive dofs: each
-    // point sums the values of the (up to 8) cubes that contain it in a fixed order, then goes to
-    // y if it lies strictly inside the brick, else to its interface slot
+    // Closure points of the brick, each the sum of the values of the (up to 8) cubes containing it
+    // in a fixed order (absent terms read a zero entry, so the sum is branch-free).  Interior
+    // points first, x fastest, so consecutive lanes store consecutive dofs of y; then the points
+    // on the brick's faces, which go to their interface slots.
     const int64_t L = a.Lout;
-    for (int q = threadIdx.x; q < Q; q += NT) {
-        const int la = q % QS, lb = (q / QS) % QS, lc = q / (QS * QS);
-        int ox[2], oy[2], oz[2];
-        bool vx[2], vy[2], vz[2];
-        axis_terms<P, B>(la, 1, 1, ox, vx);
-        axis_terms<P, B>(lb, PC, B, oy, vy);
-        axis_terms<P, B>(lc, PC * PC, B * B, oz, vz);
-        T acc = T(0);
-#pragma unroll
-        for (int iz = 0; iz < 2; ++iz)
-#pragma unroll
-            for (int iy = 0; iy < 2; ++iy)
-#pragma unroll
-                for (int ix = 0; ix < 2; ++ix)
-                    if (vx[ix] && vy[iy] && vz[iz]) acc += part[ox[ix] + oy[iy] + oz[iz]];
-        if (la == 0 || la == PB || lb == 0 || lb == PB || lc == 0 || lc == PB) {
-            put_slot<PB, T>(a, bx, by, bz, la, lb, lc, acc);
-        } else {
-            const int64_t g = (bx * PB + la) + L * ((by * PB + lb) + L * (int64_t)(bz * PB + lc));
-            finalize(a, g, acc, false);
+    constexpr int QI = PB - 1, NIN = QI * QI * QI;
+    for (int r = threadIdx.x; r < NIN; r += NT) {
+        const int la = 1 + r % QI, lb = 1 + (r / QI) % QI, lc = 1 + r / (QI * QI);
+        const T v = closure_sum<P, B>(part, la, lb, lc);
+        const int64_t g = (bx * PB + la) + L * ((by * PB + lb) + L * (int64_t)(bz * PB + lc));
+        finalize(a, g, v, false);
+    }
+    constexpr int NZF = 2 * QS * QS, NYF = 2 * QS * QI, NXF = 2 * QI * QI;
+    for (int r = threadIdx.x; r < NZF + NYF + NXF; r += NT) {
+        int la, lb, lc;
+        if (r < NZF) {                       // z faces: all (la, lb)
+            const int u = r % (QS * QS);
+            la = u % QS;
+            lb = u / QS;
+            lc = r < QS * QS ? 0 : PB;
+        } else if (r < NZF + NYF) {          // y faces: all la, lc inside
+            const int u = (r - NZF) % (QS * QI);
+            la = u % QS;
+            lc = 1 + u / QS;
+            lb = r - NZF < QS * QI ? 0 : PB;
+        } else {                             // x faces: lb, lc inside
+            const int u = (r - NZF - NYF) % (QI * QI);
+            lb = 1 + u % QI;
+            lc = 1 + u / QI;
+            la = r - NZF - NYF < QI * QI ? 0 : PB;
         }
+        put_slot<PB, T>(a, bx, by, bz, la, lb, lc, closure_sum<P, B>(part, la, lb, lc));
     }
 }
 

@@ -133,6 +133,43 @@ struct StiffTab {
     }
 };
 
+// Reference gradients of the basis at the four vertices, D[v][d][i] = d phi_i / d xi_d at vertex v.
+// With k = 1 and an affine cell, grad u is linear for P2 (degree p - 1 in general), so
+// int_K G grad(u) . grad(phi_j) = sum_v,v' M1[v][v'] (G g_v) . D[v'][.][j] with g_v the reference
+// gradient at vertex v and M1 the reference P1 mass matrix (1 + delta_vv') / 120: exact, and sparser
+// than interior quadrature because most basis gradients vanish at the vertices.
+template <int P>
+struct VertexGrad {
+    static constexpr int NL = nloc_of(P);
+    double D[4][3][NL];
+    constexpr VertexGrad() : D{} {
+        const NodeList<P> nodes{};
+        const double dl[4][3] = {{-1, -1, -1}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+        for (int v = 0; v < 4; ++v)
+            for (int i = 0; i < NL; ++i) {
+                double lam[4] = {0, 0, 0, 0};
+                lam[v] = 1.0;
+                double f[4] = {1, 1, 1, 1}, df[4] = {0, 0, 0, 0};
+                for (int k = 0; k < 4; ++k)
+                    for (int s = 0; s < nodes.m[i][k]; ++s) {
+                        const double a = (P * lam[k] - s) / (s + 1.0), da = P / (s + 1.0);
+                        df[k] = df[k] * a + f[k] * da;
+                        f[k] *= a;
+                    }
+                for (int d = 0; d < 3; ++d) {
+                    double g = 0.0;
+                    for (int k = 0; k < 4; ++k) {
+                        double prod = df[k];
+                        for (int j = 0; j < 4; ++j)
+                            if (j != k) prod *= f[j];
+                        g += prod * dl[k][d];
+                    }
+                    D[v][d][i] = g;
+                }
+            }
+    }
+};
+
 // Local node i of the path tetrahedron t sits at cube-lattice point (pa, pb, pc) in [0, P]^3;
 // each cube point is listed with the first (t, i) that reaches it.
 template <int P>
