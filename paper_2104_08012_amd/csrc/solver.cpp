@@ -11,8 +11,9 @@
 //     its transpose with boundary rows zeroed; level operators are rediscretised with the
 //     coefficient injected at the coarse vertices.
 //   * Coarsest level used: exact FP64 solve with the dense inverse of the interior block,
-//     assembled by probing the matrix-free operator with (2p+1)^3 colour vectors and inverted by a
-//     blocked Gauss-Jordan sweep.  When that level is too large for a dense inverse it is solved
+//     assembled by probing the matrix-free operator with (2p+1)^3 colour vectors, inverted by a
+//     blocked Gauss-Jordan sweep and kept as the packed lower tiles of its symmetric part (half the
+//     bytes read per coarse solve).  When that level is too large for a dense inverse it is solved
 //     by a nested FP64 MG-PCG over the levels below it, to a relative residual of coarse_rtol
 //     (deepening the hierarchy under an expensive coarse level, as the paper does in Section 4).
 //   * Outer CG in FP64: x0 given (usually 0), stop when the true residual satisfies
@@ -37,6 +38,7 @@ using namespace fem;
 namespace {
 
 constexpr int64_t kDenseMax = 40000;   // interior dofs of a level inverted densely
+constexpr int64_t kInnerDense = 8000;  // nested solve: its dense level, the finest at most this size
 
 struct LevelWs {
     size_t x = 0, b = 0, r = 0, d = 0, dinv = 0, k64 = 0, k32 = 0, b64 = 0, x64 = 0;
@@ -45,6 +47,7 @@ struct LevelWs {
 struct Layout {
     std::vector<LevelWs> lev;
     size_t cg_r = 0, cg_z = 0, cg_p = 0, cg_q = 0, partial = 0, scal = 0, dense = 0, dense_xc = 0, jac_diag = 0;
+    size_t dense_packed = 0, dense_part = 0;
     size_t inner = 0, inner_bytes = 0;
     size_t total = 0;
     int top = 0, lo = 0, hi = 0, mixed = 0, nested = 0;
@@ -56,13 +59,23 @@ int64_t interior_dofs(const fem_mesh& m, int l) {
     return M * M * M;
 }
 
-// Options of the nested coarse solver: FP64 MG-PCG over all levels below, to coarse_rtol.
-fem_solve_opts inner_opts(const fem_solve_opts& o) {
+int64_t interior_dofs(const fem_mesh& m, int l);
+
+// Options of the nested coarse solver on levels 0..top: FP64 MG-PCG to coarse_rtol whose cycle
+// stops at the finest level with at most kInnerDense interior dofs (solved with its dense inverse;
+// a small dense solve is cheaper than the launch-bound smoothing of the levels below it).
+fem_solve_opts inner_opts(const fem_mesh& m, const fem_solve_opts& o, int top) {
     fem_solve_opts in = o;
     in.rtol = o.coarse_rtol;
     in.max_it = 200;
     in.precision = FEM_PREC_FP64;
-    in.n_levels_used = 0;
+    int lo = 0;
+    for (int l = top - 1; l >= 0; --l)
+        if (interior_dofs(m, l) <= kInnerDense) {
+            lo = l;
+            break;
+        }
+    in.n_levels_used = top - lo + 1;
     in.coarse_method = FEM_COARSE_AUTO;
     in.replace_every = 0;
     in.flexible = 0;
@@ -137,7 +150,7 @@ fem_status make_layout(const fem_mesh& m, const fem_solve_opts& o, int top, Layo
     L.nested = want_nested ? 1 : 0;
     if (L.nested) {
         Layout in;
-        const fem_status st = make_layout(m, inner_opts(o), L.lo, in);
+        const fem_status st = make_layout(m, inner_opts(m, o, L.lo), L.lo, in);
         if (st) return st;
         L.inner = take(in.total);
         L.inner_bytes = in.total;
@@ -145,6 +158,8 @@ fem_status make_layout(const fem_mesh& m, const fem_solve_opts& o, int top, Layo
         L.dense_n = nI;
         L.dense = take((size_t)nI * nI * 8);
         L.dense_xc = take(std::max<int64_t>(nI, 1) * 8);
+        L.dense_packed = take(sym_packed_doubles(nI) * 8);
+        L.dense_part = take(sym_partial_doubles(nI) * 8);
     }
     L.total = off;
     return FEM_OK;
@@ -302,7 +317,7 @@ fem_status fem_solver::init(const fem_mesh* mesh, const fem_solve_opts& opts, in
     level_ms.assign(nl, 0.0);
     if (L.nested) {
         inner.reset(new fem_solver());
-        FEM_TRY(inner->init(m, inner_opts(o), L.lo, ws + L.inner, L.inner_bytes));
+        FEM_TRY(inner->init(m, inner_opts(*m, o, L.lo), L.lo, ws + L.inner, L.inner_bytes));
         inner->timing = false;
     }
     return FEM_OK;
@@ -344,7 +359,7 @@ fem_status fem_solver::coarse_solve(const double* b64, double* x64) {
         return FEM_OK;
     }
     const HostLevel& C = m->lev[L.lo];
-    dense_solve_launch(C.L, p<double>(L.dense), b64, p<double>(L.dense_xc), x64, s);
+    sym_solve_launch(C.L, p<double>(L.dense_packed), b64, p<double>(L.dense_xc), p<double>(L.dense_part), x64, s);
     return check_launch("coarse solve");
 }
 
@@ -531,6 +546,7 @@ fem_status fem_solver::setup(const double* k_top) {
                         probe_extract_launch(C.L, P, S, c0, c1, c2, y, A, s);
                     }
             FEM_TRY(dense_invert(nd, A, nullptr, s));
+            sym_pack_launch(nd, A, p<double>(L.dense_packed), s);
         }
     }
     const hipError_t e = hipStreamSynchronize(s);

@@ -280,29 +280,93 @@ __global__ void __launch_bounds__(256) k_gemm(int64_t M, int64_t N, int K, doubl
     }
 }
 
-// y_lattice = Ainv * x_interior: one workgroup per row, fixed-order reduction.  The input is
-// read from the level vector at the interior lattice points; the output is written to the
-// level vector (boundary entries set to zero by k_zero_boundary).
-__global__ void __launch_bounds__(256) k_dense_gemv(int L, const double* __restrict__ Ainv, const double* __restrict__ xc,
-                                                    double* __restrict__ yl, const double* __restrict__ xl) {
-    const int M = L - 2;
-    const int64_t m = (int64_t)M * M * M;
-    const int64_t row = blockIdx.x;
-    __shared__ double sh[256];
-    double acc = 0.0;
-    const double* a = Ainv + row * m;
-    for (int64_t j = threadIdx.x; j < m; j += 256) acc += a[j] * xc[j];
-    sh[threadIdx.x] = acc;
+// Symmetric coarse inverse in packed lower tiles: tile (I, J), I >= J, of 64 x 64 entries
+// (row-major inside the tile, zero beyond n) at offset (I (I + 1) / 2 + J) * 4096.
+constexpr int ST = 64;
+
+__device__ __forceinline__ void tile_of(int64_t t, int& I, int& J) {
+    int i = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(i + 1) * (i + 2) / 2 <= t) ++i;
+    while ((int64_t)i * (i + 1) / 2 > t) --i;
+    I = i;
+    J = (int)(t - (int64_t)i * (i + 1) / 2);
+}
+
+// Ap tile (I, J) = (A_IJ + A_JI^T) / 2: the symmetric part of the computed inverse.
+__global__ void __launch_bounds__(256) k_sym_pack(int64_t n, const double* __restrict__ A, double* __restrict__ Ap) {
+    int I, J;
+    tile_of(blockIdx.x, I, J);
+    double* out = Ap + (int64_t)blockIdx.x * ST * ST;
+    for (int e = threadIdx.x; e < ST * ST; e += 256) {
+        const int64_t i = (int64_t)I * ST + e / ST, j = (int64_t)J * ST + e % ST;
+        out[e] = (i < n && j < n) ? 0.5 * (A[i * n + j] + A[j * n + i]) : 0.0;
+    }
+}
+
+// Per tile t = (I, J): prow[t] = A_IJ x_J and, off the diagonal, pcol[t] = A_IJ^T x_I
+// (64 entries each).  The tile is staged in LDS; thread (e, q) of the 256 sums a quarter
+// (16 terms, fixed order) of row e and of column e, and the quarters are added in order q = 0..3.
+__global__ void __launch_bounds__(256) k_sym_tiles(int64_t n, const double* __restrict__ Ap,
+                                                   const double* __restrict__ xc, double* __restrict__ prow,
+                                                   double* __restrict__ pcol) {
+    __shared__ double sa[ST][ST + 1];
+    __shared__ double sx[2][ST];
+    __shared__ double sq[2][4][ST];
+    int I, J;
+    tile_of(blockIdx.x, I, J);
+    const double2* tile = reinterpret_cast<const double2*>(Ap + (int64_t)blockIdx.x * ST * ST);
+    for (int e = threadIdx.x; e < ST * ST / 2; e += 256) {
+        const double2 v = tile[e];
+        const int r = (2 * e) / ST, c = (2 * e) % ST;
+        sa[r][c] = v.x;
+        sa[r][c + 1] = v.y;
+    }
+    if (threadIdx.x < ST) {
+        const int64_t jj = (int64_t)J * ST + threadIdx.x, ii = (int64_t)I * ST + threadIdx.x;
+        sx[0][threadIdx.x] = jj < n ? xc[jj] : 0.0;
+        sx[1][threadIdx.x] = ii < n ? xc[ii] : 0.0;
+    }
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
+    const int e = threadIdx.x % ST, q = threadIdx.x / ST;
+    double ar = 0.0, ac = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int c = q * 16 + k;
+        ar += sa[e][c] * sx[0][c];
+        ac += sa[c][e] * sx[1][c];
     }
-    if (threadIdx.x == 0) {
-        const int I = (int)(row % M) + 1, J = (int)((row / M) % M) + 1, K = (int)(row / ((int64_t)M * M)) + 1;
-        yl[I + (int64_t)L * (J + (int64_t)L * K)] = sh[0];
+    sq[0][q][e] = ar;
+    sq[1][q][e] = ac;
+    __syncthreads();
+    if (q == 0) {
+        prow[(int64_t)blockIdx.x * ST + e] = ((sq[0][0][e] + sq[0][1][e]) + sq[0][2][e]) + sq[0][3][e];
+    } else if (q == 1 && I != J) {
+        pcol[(int64_t)blockIdx.x * ST + e] = ((sq[1][0][e] + sq[1][1][e]) + sq[1][2][e]) + sq[1][3][e];
     }
-    (void)xl;
+}
+
+// y at the interior lattice points of row block I: the terms A_IJ x_J, from prow (J <= I) or
+// pcol of tile (J, I) (J > I), summed by four groups of 64 threads over J = g, g + 4, ... and the
+// four group sums added in group order (a fixed order).
+__global__ void __launch_bounds__(4 * ST) k_sym_reduce(int L, int64_t n, int nt, const double* __restrict__ prow,
+                                                       const double* __restrict__ pcol, double* __restrict__ yl) {
+    __shared__ double sg[4][ST];
+    const int I = blockIdx.x, r = threadIdx.x % ST, g = threadIdx.x / ST;
+    double acc = 0.0;
+#pragma unroll 4
+    for (int J = g; J < nt; J += 4) {
+        const double* src = J <= I ? prow + ((int64_t)I * (I + 1) / 2 + J) * ST : pcol + ((int64_t)J * (J + 1) / 2 + I) * ST;
+        acc += src[r];
+    }
+    sg[g][r] = acc;
+    __syncthreads();
+    if (g != 0) return;
+    acc = ((sg[0][r] + sg[1][r]) + sg[2][r]) + sg[3][r];
+    const int64_t row = (int64_t)I * ST + r;
+    if (row >= n) return;
+    const int M = L - 2;
+    const int i = (int)(row % M) + 1, j = (int)((row / M) % M) + 1, k = (int)(row / ((int64_t)M * M)) + 1;
+    yl[i + (int64_t)L * (j + (int64_t)L * k)] = acc;
 }
 
 // gather interior entries of a lattice vector into a compact vector
@@ -445,12 +509,29 @@ fem_status dense_invert(int64_t n, double* A, double* tmp, hipStream_t s) {
     return check_launch("dense inversion");
 }
 
-void dense_solve_launch(int L, const double* Ainv, const double* xl, double* xc, double* yl, hipStream_t s) {
-    const int64_t M = L - 2, m = M * M * M;
+int64_t sym_tiles(int64_t n) {
+    const int64_t nt = (n + ST - 1) / ST;
+    return nt * (nt + 1) / 2;
+}
+size_t sym_packed_doubles(int64_t n) { return (size_t)sym_tiles(n) * ST * ST; }
+size_t sym_partial_doubles(int64_t n) { return (size_t)2 * sym_tiles(n) * ST; }
+
+void sym_pack_launch(int64_t n, const double* A, double* Ap, hipStream_t s) {
+    hipLaunchKernelGGL(k_sym_pack, dim3((unsigned)sym_tiles(n)), dim3(256), 0, s, n, A, Ap);
+}
+
+void sym_solve_launch(int L, const double* Ap, const double* xl, double* xc, double* part, double* yl,
+                      hipStream_t s) {
+    const int64_t M = L - 2, m = M * M * M, ntl = sym_tiles(m);
+    const int nt = (int)((m + ST - 1) / ST);
     hipLaunchKernelGGL(k_gather_interior, dim3(grid_for(m)), dim3(VT), 0, s, L, xl, xc);
     const int64_t N = (int64_t)L * L * L;
     hipLaunchKernelGGL((k_zero_boundary<double>), dim3(grid_for(N)), dim3(VT), 0, s, L, yl);
-    hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)m), dim3(256), 0, s, L, Ainv, xc, yl, xl);
+    double* prow = part;
+    double* pcol = part + ntl * ST;
+    hipLaunchKernelGGL(k_sym_tiles, dim3((unsigned)ntl), dim3(256), 0, s, m, Ap, (const double*)xc, prow, pcol);
+    hipLaunchKernelGGL(k_sym_reduce, dim3((unsigned)nt), dim3(4 * ST), 0, s, L, m, nt, (const double*)prow,
+                       (const double*)pcol, yl);
 }
 
 template <typename T>

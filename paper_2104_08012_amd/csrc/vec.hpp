@@ -43,7 +43,14 @@ void random_launch(int64_t n, int L, uint64_t seed, double* v, hipStream_t s);
 void probe_fill_launch(int L, int S, int c0, int c1, int c2, double* v, hipStream_t s);
 void probe_extract_launch(int L, int p, int S, int c0, int c1, int c2, const double* y, double* A, hipStream_t s);
 fem_status dense_invert(int64_t n, double* A, double* tmp, hipStream_t s);
-void dense_solve_launch(int L, const double* Ainv, const double* xl, double* xc, double* yl, hipStream_t s);
+// Coarse inverse kept as the packed lower 64 x 64 tiles of its symmetric part; the solve reads
+// each stored tile once (y_I += A_IJ x_J and y_J += A_IJ^T x_I through per-tile partials summed in
+// a fixed order).  yl: lattice vector, boundary entries set to zero.
+size_t sym_packed_doubles(int64_t n);
+size_t sym_partial_doubles(int64_t n);
+void sym_pack_launch(int64_t n, const double* A, double* Ap, hipStream_t s);
+void sym_solve_launch(int L, const double* Ap, const double* xl, double* xc, double* part, double* yl,
+                      hipStream_t s);
 template <typename T>
 void zero_boundary_launch(int L, T* y, hipStream_t s);
 

@@ -96,9 +96,10 @@ def test_solver_workspace_coarse_choices():
     assert st_n == 0
     st_n2, b_n2 = ws(n_levels_used=1, coarse_method="nested")
     assert st_n2 == 0 and b_n2 == b_n
-    # nested: the full hierarchy's vectors twice over at most, never a dense 250047^2 block
+    # nested: vectors of the levels plus the dense inverse of the 8^3 level (3375 interior dofs,
+    # the finest level with at most 8000), never a dense 250047^2 block
     n4 = m.levels[4]["n_dofs"]
-    assert 4 * n4 * 8 < b_n < 64 * n4 * 8
+    assert 4 * n4 * 8 + 3375 ** 2 * 8 < b_n < 64 * n4 * 8 + 3 * 3375 ** 2 * 8
     st, _ = ws(coarse_method="nested")                          # nothing below level 0
     assert st == L.FEM_ERR_UNSUPPORTED
     st_m, b_m = ws(n_levels_used=2, precision="mixed")          # 16^3 coarse: dense, 31^3 dofs
