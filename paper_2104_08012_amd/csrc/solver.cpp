@@ -231,7 +231,12 @@ struct fem_solver {
     double coarse_ms = 0.0;
     std::vector<double> level_ms;
     int coarse_iters = 0;
-    std::vector<hipEvent_t> ev;   // per level: pre start/end, post start/end; coarse start/end
+    // two sets (alternate iterations) of per-level events: pre start/end, post start/end; coarse
+    // start/end; then the event marking each iteration's residual copy
+    std::vector<hipEvent_t> ev;
+    int evset = 0;
+    int ev_per_set() const { return 4 * m->nlev + 2; }
+    hipEvent_t* evs(int set) { return &ev[(size_t)set * ev_per_set()]; }
     bool timing = true;
     std::unique_ptr<fem_solver> inner;   // nested coarse solver over levels 0..L.lo
 
@@ -288,7 +293,7 @@ struct fem_solver {
     fem_status lanczos(int l, double& lm);
     fem_status precondition(const double* r, double* z);
     fem_status cg(const double* b, double* x, int& iters, double& rel_true, bool& converged);
-    void accumulate_times();
+    void accumulate_times(int set);
 };
 
 fem_status fem_solver::init(const fem_mesh* mesh, const fem_solve_opts& opts, int top, char* wsp, size_t bytes) {
@@ -307,7 +312,7 @@ fem_status fem_solver::init(const fem_mesh* mesh, const fem_solve_opts& opts, in
         return FEM_ERR_HIP;
     }
     const int nl = m->nlev;
-    ev.assign(4 * nl + 2, nullptr);
+    ev.assign(2 * (4 * nl + 2) + 1, nullptr);
     for (auto& e : ev)
         if (hipEventCreate(&e) != hipSuccess) {
             e = nullptr;
@@ -366,9 +371,10 @@ fem_status fem_solver::coarse_solve(const double* b64, double* x64) {
 template <typename T>
 fem_status fem_solver::vcycle(int l, const T* b, T* x) {
     const int nl = (int)m->lev.size();
-    hipEvent_t* e = timing ? &ev[4 * l] : nullptr;
+    hipEvent_t* ev0 = evs(evset);
+    hipEvent_t* e = timing ? &ev0[4 * l] : nullptr;
     if (l == L.lo) {
-        if (timing) ignore(hipEventRecord(ev[4 * nl], s));
+        if (timing) ignore(hipEventRecord(ev0[4 * nl], s));
         if (L.mixed) {
             const int64_t n = m->lev[l].N;
             cast_launch<T, double>(n, b, p<double>(L.lev[l].b64), s);
@@ -377,7 +383,7 @@ fem_status fem_solver::vcycle(int l, const T* b, T* x) {
         } else {
             FEM_TRY(coarse_solve(reinterpret_cast<const double*>(b), reinterpret_cast<double*>(x)));
         }
-        if (timing) ignore(hipEventRecord(ev[4 * nl + 1], s));
+        if (timing) ignore(hipEventRecord(ev0[4 * nl + 1], s));
         return FEM_OK;
     }
     const HostLevel& H = m->lev[l];
@@ -559,18 +565,18 @@ fem_status fem_solver::setup(const double* k_top) {
     return FEM_OK;
 }
 
-// Adds the V-cycle's per-level times of the last preconditioner application (events recorded on
-// the stream; called after a host synchronisation).
-void fem_solver::accumulate_times() {
+// Adds the per-level times of a completed V-cycle whose events are in the given set.
+void fem_solver::accumulate_times(int set) {
     const int nl = m->nlev;
+    hipEvent_t* e = evs(set);
     for (int l = L.lo + 1; l <= L.hi; ++l) {
         float a = 0.f, b = 0.f;
-        if (hipEventElapsedTime(&a, ev[4 * l], ev[4 * l + 1]) == hipSuccess &&
-            hipEventElapsedTime(&b, ev[4 * l + 2], ev[4 * l + 3]) == hipSuccess)
+        if (hipEventElapsedTime(&a, e[4 * l], e[4 * l + 1]) == hipSuccess &&
+            hipEventElapsedTime(&b, e[4 * l + 2], e[4 * l + 3]) == hipSuccess)
             level_ms[l] += a + b;
     }
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, ev[4 * nl], ev[4 * nl + 1]) == hipSuccess) {
+    if (hipEventElapsedTime(&ms, e[4 * nl], e[4 * nl + 1]) == hipSuccess) {
         coarse_ms += ms;
         level_ms[L.lo] += ms;
     }
@@ -596,6 +602,12 @@ fem_status fem_solver::precondition(const double* r, double* z) {
 
 // Preconditioned CG on this solver's finest level; x holds the initial guess and returns the
 // iterate.  converged reports whether the true relative residual reached o.rtol.
+//
+// The scalars alpha, beta and r^T z stay on the device.  Each iteration enqueues q = A p, alpha,
+// the update of x and r, r^T r (copied to pinned host memory behind an event) and then,
+// speculatively, the preconditioner, r^T z, beta and the new direction; the host waits only for
+// that iteration's r^T r, which is ready before the preconditioner runs, so the queue never
+// drains.  On convergence the speculative work is discarded (it touches only z, p and scalars).
 fem_status fem_solver::cg(const double* b, double* x, int& it, double& rel_true, bool& converged) {
     const int hi = L.hi;
     const int64_t n = m->lev[hi].N;
@@ -603,15 +615,20 @@ fem_status fem_solver::cg(const double* b, double* x, int& it, double& rel_true,
     double* z = p<double>(L.cg_z);
     double* pp = p<double>(L.cg_p);
     double* q = p<double>(L.cg_q);
-    double out[2];
+    double* sc = p<double>(L.scal);
+    double* part = p<double>(L.partial);
     it = 0;
     converged = false;
     rel_true = 0.0;
     auto record = [&](int i, double v) {
         if (o.history && i < o.history_cap) o.history[i] = v;
     };
+    auto dotdev = [&](int npair, const double* x0, const double* y0, const double* x1, const double* y1, int slot) {
+        DotPairs<double> pr{{x0, x1, nullptr}, {y0, y1, nullptr}};
+        dot_launch<double>(npair, n, pr, part, sc + slot, s);
+    };
     const bool tmg = timing && o.preconditioner == FEM_PC_MG;
-    double bb = 0.0;
+    double bb = 0.0, rr = 0.0;
     FEM_TRY(dot(n, b, b, bb));
     const double nb = std::sqrt(bb);
     if (!std::isfinite(nb)) {
@@ -625,36 +642,67 @@ fem_status fem_solver::cg(const double* b, double* x, int& it, double& rel_true,
         return check_launch("solver");
     }
     FEM_TRY(apply64(hi, x, -1.0, b, 1.0, r));                 // r = b - A x
-    double rr = 0.0;
     FEM_TRY(dot(n, r, r, rr));
     double rel = std::sqrt(rr) / nb;
     record(0, rel);
-    double rz = 0.0;
-    if (rel <= o.rtol) {
-        converged = true;
-    } else {
+    // z = B r, rz, p = z (also the restart after a failed true-residual check)
+    auto start = [&]() -> fem_status {
+        evset = 0;
         FEM_TRY(precondition(r, z));
+        double rz = 0.0;
         FEM_TRY(dot(n, r, z, rz));
-        if (tmg) accumulate_times();
+        if (tmg) accumulate_times(0);
         if (!(rz > 0) || !std::isfinite(rz)) {
             set_error("solver: preconditioner is not positive definite (r^T B r <= 0)");
             return FEM_ERR_BREAKDOWN;
         }
+        fill_launch<double>(1, rz, sc + CG_RZ, s);
+        fill_launch<double>(1, 0.0, sc + CG_FLAG, s);
         axpby_launch<double>(n, 1.0, z, 0.0, pp, s);
-    }
+        return FEM_OK;
+    };
+    if (rel <= o.rtol) converged = true;
+    else FEM_TRY(start());
+    hipEvent_t done = ev.back();
+    bool pending_times = false;
+    // next search direction: z = B r, r^T z and q^T z (q = A p), beta, p = z + beta p
+    auto tail = [&](int set) -> fem_status {
+        evset = set;
+        FEM_TRY(precondition(r, z));
+        dotdev(2, r, z, q, z, CG_RZNEW);
+        cg_beta_launch(sc, o.flexible != 0, s);
+        cg_direction_dev_launch(n, sc, z, pp, s);
+        return FEM_OK;
+    };
     while (!converged && it < o.max_it) {
         FEM_TRY(apply64(hi, pp, 1.0, nullptr, 0.0, q));        // q = A p
-        double pq = 0.0;
-        FEM_TRY(dot(n, pp, q, pq));
-        if (!(pq > 0) || !std::isfinite(pq)) {
-            set_error("solver: CG breakdown (p^T A p <= 0 or not finite)");
-            return FEM_ERR_BREAKDOWN;
-        }
-        const double alpha = rz / pq;
-        cg_update_launch(n, alpha, pp, q, x, r, s);
+        dotdev(1, pp, q, nullptr, nullptr, CG_PQ);
+        cg_alpha_launch(sc, s);
+        cg_update_dev_launch(n, sc, pp, q, x, r, s);
         ++it;
         if (o.replace_every > 0 && it % o.replace_every == 0) FEM_TRY(apply64(hi, x, -1.0, b, 1.0, r));
-        FEM_TRY(dot(n, r, r, rr));
+        dotdev(1, r, r, nullptr, nullptr, CG_RR);
+        hipError_t e = hipMemcpyAsync(hscal, sc + CG_RR, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipEventRecord(done, s);
+        // far from convergence the next direction is computed speculatively, before the residual
+        // is known on the host; close to it the host checks first
+        const int set = it & 1;
+        const bool spec = rel > 30.0 * o.rtol;
+        if (spec) FEM_TRY(tail(set));
+        if (e == hipSuccess) e = hipEventSynchronize(done);
+        if (e != hipSuccess) {
+            set_error(std::string("solver: ") + hipGetErrorString(e));
+            return FEM_ERR_HIP;
+        }
+        if (tmg && pending_times) accumulate_times(set ^ 1);   // the previous iteration's V-cycle
+        pending_times = false;
+        rr = hscal[0];
+        const int flag = (int)hscal[1];
+        if (flag) {
+            set_error(flag & 1 ? "solver: CG breakdown (p^T A p <= 0 or not finite)"
+                               : "solver: preconditioner is not positive definite (r^T B r <= 0)");
+            return FEM_ERR_BREAKDOWN;
+        }
         rel = std::sqrt(rr) / nb;
         record(it, rel);
         if (!std::isfinite(rel)) {
@@ -662,27 +710,31 @@ fem_status fem_solver::cg(const double* b, double* x, int& it, double& rel_true,
             return FEM_ERR_BREAKDOWN;
         }
         if (rel <= o.rtol) {
-            // confirm with the true residual; if it disagrees, continue from it
+            // confirm with the true residual (stream-ordered after any speculative work)
             FEM_TRY(apply64(hi, x, -1.0, b, 1.0, q));
             double tt = 0.0;
             FEM_TRY(dot(n, q, q, tt));
+            if (tmg && spec) accumulate_times(set);
             if (std::sqrt(tt) / nb <= o.rtol) {
                 converged = true;
                 break;
             }
+            if (spec) {
+                // the speculative direction used the recurrence residual: restart from the true one
+                axpby_launch<double>(n, 1.0, q, 0.0, r, s);
+                FEM_TRY(start());
+                continue;
+            }
+            // continue from the true residual; q must hold A p again for the Polak-Ribiere beta
             axpby_launch<double>(n, 1.0, q, 0.0, r, s);
+            FEM_TRY(apply64(hi, pp, 1.0, nullptr, 0.0, q));
         }
-        FEM_TRY(precondition(r, z));
-        FEM_TRY(dots(2, n, r, z, q, z, out));                  // q still holds A p
-        if (tmg) accumulate_times();
-        const double rz_new = out[0], qz = out[1];
-        if (!(rz_new > 0) || !std::isfinite(rz_new)) {
-            set_error("solver: preconditioner is not positive definite (r^T B r <= 0)");
-            return FEM_ERR_BREAKDOWN;
-        }
-        const double beta = o.flexible ? (-alpha * qz / rz) : (rz_new / rz);
-        rz = rz_new;
-        axpby_launch<double>(n, 1.0, z, beta, pp, s);
+        if (!spec) FEM_TRY(tail(set));
+        pending_times = tmg;
+    }
+    if (pending_times) {
+        const hipError_t e = hipStreamSynchronize(s);
+        if (e == hipSuccess) accumulate_times(evset);
     }
     // true residual at exit
     FEM_TRY(apply64(hi, x, -1.0, b, 1.0, q));

@@ -79,6 +79,45 @@ __global__ void k_cg_update(int64_t n, double alpha, const double* __restrict__ 
     }
 }
 
+// Device-resident CG scalars (indices into the solver's scalar block, see vec.hpp).
+// alpha = rz / pq, or 0 with flag bit 1 when p^T A p is not positive and finite.
+__global__ void k_cg_alpha(double* sc) {
+    if (threadIdx.x != 0) return;
+    const double pq = sc[CG_PQ], rz = sc[CG_RZ];
+    const bool ok = pq > 0.0 && pq < INFINITY;
+    sc[CG_ALPHA] = ok ? rz / pq : 0.0;
+    if (!ok) sc[CG_FLAG] = (double)((int)sc[CG_FLAG] | 1);
+}
+
+// beta (Fletcher-Reeves rz_new / rz, or Polak-Ribiere -alpha qz / rz) and rz = rz_new; beta = 0
+// with flag bit 2 when r^T z is not positive and finite.
+__global__ void k_cg_beta(double* sc, int flexible) {
+    if (threadIdx.x != 0) return;
+    const double rzn = sc[CG_RZNEW], rz = sc[CG_RZ];
+    const bool ok = rzn > 0.0 && rzn < INFINITY;
+    sc[CG_BETA] = !ok ? 0.0 : flexible ? -sc[CG_ALPHA] * sc[CG_QZ] / rz : rzn / rz;
+    sc[CG_RZ] = rzn;
+    if (!ok) sc[CG_FLAG] = (double)((int)sc[CG_FLAG] | 2);
+}
+
+// x += alpha p ; r -= alpha q with alpha read from device memory
+__global__ void k_cg_update_dev(int64_t n, const double* __restrict__ sc, const double* __restrict__ p,
+                                const double* __restrict__ q, double* __restrict__ x, double* __restrict__ r) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i < n) {
+        const double alpha = sc[CG_ALPHA];
+        x[i] += alpha * p[i];
+        r[i] -= alpha * q[i];
+    }
+}
+
+// p = z + beta p with beta read from device memory
+__global__ void k_cg_direction_dev(int64_t n, const double* __restrict__ sc, const double* __restrict__ z,
+                                   double* __restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i < n) p[i] = z[i] + sc[CG_BETA] * p[i];
+}
+
 // Chebyshev step: d = c1 d + c2 dinv r ; x = (init ? d : x + d)
 template <typename T>
 __global__ void k_cheb(int64_t n, T c1, T c2, const T* __restrict__ dinv, const T* __restrict__ r,
@@ -416,6 +455,18 @@ template void axpby_launch<float>(int64_t, double, const float*, double, float*,
 
 void cg_update_launch(int64_t n, double alpha, const double* p, const double* q, double* x, double* r, hipStream_t s) {
     hipLaunchKernelGGL(k_cg_update, dim3(grid_for(n)), dim3(VT), 0, s, n, alpha, p, q, x, r);
+}
+
+void cg_alpha_launch(double* sc, hipStream_t s) { hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64), 0, s, sc); }
+void cg_beta_launch(double* sc, bool flexible, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64), 0, s, sc, flexible ? 1 : 0);
+}
+void cg_update_dev_launch(int64_t n, const double* sc, const double* p, const double* q, double* x, double* r,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_update_dev, dim3(grid_for(n)), dim3(VT), 0, s, n, sc, p, q, x, r);
+}
+void cg_direction_dev_launch(int64_t n, const double* sc, const double* z, double* p, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_direction_dev, dim3(grid_for(n)), dim3(VT), 0, s, n, sc, z, p);
 }
 
 template <typename T>

@@ -23,6 +23,16 @@ size_t dot_partial_doubles();
 template <typename T>
 void axpby_launch(int64_t n, double a, const T* x, double b, T* y, hipStream_t s);
 void cg_update_launch(int64_t n, double alpha, const double* p, const double* q, double* x, double* r, hipStream_t s);
+
+// CG scalars kept on the device (slots of the solver's scalar block), so that an iteration needs
+// no host round trip: alpha = rz / pq; beta and rz <- rz_new; flag bits 1 (p^T A p <= 0) and
+// 2 (r^T z <= 0) record breakdowns.
+enum { CG_RZ = 8, CG_PQ = 9, CG_ALPHA = 10, CG_RR = 11, CG_FLAG = 12, CG_RZNEW = 13, CG_QZ = 14, CG_BETA = 15 };
+void cg_alpha_launch(double* sc, hipStream_t s);
+void cg_beta_launch(double* sc, bool flexible, hipStream_t s);
+void cg_update_dev_launch(int64_t n, const double* sc, const double* p, const double* q, double* x, double* r,
+                          hipStream_t s);
+void cg_direction_dev_launch(int64_t n, const double* sc, const double* z, double* p, hipStream_t s);
 // d = c1 d + c2 dinv r (first: d = c2 dinv r); x = d (init) or x += d
 template <typename T>
 void cheb_launch(int64_t n, double c1, double c2, const T* dinv, const T* r, T* d, T* x, bool first, bool init,
