@@ -18,9 +18,21 @@ Setup (mesh upload, Jacobi diagonals, Lanczos estimates, coarse inverse) is outs
 region and reported separately.
 
 value = operator-action GDoF/s of step 1: n_dofs / (mean duration of the action, from HIP events
-recorded on the stream the action's kernels run on, over the timed steps).  roofline.achieved
-uses the algorithmic bytes of one action, B = 2 N s + 4 C nloc + 6 C s (+ N_v s for a P1
-coefficient): x read and y write, the int32 cell-to-dof map and the per-cell geometric factors.
+recorded on the stream the action's kernels run on, over the timed steps).  The action is two
+launches (the cube kernel and the interface fix-up).  Algorithmic bytes of one action:
+  P1/P2 on 4-cube bricks (geometry from vertex coordinates, per-cube dof map):
+      B = 2 N s + 4 (p+1)^3 C/6 + 24 N_v (+ N_v s for a P1 coefficient)
+  otherwise (stored per-cell factors): B = 2 N s + 4 C nloc + 6 C s (+ N_v s)
+(x read and y written once, int32 dof indices, FP64 vertex coordinates or per-cell factors).
+Algorithmic flops: (12 nq nloc + 20 nq) per cell, the tabulated-gradient contraction.  roofline
+reports the binding roof: the larger of bytes / 8 TB/s and flops / vector peak (FP64 78.6,
+FP32 157.3 TFLOP/s), as a fraction of the measured time.
+
+Profiler post-processing (no GPU needed): --summarize-trace DIR prints per-kernel, per-grid
+durations from a rocprofv3 --kernel-trace csv directory; --summarize-counters FETCH_DIR
+WRITE_DIR prints FETCH_SIZE / WRITE_SIZE per kernel and grid, scaled by the counts of the
+512 MiB calibration copy (--copy-calibration), and --write-traffic stores the action's bytes in
+profiles/apply_traffic.json for the current kernel sources.
 
 Other workloads (--workload): "p3-48-vark" (P3, k = exp(g), 6^3 refined 3x to 48^3, 4-level
 MG-CG, mixed precision as the solver of record), "p2-128" (P2 from 4^3 refined 5x to 128^3; the
@@ -100,11 +112,18 @@ def traffic_from_profiles(key):
     return e.get("traffic_bytes")
 
 
+def action_bytes(p, n, C, N, NV, s, kvar):
+    """Algorithmic bytes of one action for the layout the library uses at this size."""
+    if p <= 2 and n % 4 == 0:
+        return 2 * N * s + 4 * (p + 1) ** 3 * (C // 6) + 24 * NV + (NV * s if kvar else 0)
+    return balg_bytes(C, N, nloc_of(p), s, NV if kvar else 0)
+
+
 def roofline(p, kvar, C, N, NV, s, t, key):
-    """Roofline entry of the action: HBM-bound for P1/P2; for P3 the larger of the HBM fraction
-    and the fraction of the vector ALU peak (FP64 78.6, FP32 157.3 TFLOP/s)."""
-    nl = nloc_of(p)
-    B = balg_bytes(C, N, nl, s, NV if kvar else 0)
+    """Roofline entry of the action: the binding roof of bytes / 8 TB/s and flops / vector peak,
+    with the measured fraction of it."""
+    n = round((C / 6) ** (1 / 3))
+    B = action_bytes(p, n, C, N, NV, s, kvar)
     gbs = B / t / 1e9
     out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(key),
@@ -455,6 +474,96 @@ def run_sweep(args, name, w):
     return out
 
 
+def _csv(path):
+    import csv
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _short(name):
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "").replace("fem::", "")
+    return name.split("(")[0]
+
+
+def summarize_trace(d):
+    """Per-kernel, per-grid durations from a rocprofv3 --kernel-trace csv directory."""
+    import collections
+    rows = _csv(os.path.join(d, "run_kernel_trace.csv"))
+    agg = collections.defaultdict(list)
+    for r in rows:
+        key = (_short(r["Kernel_Name"]), int(r["Grid_Size_X"]), int(r["Workgroup_Size_X"]))
+        agg[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(v) for v in agg.values())
+    print(f"{'calls':>6} {'mean_us':>9} {'median_us':>9} {'min_us':>8} {'share':>6}  kernel [grid threads, workgroup]")
+    for (nm, g, w), v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:30]:
+        v.sort()
+        print(f"{len(v):6d} {sum(v) / len(v):9.2f} {v[len(v) // 2]:9.2f} {v[0]:8.2f} {100 * sum(v) / total:5.1f}%  "
+              f"{nm} [{g}, {w}]")
+    stats = os.path.join(d, "run_kernel_stats.csv")
+    if os.path.exists(stats):
+        print("\nrocprofv3 --stats (all grids of a kernel together), top 12:")
+        print(f"{'calls':>6} {'avg_us':>9} {'share':>6}  kernel")
+        for r in _csv(stats)[:12]:
+            print(f"{int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:9.2f} {float(r['Percentage']):5.1f}%  {_short(r['Name'])}")
+
+
+def summarize_counters(fdir, wdir, workload, write_traffic):
+    """FETCH_SIZE / WRITE_SIZE per kernel and grid, in bytes, scaled by the counts the 512 MiB
+    calibration copy produced; optionally the action's bytes to profiles/apply_traffic.json."""
+    import collections
+    res = {}
+    cal = {}
+    for cname, d in (("FETCH_SIZE", fdir), ("WRITE_SIZE", wdir)):
+        rows = [r for r in _csv(os.path.join(d, "run_counter_collection.csv")) if r["Counter_Name"] == cname]
+        per = collections.defaultdict(list)
+        for r in rows:
+            per[(_short(r["Kernel_Name"]), r["Kernel_Name"], int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+        copies = [max(v) for (nm, full, g), v in per.items() if "copyBuffer" in nm]
+        cal[cname] = (512 * 1024.0) / max(copies)             # counter KiB per 512 MiB copy
+        for key, v in per.items():
+            res.setdefault(key, {})[cname] = sum(v) / len(v) * 1024.0 * cal[cname]
+    print(f"calibration: FETCH_SIZE x{cal['FETCH_SIZE']:.3f}, WRITE_SIZE x{cal['WRITE_SIZE']:.3f} "
+          "(counter KiB of the 512 MiB device copy vs its bytes)")
+    print(f"{'fetch_MB':>9} {'write_MB':>9}  kernel [grid threads]")
+    acts = {}
+    for (nm, full, g), c in sorted(res.items(), key=lambda kv: -kv[1].get("FETCH_SIZE", 0.0)):
+        if not any(k in nm for k in ("k_cube_apply", "k_fixup", "k_brick", "copyBuffer", "k_prolong", "k_sym")):
+            continue
+        f, w = c.get("FETCH_SIZE", 0.0), c.get("WRITE_SIZE", 0.0)
+        print(f"{f / 1e6:9.2f} {w / 1e6:9.2f}  {nm} [{g}]")
+        acts.setdefault("f64" if "double" in full else "f32", []).append((g, nm, f + w))
+    w = WORKLOADS[workload]
+    pw = w.get("p", 2)
+    action_kernels = (f"k_cube_apply<{pw},", f"k_brick<0, {pw},", f"k_fixup<{pw},")
+    acts = {prec: [(g, nm, b) for g, nm, b in lst if nm.startswith(action_kernels)] for prec, lst in acts.items()}
+    n = w.get("n0", 0) * 2 ** w.get("refine", 0)
+    key0 = f"P{w.get('p', 2)}{'k' if w.get('kvar') else ''}_n{n}"
+    out = {}
+    for prec, lst in acts.items():
+        # the finest level's launches: the largest grid of the main kernel and of the fix-up
+        best = {}
+        for fam in ("main", "fix"):
+            cand = [(g, nm, b) for g, nm, b in lst if nm.startswith("k_fixup") == (fam == "fix")]
+            if cand:
+                g, nm, b = max(cand)
+                best[nm] = (g, b)
+        total = sum(b for g, b in best.values())
+        out[f"{key0}_{prec}"] = {"kernel_sources_sha": kernel_sources_sha(), "traffic_bytes": int(total),
+                                 "kernels": {nm: {"grid": g, "bytes": int(b)} for nm, (g, b) in best.items()}}
+        print(f"action {key0}_{prec}: {total / 1e6:.2f} MB per application (FETCH + WRITE, calibrated)")
+    if write_traffic:
+        path = os.path.join(ROOT, "profiles", "apply_traffic.json")
+        try:
+            with open(path) as fh:
+                old = json.load(fh)
+        except (OSError, ValueError):
+            old = {}
+        old.update(out)
+        with open(path, "w") as fh:
+            json.dump(old, fh, indent=1, sort_keys=True)
+        print(f"wrote {path}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -465,7 +574,16 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 512 MiB device-to-device copy first: a dispatch of known size that "
                          "calibrates hardware byte counters in profiler runs of this command")
+    ap.add_argument("--summarize-trace", metavar="DIR")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--write-traffic", action="store_true")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
+        return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, args.workload, args.write_traffic)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
