@@ -14,8 +14,9 @@
 //    node-to-point map is a compile-time table);
 //  * quadrature tabulations are literals, so zero gradient entries generate no instructions;
 //  * the cubes' point values go to LDS once; then each closure point of the brick sums the values
-//    of the (up to 8) cubes containing it in a fixed order (so the result is reproducible), with
-//    consecutive lanes on consecutive points along x, so the stores to y are contiguous runs;
+//    of the (up to 8) cubes containing it in a fixed order (so the result is reproducible), one
+//    lane per row of points along x with the x loop unrolled; the sums return to LDS and are
+//    written with consecutive lanes on consecutive points, so stores to y are contiguous runs;
 //  * loads use 32-bit offsets from uniform bases (the host keeps such levels below 4 GiB per array).
 #pragma once
 #include "scatter.hpp"
@@ -43,25 +44,14 @@ __device__ __forceinline__ void axis_terms(int l, int sj, int sc, int off[2], bo
     off[1] = P * sj * NT + (c0 - 1) * sc;
 }
 
-// Sum over the cubes containing closure point (la, lb, lc): up to two terms per axis, in the
-// order (z, y, x) lower term first; absent terms read the zero entry at the end of part.
-template <int P, int B, typename T>
-__device__ __forceinline__ T closure_sum(const T* part, int la, int lb, int lc) {
-    constexpr int PC = P + 1, NT = B * B * B, ZERO = PC * PC * PC * NT;
-    int ox[2], oy[2], oz[2];
-    bool vx[2], vy[2], vz[2];
-    axis_terms<P, B>(la, 1, 1, ox, vx);
-    axis_terms<P, B>(lb, PC, B, oy, vy);
-    axis_terms<P, B>(lc, PC * PC, B * B, oz, vz);
-    T acc = T(0);
-#pragma unroll
-    for (int iz = 0; iz < 2; ++iz)
-#pragma unroll
-        for (int iy = 0; iy < 2; ++iy)
-#pragma unroll
-            for (int ix = 0; ix < 2; ++ix)
-                acc += part[(vx[ix] && vy[iy] && vz[iz]) ? ox[ix] + oy[iy] + oz[iz] : ZERO];
-    return acc;
+// 1 / d from the hardware reciprocal refined by two Newton steps r <- r + r (1 - d r) (quadratic
+// convergence: well below an ulp of error left for the accuracy the kernels need).
+__device__ __forceinline__ double recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
 }
 
 #ifndef FEM_CUBE_MIN_WAVES
@@ -73,6 +63,7 @@ __global__ void __launch_bounds__(B * B * B, FEM_CUBE_MIN_WAVES) k_cube_apply(SA
     constexpr int NT = B * B * B, PB = P * B, QS = PB + 1, Q = QS * QS * QS;
     constexpr StiffTab<P, KVAR> TB{};
     constexpr CubeNodes<P> CN{};
+    constexpr int ZERO = NCP * NT;
     __shared__ T part[NCP * NT + 1];   // cube point j of cube c at part[j * NT + c]; last: zero
     const int brick = brick_of_block(blockIdx.x, gridDim.x);
     const int nb = a.nb;
@@ -129,7 +120,7 @@ __global__ void __launch_bounds__(B * B * B, FEM_CUBE_MIN_WAVES) k_cube_apply(SA
                      c3z = e1[0] * e2[1] - e1[1] * e2[0];
         const double det = e1[0] * c1x + e1[1] * c1y + e1[2] * c1z;
         constexpr double kScale = (P == 2 && !KVAR) ? 1.0 / 120.0 : 1.0;   // P1 mass factor, vertex form
-        const double inv = kScale / fabs(det);
+        const double inv = kScale * recip(fabs(det));
         const T g00 = T((c1x * c1x + c1y * c1y + c1z * c1z) * inv);
         const T g11 = T((c2x * c2x + c2y * c2y + c2z * c2z) * inv);
         const T g22 = T((c3x * c3x + c3y * c3y + c3z * c3z) * inv);
@@ -215,16 +206,67 @@ __global__ void __launch_bounds__(B * B * B, FEM_CUBE_MIN_WAVES) k_cube_apply(SA
     if (cube == 0) part[NCP * NT] = T(0);
     __syncthreads();
     // Closure points of the brick, each the sum of the values of the (up to 8) cubes containing it
-    // in a fixed order (absent terms read a zero entry, so the sum is branch-free).  Interior
-    // points first, x fastest, so consecutive lanes store consecutive dofs of y; then the points
-    // on the brick's faces, which go to their interface slots.
+    // in a fixed order (absent terms read a zero entry, so the sum is branch-free).  The sums are
+    // formed one lane per row of points along x (interior rows, then the rows on the brick's y and
+    // z faces) with the x loop unrolled, so its cube terms are compile-time constants; the rows
+    // are then put back in LDS in closure order and written with consecutive lanes on
+    // consecutive points: interior points to y (contiguous runs), face points to their slots.
+    constexpr int QI = PB - 1, NFR = QS * QS - QI * QI;
+    T rowv[2][QS];
+    int rowq[2];
+#pragma unroll
+    for (int round = 0; round < 2; ++round) {
+        const int r = threadIdx.x;
+        int lb = 0, lc = 0;
+        rowq[round] = -1;
+        if (round == 0) {
+            if (r >= QI * QI) continue;
+            lb = 1 + r % QI;
+            lc = 1 + r / QI;
+        } else {
+            if (r >= NFR) continue;
+            if (r < 2 * QS) {                 // z faces: lc = 0 or PB, all lb
+                lb = r % QS;
+                lc = r < QS ? 0 : PB;
+            } else {                          // y faces: lb = 0 or PB, lc inside
+                const int u = r - 2 * QS;
+                lc = 1 + u % QI;
+                lb = u < QI ? 0 : PB;
+            }
+        }
+        rowq[round] = QS * (lb + QS * lc);
+        int oy[2], oz[2];
+        bool vy[2], vz[2];
+        axis_terms<P, B>(lb, PC, B, oy, vy);
+        axis_terms<P, B>(lc, PC * PC, B * B, oz, vz);
+        int oyz[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) oyz[k] = (vy[k & 1] && vz[k >> 1]) ? oy[k & 1] + oz[k >> 1] : -1;
+#pragma unroll
+        for (int la = 0; la < QS; ++la) {
+            const int cx = la / P, ax = la % P;
+            T v = T(0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (cx < B) v += part[oyz[k] >= 0 ? oyz[k] + ax * NT + cx : ZERO];
+                if (ax == 0 && cx > 0) v += part[oyz[k] >= 0 ? oyz[k] + P * NT + cx - 1 : ZERO];
+            }
+            rowv[round][la] = v;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int round = 0; round < 2; ++round)
+        if (rowq[round] >= 0)
+#pragma unroll
+            for (int la = 0; la < QS; ++la) part[rowq[round] + la] = rowv[round][la];
+    __syncthreads();
     const int64_t L = a.Lout;
-    constexpr int QI = PB - 1, NIN = QI * QI * QI;
+    constexpr int NIN = QI * QI * QI;
     for (int r = threadIdx.x; r < NIN; r += NT) {
         const int la = 1 + r % QI, lb = 1 + (r / QI) % QI, lc = 1 + r / (QI * QI);
-        const T v = closure_sum<P, B>(part, la, lb, lc);
         const int64_t g = (bx * PB + la) + L * ((by * PB + lb) + L * (int64_t)(bz * PB + lc));
-        finalize(a, g, v, false);
+        finalize(a, g, part[la + QS * (lb + QS * lc)], false);
     }
     constexpr int NZF = 2 * QS * QS, NYF = 2 * QS * QI, NXF = 2 * QI * QI;
     for (int r = threadIdx.x; r < NZF + NYF + NXF; r += NT) {
@@ -245,7 +287,7 @@ __global__ void __launch_bounds__(B * B * B, FEM_CUBE_MIN_WAVES) k_cube_apply(SA
             lc = 1 + u / QI;
             la = r - NZF - NYF < QI * QI ? 0 : PB;
         }
-        put_slot<PB, T>(a, bx, by, bz, la, lb, lc, closure_sum<P, B>(part, la, lb, lc));
+        put_slot<PB, T>(a, bx, by, bz, la, lb, lc, part[la + QS * (lb + QS * lc)]);
     }
 }
 
