@@ -13,7 +13,9 @@ One step = one pass of the hot path:
   2. the same action in FP32 (cold),
   3. the MG-CG solve to 1e-8 in FP64 (x0 = 0),
   4. the MG-CG solve to 1e-8 with FP32 smoothing / transfers and FP64 outer CG (x0 = 0),
-  5. the adjoint gradient kernel dJ/dk (u and lambda from steps 3 and 4).
+  5. the adjoint gradient kernel dJ/dk (u and lambda from steps 3 and 4),
+  6. one full-multigrid cycle as the solver (the paper's Listing 2 configuration), FP64 and
+     mixed.
 Setup (mesh upload, Jacobi diagonals, Lanczos estimates, coarse inverse) is outside the timed
 region and reported separately.
 
@@ -270,11 +272,18 @@ def run_solve(args, name, w):
         e = tm.start()
         mesh.adjoint_grad_k(u64, umx)
         tm.stop(e, "grad", r)
+        t3 = time.perf_counter()
+        uf64, rf64 = s64.fmg(b)
+        t4 = time.perf_counter()
+        ufmx, rfmx = smx.fmg(b)
+        t5 = time.perf_counter()
         tm.collect()
         if record:
             rec.setdefault("solve64", []).append(t1 - t0)
             rec.setdefault("solvemx", []).append(t2 - t1)
-            last.update(u64=u64, umx=umx, r64=r64, rmx=rmx)
+            rec.setdefault("fmg64", []).append(t4 - t3)
+            rec.setdefault("fmgmx", []).append(t5 - t4)
+            last.update(u64=u64, umx=umx, r64=r64, rmx=rmx, uf64=uf64, ufmx=ufmx, rf64=rf64, rfmx=rfmx)
 
     for _ in range(args.warmup):
         step(False)
@@ -321,8 +330,15 @@ def run_solve(args, name, w):
         "solver_setup_s": {"fp64": round(setup64, 3), "mixed": round(setupmx, 3)},
         "adjoint_grad_kernel_ms": round(mean(rec["grad"]) * 1e3, 4),
     })
+    out.update({
+        "fmg_fp64_ms": round(mean(rec["fmg64"]) * 1e3, 3), "fmg_mixed_ms": round(mean(rec["fmgmx"]) * 1e3, 3),
+        "fmg_fp64_rel_residual": last["rf64"].rel_residual_true, "fmg_mixed_rel_residual": last["rfmx"].rel_residual_true,
+        "fmg_vs_mgcg_solution_rel_diff": (torch.linalg.norm(last["uf64"] - u64) / torch.linalg.norm(u64)).item(),
+    })
     if u_exact is not None:
-        out["discretisation_rel_l2_nodal"] = (torch.linalg.norm(u64 - u_exact) / torch.linalg.norm(u_exact)).item()
+        nu = torch.linalg.norm(u_exact)
+        out["discretisation_rel_l2_nodal"] = (torch.linalg.norm(u64 - u_exact) / nu).item()
+        out["fmg_discretisation_rel_l2_nodal"] = (torch.linalg.norm(last["uf64"] - u_exact) / nu).item()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(info["n"], p, kvar)
     return out

@@ -193,6 +193,15 @@ fem_status fem_solver_setup(fem_solver* s, const double* k_vertex, void* stream)
 fem_status fem_solver_solve(fem_solver* s, const double* b, double* x, fem_solve_stats* stats, void* stream);
 /* z = B r: one application of the multigrid preconditioner (FP64 in/out, finest level). */
 fem_status fem_solver_vcycle(fem_solver* s, const double* r, double* z, void* stream);
+/* One full-multigrid cycle as the solver (Listing 2: pc_mg_type full with a preonly outer
+ * solver): b (FP64 device, finest level, boundary rows zero) is restricted to every level used,
+ * the coarsest is solved exactly, and on each finer level the prolonged solution is corrected by
+ * one V-cycle on that level's residual; x (FP64 device, overwritten) receives the finest-level
+ * result.  In mixed precision the V-cycles run in FP32 (restriction, prolongation, residuals and
+ * the coarse solve stay FP64).  stats: iterations = 1, rel_residual_true = ||b - A x|| / ||b||,
+ * solve_ms.  Host-synchronous; needs the multigrid preconditioner (FEM_ERR_UNSUPPORTED for
+ * Jacobi). */
+fem_status fem_solver_fmg(fem_solver* s, const double* b, double* x, fem_solve_stats* stats, void* stream);
 void fem_solver_destroy(fem_solver* s);
 
 /* One-shot: create, set up, solve, destroy. */

@@ -6,8 +6,9 @@ again; Listing 2: 2 Chebyshev iterations per level, direct coarse solve).
 
 Readings (listed in DESIGN.md):
 * The multigrid cycle is a V(2,2) cycle used as the preconditioner of CG
-  (the configuration this library targets), not Listing 2's full-multigrid
-  cycle with a preonly outer solver.
+  (the configuration this library targets); Listing 2's full-multigrid cycle
+  with a preonly outer solver is MGHierarchy.fmg (one F-cycle: restricted
+  right-hand sides, exact coarse solve, prolongation and one V-cycle per level).
 * The smoother is Chebyshev on D^-1 A (Jacobi-preconditioned) over the
   interval [0.1 lmax, 1.1 lmax], degree 2, in the three-term recurrence of
   Saad, Iterative Methods for Sparse Linear Systems, Alg. 12.1.  The same
@@ -165,6 +166,24 @@ class MGHierarchy:
     def solve(self, b, rtol=1e-8, max_it=200, flexible=False):
         A = self.levels[-1].A
         return cg(A, b, rtol=rtol, max_it=max_it, M=self.vcycle, flexible=flexible)
+
+    def fmg(self, b):
+        """One full-multigrid cycle as the solver (Listing 2: full multigrid with a preonly
+        outer solver): the right-hand side is restricted to every level (R = P^T, boundary rows
+        zero), the coarsest problem is solved exactly, and on each finer level the prolonged
+        coarse solution is corrected by one V-cycle on that level's residual."""
+        bs = [None] * len(self.levels)
+        bs[-1] = np.asarray(b, dtype=np.float64)
+        for ell in range(len(self.levels) - 1, 0, -1):
+            bc = self.levels[ell].P.T @ bs[ell]
+            bc[self.levels[ell - 1].level.boundary] = 0.0
+            bs[ell - 1] = bc
+        x = self.coarse_solve(bs[0])
+        for ell in range(1, len(self.levels)):
+            L = self.levels[ell]
+            x = L.P @ x
+            x = x + self.vcycle(bs[ell] - L.A @ x, ell)
+        return x
 
 
 def _inject_k(levels, k_fine_vertex):

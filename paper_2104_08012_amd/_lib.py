@@ -91,6 +91,7 @@ SIGNATURES = {
     "fem_solver_setup": (_st, [_vp, _vp, _vp]),
     "fem_solver_solve": (_st, [_vp, _vp, _vp, C.POINTER(SolveStats), _vp]),
     "fem_solver_vcycle": (_st, [_vp, _vp, _vp, _vp]),
+    "fem_solver_fmg": (_st, [_vp, _vp, _vp, C.POINTER(SolveStats), _vp]),
     "fem_solver_destroy": (None, [_vp]),
     "fem_mg_cg_solve": (_st, [_vp, _vp, _vp, _vp, C.POINTER(SolveOpts), _vp, C.c_size_t,
                               C.POINTER(SolveStats), _vp]),

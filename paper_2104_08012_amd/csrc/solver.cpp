@@ -42,6 +42,7 @@ constexpr int64_t kInnerDense = 8000;  // nested solve: its dense level, the fin
 
 struct LevelWs {
     size_t x = 0, b = 0, r = 0, d = 0, dinv = 0, k64 = 0, k32 = 0, b64 = 0, x64 = 0;
+    size_t fb = 0, fx = 0;   // full multigrid: FP64 right-hand side and solution (below the top)
 };
 
 struct Layout {
@@ -116,6 +117,10 @@ fem_status make_layout(const fem_mesh& m, const fem_solve_opts& o, int top, Layo
         if (l == L.lo && L.mixed) {
             w.b64 = take(N * 8);
             w.x64 = take(N * 8);
+        }
+        if (l < top && o.preconditioner == FEM_PC_MG) {
+            w.fb = take(N * 8);
+            w.fx = take(N * 8);
         }
     }
     const int64_t Nf = m.lev[L.hi].N;
@@ -293,6 +298,7 @@ struct fem_solver {
     fem_status lanczos(int l, double& lm);
     fem_status precondition(const double* r, double* z);
     fem_status cg(const double* b, double* x, int& iters, double& rel_true, bool& converged);
+    fem_status fmg(const double* b, double* x, double& rel_true);
     void accumulate_times(int set);
 };
 
@@ -745,6 +751,47 @@ fem_status fem_solver::cg(const double* b, double* x, int& it, double& rel_true,
     return FEM_OK;
 }
 
+// One full-multigrid cycle (see fem_solver_fmg in the header).
+fem_status fem_solver::fmg(const double* b, double* x, double& rel_true) {
+    const int hi = L.hi, lo = L.lo;
+    auto fb = [&](int l) -> double* { return l == hi ? const_cast<double*>(b) : p<double>(L.lev[l].fb); };
+    auto fx = [&](int l) -> double* { return l == hi ? x : p<double>(L.lev[l].fx); };
+    for (int l = hi; l > lo; --l) {
+        ScatterIO<double> io;
+        io.x = fb(l);
+        io.y = fb(l - 1);
+        io.row_mode = ROW_ZERO;
+        FEM_TRY(run_scatter<double>(*m, l - 1, K_RESTRICT, false, io, s));
+    }
+    FEM_TRY(coarse_solve(fb(lo), fx(lo)));                    // FP64 in both precisions
+    for (int l = lo + 1; l <= hi; ++l) {
+        const int64_t n = m->lev[l].N;
+        fill_launch<double>(n, 0.0, fx(l), s);
+        FEM_TRY(run_prolong<double>(*m, l, fx(l - 1), fx(l), s));
+        if (L.mixed) {
+            double* r64 = p<double>(L.cg_q);
+            double* e64 = p<double>(L.cg_z);
+            FEM_TRY(apply64(l, fx(l), -1.0, fb(l), 1.0, r64));
+            cast_launch<double, float>(n, r64, p<float>(L.lev[l].b), s);
+            FEM_TRY(vcycle<float>(l, p<float>(L.lev[l].b), p<float>(L.lev[l].x)));
+            cast_launch<float, double>(n, p<float>(L.lev[l].x), e64, s);
+            axpby_launch<double>(n, 1.0, e64, 1.0, fx(l), s);
+        } else {
+            FEM_TRY(apply64(l, fx(l), -1.0, fb(l), 1.0, p<double>(L.lev[l].b)));
+            FEM_TRY(vcycle<double>(l, p<double>(L.lev[l].b), p<double>(L.lev[l].x)));
+            axpby_launch<double>(n, 1.0, p<double>(L.lev[l].x), 1.0, fx(l), s);
+        }
+    }
+    const int64_t n = m->lev[hi].N;
+    double* q = p<double>(L.cg_q);
+    FEM_TRY(apply64(hi, x, -1.0, b, 1.0, q));
+    double bb = 0.0, qq = 0.0;
+    FEM_TRY(dot(n, b, b, bb));
+    FEM_TRY(dot(n, q, q, qq));
+    rel_true = bb > 0 ? std::sqrt(qq / bb) : std::sqrt(qq);
+    return FEM_OK;
+}
+
 extern "C" {
 
 void fem_solve_opts_default(fem_solve_opts* o) {
@@ -893,6 +940,45 @@ fem_status fem_solver_solve(fem_solver* S, const double* b, double* x, fem_solve
     if (!conv) {
         set_error("fem_solver_solve: max_it reached before rtol (relative residual " + std::to_string(rel_true) + ")");
         return FEM_WARN_NOT_CONVERGED;
+    }
+    return FEM_OK;
+}
+
+fem_status fem_solver_fmg(fem_solver* S, const double* b, double* x, fem_solve_stats* stats, void* stream) {
+    if (!S || !b || !x || b == x) {
+        set_error("fem_solver_fmg: bad arguments");
+        return FEM_ERR_INVALID_ARG;
+    }
+    if (!S->ready) {
+        set_error("fem_solver_fmg: solver not set up");
+        return FEM_ERR_STATE;
+    }
+    if (S->o.preconditioner != FEM_PC_MG) {
+        set_error("fem_solver_fmg: needs the multigrid preconditioner");
+        return FEM_ERR_UNSUPPORTED;
+    }
+    S->s = (hipStream_t)stream;
+    S->coarse_iters = 0;
+    const bool t = S->timing;
+    S->timing = false;
+    const double t0 = now_ms();
+    double rel = 0.0;
+    fem_status st = S->fmg(b, x, rel);
+    S->timing = t;
+    if (st) return st;
+    const hipError_t e = hipStreamSynchronize(S->s);
+    if (e != hipSuccess) {
+        set_error(std::string("fem_solver_fmg: ") + hipGetErrorString(e));
+        return FEM_ERR_HIP;
+    }
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->iterations = 1;
+        stats->coarse_iterations = S->coarse_iters;
+        stats->rel_residual_true = rel;
+        stats->solve_ms = now_ms() - t0;
+        for (int l = 0; l < S->m->nlev && l < 8; ++l)
+            stats->lambda_max[l] = S->lmax.size() > (size_t)l ? S->lmax[l] : 0.0;
     }
     return FEM_OK;
 }

@@ -267,6 +267,18 @@ class Solver:
                           st.coarse_iterations, status)
         return x, res
 
+    def fmg(self, b: torch.Tensor, x: torch.Tensor | None = None):
+        """One full-multigrid cycle as the solver (the paper's Listing 2 configuration)."""
+        n = self.mesh.n_dofs(-1)
+        _need(b, n, torch.float64, "fmg b")
+        x = torch.empty_like(b) if x is None else x
+        _need(x, n, torch.float64, "fmg x")
+        st = L.SolveStats()
+        check(lib().fem_solver_fmg(self._h, _ptr(b), _ptr(x), C.byref(st), _stream(b.device)), "fem_solver_fmg")
+        res = SolveResult(1, st.rel_residual_true, st.setup_ms, st.solve_ms, st.coarse_ms, list(st.level_ms),
+                          list(st.lambda_max), [], st.coarse_iterations, 0)
+        return x, res
+
     def vcycle(self, r: torch.Tensor, z: torch.Tensor | None = None) -> torch.Tensor:
         z = torch.empty_like(r) if z is None else z
         check(lib().fem_solver_vcycle(self._h, _ptr(r), _ptr(z), _stream(r.device)), "fem_solver_vcycle")

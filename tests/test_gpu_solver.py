@@ -184,3 +184,32 @@ def test_determinism_and_warm_start():
     x, ra = S4.solve(b)
     x, rb = S.solve(b, x=x)
     assert rb.rel_residual_true <= 1e-10 and rb.iterations < r1.iterations
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("p,kvar,used", [(2, True, 0), (1, False, 0), (2, False, 2)])
+def test_fmg_matches_oracle(p, kvar, used):
+    """One full-multigrid cycle against the oracle's (same lambda_max on every level): FP64 to
+    1e-10; the mixed-precision cycle within FP32 rounding of it; on the truncated hierarchy
+    (used = 2) the coarse level is the nested solve's."""
+    banner(f"fmg p={p} kvar={kvar} used={used}")
+    from paper_2104_08012_amd import fem
+    mesh, levels = make_pair(2, 2, p, 0.1)
+    lev = levels[-1]
+    k = fem_inputs.k_exp_fourier(lev.vert_xyz) if kvar else None
+    sub = levels if used == 0 else levels[-used:]
+    omg = solvers.MGHierarchy(sub, k)
+    lm = [0.0] * (len(levels) - len(sub)) + [0.0] + [L.lmax for L in omg.levels[1:]]
+    b = _rhs(lev)
+    x_ref = omg.fmg(b)
+    extra = dict(n_levels_used=used, coarse_method="nested", coarse_rtol=1e-13) if used else {}
+    S = fem.Solver(mesh, fem.SolveOptions(lambda_max=lm, **extra)).setup(_t(k) if kvar else None)
+    x, res = S.fmg(_t(b))
+    torch.cuda.synchronize()
+    assert rel(x.cpu().numpy(), x_ref) <= (1e-9 if used else 1e-10)
+    r_ref = np.linalg.norm(b - omg.levels[-1].A @ x_ref) / np.linalg.norm(b)
+    assert abs(res.rel_residual_true - r_ref) <= 1e-6 * r_ref
+    Sm = fem.Solver(mesh, fem.SolveOptions(lambda_max=lm, precision="mixed", **extra)).setup(_t(k) if kvar else None)
+    xm, _ = Sm.fmg(_t(b))
+    torch.cuda.synchronize()
+    assert rel(xm.cpu().numpy(), x_ref) <= 1e-5

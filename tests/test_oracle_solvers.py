@@ -178,3 +178,41 @@ def test_vcycle_symmetric_and_mgcg_converges(p):
     u_ref = spla.spsolve(A.tocsc(), b)
     assert np.linalg.norm(u - u_ref) <= 1e-8 * np.linalg.norm(u_ref)
     assert it <= 20
+
+
+@pytest.mark.parametrize("p,n0,refine", [(1, 2, 3), (2, 2, 2)])
+def test_fmg_reaches_discretisation_accuracy(p, n0, refine):
+    """One full-multigrid cycle (Listing 2's solver) lands within a small factor of the exact
+    discrete solution's L2 error for the sine solution (the textbook FMG property: the error is
+    at most (1 + C) times the discretisation error, C from the V-cycle's contraction)."""
+    levels = om.hierarchy(n0, refine, p)
+    lev = levels[-1]
+    mg = solvers.MGHierarchy(levels)
+    b = assemble.load_vector(lev, fem_inputs.sin3_f, 2 * p + 4)
+    b[lev.boundary] = 0
+    u_fmg = mg.fmg(b)
+    u_h = solvers.direct_solve(mg.levels[-1].A, b)
+    e_fmg = assemble.l2_error(lev, u_fmg, fem_inputs.sin3_u, 2 * p + 4)
+    e_h = assemble.l2_error(lev, u_h, fem_inputs.sin3_u, 2 * p + 4)
+    assert e_fmg <= 2.0 * e_h, (e_fmg, e_h)
+    # its distance from the discrete solution is of the order of the discretisation error
+    d = assemble.l2_error(lev, u_fmg - u_h, lambda x: np.zeros(len(x)), 2 * p + 4)
+    assert d <= 1.5 * e_h, (d, e_h)
+
+
+def test_fmg_linear_and_exact_on_one_level():
+    levels = om.hierarchy(2, 1, 2, fem_inputs.jitter_offsets(2, 0.1))
+    mg = solvers.MGHierarchy(levels)
+    lev = levels[-1]
+    b1 = fem_inputs.uniform_vector(lev.n_dofs, 0)
+    b2 = fem_inputs.uniform_vector(lev.n_dofs, 7)
+    b1[lev.boundary] = 0
+    b2[lev.boundary] = 0
+    lhs = mg.fmg(2.5 * b1 + b2)
+    rhs = 2.5 * mg.fmg(b1) + mg.fmg(b2)
+    assert np.linalg.norm(lhs - rhs) <= 1e-12 * np.linalg.norm(rhs)
+    one = solvers.MGHierarchy(levels[:1])
+    bc = fem_inputs.uniform_vector(levels[0].n_dofs, 3)
+    bc[levels[0].boundary] = 0
+    x = one.fmg(bc)
+    assert np.linalg.norm(one.levels[0].A @ x - bc) <= 1e-12 * np.linalg.norm(bc)
