@@ -40,8 +40,11 @@ Other workloads (--workload): "p3-48-vark" (P3, k = exp(g), 6^3 refined 3x to 48
 MG-CG, mixed precision as the solver of record), "p2-128" (P2 from 4^3 refined 5x to 128^3; the
 outer cycle uses the 3 finest levels and its 32^3 coarse level is solved by nested FP64 MG-PCG),
 "adjoint-p2-32" (P2 state on 32^3, P1 k: forward solve, misfit, adjoint solve and gradient),
-"p1-8-jacobi" (P1 8^3, Jacobi-CG to 1e-10) and "sweep-128" (the action alone, P1/P2/P3 x
-FP64/FP32 on 128^3 x 6 tetrahedra).
+"p1-8-jacobi" (P1 8^3, Jacobi-CG to 1e-10), "sweep-128" (the action alone, P1/P2/P3 x
+FP64/FP32 on 128^3 x 6 tetrahedra), and for the hierarchy-depth study "p2-64-4lev" (the default
+problem from 8^3, 4 levels, dense 8^3 coarse) and "p2-64-nested" (3 levels with the 16^3 coarse
+level solved by nested MG-PCG); "csr" times the assembled operator (GPU assembly, SpMV) next to
+the matrix-free action.
 """
 from __future__ import annotations
 
@@ -65,9 +68,16 @@ WORKLOADS = {
     "p2-64": dict(kind="solve", n0=16, refine=2, p=2, kvar=False, used=0, rhs="sin", rtol=1e-8),
     "p3-48-vark": dict(kind="solve", n0=6, refine=3, p=3, kvar=True, used=0, rhs="one", rtol=1e-8),
     "p2-128": dict(kind="solve", n0=4, refine=5, p=2, kvar=False, used=3, rhs="sin", rtol=1e-8),
+    # hierarchy-depth study on the default problem: one more level (dense 8^3 coarse), and the
+    # 3-level cycle with its 16^3 coarse level solved by nested MG-PCG instead of the dense inverse
+    "p2-64-4lev": dict(kind="solve", n0=8, refine=3, p=2, kvar=False, used=0, rhs="sin", rtol=1e-8),
+    "p2-64-nested": dict(kind="solve", n0=4, refine=4, p=2, kvar=False, used=3, rhs="sin", rtol=1e-8,
+                         coarse="nested"),
     "adjoint-p2-32": dict(kind="adjoint", n0=8, refine=2, p=2, kvar=True),
     "p1-8-jacobi": dict(kind="jacobi", n0=8, refine=0, p=1, kvar=False, rtol=1e-10),
     "sweep-128": dict(kind="sweep", n=128),
+    # the assembled operator (CSR + SpMV, the paper's representation) next to the matrix-free one
+    "csr": dict(kind="csr", cases=((1, 128, False), (2, 64, False), (3, 48, True))),
 }
 
 
@@ -241,8 +251,9 @@ def run_solve(args, name, w):
     flush = torch.ones(1 << 29, dtype=torch.float32, device=dev)
     b, u_exact = rhs_for(mesh, w["rhs"], torch, dev, np, fem_inputs)
     used = w["used"]
-    o64 = fem.SolveOptions(rtol=w["rtol"], precision="fp64", n_levels_used=used)
-    omx = fem.SolveOptions(rtol=w["rtol"], precision="mixed", n_levels_used=used)
+    cm = w.get("coarse", "auto")
+    o64 = fem.SolveOptions(rtol=w["rtol"], precision="fp64", n_levels_used=used, coarse_method=cm)
+    omx = fem.SolveOptions(rtol=w["rtol"], precision="mixed", n_levels_used=used, coarse_method=cm)
     ts = time.perf_counter()
     s64 = fem.Solver(mesh, o64).setup(k64)
     setup64 = time.perf_counter() - ts
@@ -580,6 +591,66 @@ def summarize_counters(fdir, wdir, workload, write_traffic):
         print(f"wrote {path}")
 
 
+def run_csr(args, name, w):
+    import torch
+    import fem_inputs
+    from paper_2104_08012_amd import fem
+
+    dev = torch.device("cuda:0")
+    flush = torch.ones(1 << 29, dtype=torch.float32, device=dev)
+    rows = []
+    wall = 0.0
+    for p, n, kvar in w["cases"]:
+        mesh = fem.Mesh(n, 0, p, device=dev)
+        info = mesh.levels[-1]
+        N, C, NV = info["n_dofs"], info["n_cells"], info["n_vertices"]
+        k = torch.as_tensor(fem_inputs.k_exp_fourier(mesh.vertex_coords()), device=dev) if kvar else None
+        th = time.perf_counter()
+        A = fem.CsrOperator(mesh, 0)
+        host_s = time.perf_counter() - th
+        for dt, s in ((torch.float64, 8), (torch.float32, 4)):
+            x = torch.as_tensor(fem_inputs.uniform_vector(N, 0), device=dev).to(dt)
+            y = torch.empty_like(x)
+            kk = None if k is None else k.to(dt)
+            vals = A.assemble(k, dtype=dt)
+            tm = Timer(torch)
+            rec = {}
+            t0 = time.perf_counter()
+            for i in range(args.warmup + args.steps):
+                r = rec if i >= args.warmup else None
+                e = tm.start()
+                A.assemble(k, dtype=dt, out=vals)
+                tm.stop(e, "asm", r)
+                flush.sum()
+                e = tm.start()
+                A.spmv(vals, x, out=y)
+                tm.stop(e, "spmv", r)
+                flush.sum()
+                e = tm.start()
+                mesh.apply(x, kk, out=y)
+                tm.stop(e, "mf", r)
+                tm.collect()
+            wall += time.perf_counter() - t0
+            ts, tmf, ta = mean(rec["spmv"]), mean(rec["mf"]), mean(rec["asm"])
+            B = A.nnz * (s + 4) + 4 * (N + 1) + 2 * N * s
+            rows.append({"degree": p, "n": n, "coefficient": "exp(g)" if kvar else "1",
+                         "dtype": "f64" if s == 8 else "f32", "dofs": N, "nnz": A.nnz,
+                         "spmv_ms_cold": round(ts * 1e3, 4), "spmv_gdofs": round(N / ts / 1e9, 3),
+                         "spmv_bytes": B, "spmv_hbm_frac": round(B / ts / 1e9 / HBM_PEAK_GBS, 4),
+                         "matrix_free_ms_cold": round(tmf * 1e3, 4), "matrix_free_gdofs": round(N / tmf / 1e9, 3),
+                         "assembly_ms": round(ta * 1e3, 3), "pattern_host_s": round(host_s, 2)})
+            del x, y, vals
+        del A, mesh
+        torch.cuda.empty_cache()
+    out = header(args, name, {"description": "assembled CSR operator (GPU element matrices, fixed-order sums, "
+                                             "SpMV) next to the matrix-free action: P1 128^3, P2 64^3 (k = 1), "
+                                             "P3 48^3 (k = exp(g)); Infinity Cache flushed before each product"},
+                 wall)
+    p2 = [r for r in rows if r["degree"] == 2 and r["dtype"] == "f64"][0]
+    out.update({"value": p2["spmv_gdofs"], "unit": "GDoF/s", "csr": rows})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -615,7 +686,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     w = WORKLOADS[args.workload]
-    run = {"solve": run_solve, "adjoint": run_adjoint, "jacobi": run_jacobi, "sweep": run_sweep}[w["kind"]]
+    run = {"solve": run_solve, "adjoint": run_adjoint, "jacobi": run_jacobi, "sweep": run_sweep,
+           "csr": run_csr}[w["kind"]]
     out = run(args, args.workload, w)
     print(json.dumps(out), flush=True)
 

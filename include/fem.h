@@ -140,6 +140,28 @@ fem_status fem_prolong(const fem_mesh* mesh, int32_t fine_level, fem_dtype dtype
 fem_status fem_restrict(const fem_mesh* mesh, int32_t fine_level, fem_dtype dtype,
                         const void* r_fine, void* r_coarse, void* stream);
 
+/* Assembled operator (the representation of the paper's solvers, §4: a sparse matrix and SpMV),
+ * for comparison with the matrix-free action.  fem_csr_create builds on the host the CSR pattern of
+ * A_bc on one level (rows and columns in the library's dof order; int32 row pointers and columns)
+ * and, for every stored entry, the list of element-matrix entries summed into it, in ascending cell
+ * order.  fem_csr_upload copies pattern and lists into a caller-owned device buffer of
+ * device_bytes (256-byte aligned; it also holds the FP64 element-matrix scratch of
+ * C * nloc^2 doubles).  fem_csr_assemble forms the element matrices of A(k) (same quadrature as
+ * the matrix-free action; k_vertex: NULL for k = 1 or FP64 device vertex values) and sums them in
+ * that fixed order into values (nnz entries of dtype, caller-owned device memory): Dirichlet rows
+ * become identity rows and Dirichlet columns zero.  fem_csr_spmv: y = A x (n_rows entries of dtype,
+ * x != y), bitwise reproducible.  Levels whose C * nloc^2 or nnz reach 2^31 are
+ * FEM_ERR_UNSUPPORTED. */
+typedef struct fem_csr fem_csr;
+fem_status fem_csr_create(const fem_mesh* mesh, int32_t level, fem_csr** out);
+fem_status fem_csr_info(const fem_csr* a, int64_t* n_rows, int64_t* nnz, size_t* device_bytes);
+fem_status fem_csr_pattern(const fem_csr* a, int32_t* row_ptr_host, int32_t* col_host);
+fem_status fem_csr_upload(fem_csr* a, void* device, size_t bytes, void* stream);
+fem_status fem_csr_assemble(fem_csr* a, fem_dtype dtype, const double* k_vertex, void* values, void* stream);
+fem_status fem_csr_spmv(const fem_csr* a, fem_dtype dtype, const void* values, const void* x, void* y,
+                        void* stream);
+void fem_csr_destroy(fem_csr* a);
+
 /* Solver */
 enum { FEM_PREC_FP64 = 0, FEM_PREC_MIXED = 1 };
 enum { FEM_COARSE_AUTO = 0, FEM_COARSE_DENSE = 1, FEM_COARSE_NESTED = 2 };

@@ -96,6 +96,13 @@ SIGNATURES = {
     "fem_mg_cg_solve": (_st, [_vp, _vp, _vp, _vp, C.POINTER(SolveOpts), _vp, C.c_size_t,
                               C.POINTER(SolveStats), _vp]),
     "fem_adjoint_grad_k": (_st, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "fem_csr_create": (_st, [_vp, _i32, C.POINTER(_vp)]),
+    "fem_csr_info": (_st, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]),
+    "fem_csr_pattern": (_st, [_vp, _vp, _vp]),
+    "fem_csr_upload": (_st, [_vp, _vp, C.c_size_t, _vp]),
+    "fem_csr_assemble": (_st, [_vp, _i32, _vp, _vp, _vp]),
+    "fem_csr_spmv": (_st, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "fem_csr_destroy": (None, [_vp]),
 }
 
 _lib = None

@@ -168,6 +168,57 @@ class Mesh:
             pass
 
 
+class CsrOperator:
+    """Assembled CSR matrix of A_bc(k) on one mesh level (host pattern, device values)."""
+
+    def __init__(self, mesh: Mesh, level: int = -1, upload: bool = True):
+        self.mesh = mesh
+        self.level = mesh._lev(level)
+        h = C.c_void_p()
+        check(lib().fem_csr_create(mesh.handle, self.level, C.byref(h)), "fem_csr_create")
+        self._h = h
+        n, nnz, nb = C.c_int64(), C.c_int64(), C.c_size_t()
+        check(lib().fem_csr_info(h, C.byref(n), C.byref(nnz), C.byref(nb)), "fem_csr_info")
+        self.n_rows, self.nnz, self.device_bytes = n.value, nnz.value, nb.value
+        self.buffer = None
+        if upload:
+            self.buffer = torch.empty(max(256, self.device_bytes), dtype=torch.uint8, device=mesh.device)
+            check(lib().fem_csr_upload(h, _ptr(self.buffer), self.device_bytes, _stream(mesh.device)),
+                  "fem_csr_upload")
+
+    def pattern(self):
+        rp = np.empty(self.n_rows + 1, dtype=np.int32)
+        col = np.empty(self.nnz, dtype=np.int32)
+        check(lib().fem_csr_pattern(self._h, rp.ctypes.data, col.ctypes.data), "fem_csr_pattern")
+        return rp, col
+
+    def assemble(self, k: torch.Tensor | None = None, dtype=torch.float64, out=None) -> torch.Tensor:
+        if k is not None:
+            _need(k, self.mesh.n_vertices(self.level), torch.float64, "csr k")
+        vals = torch.empty(self.nnz, dtype=dtype, device=self.mesh.device) if out is None else out
+        _need(vals, self.nnz, dtype, "csr values")
+        check(lib().fem_csr_assemble(self._h, _DT[dtype], _ptr(k), _ptr(vals), _stream(vals.device)),
+              "fem_csr_assemble")
+        return vals
+
+    def spmv(self, values: torch.Tensor, x: torch.Tensor, out=None) -> torch.Tensor:
+        _need(values, self.nnz, values.dtype, "csr values")
+        _need(x, self.n_rows, values.dtype, "spmv x")
+        y = torch.empty_like(x) if out is None else out
+        _need(y, self.n_rows, values.dtype, "spmv y")
+        check(lib().fem_csr_spmv(self._h, _DT[values.dtype], _ptr(values), _ptr(x), _ptr(y), _stream(x.device)),
+              "fem_csr_spmv")
+        return y
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().fem_csr_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
 @dataclass
 class SolveOptions:
     rtol: float = 1e-8

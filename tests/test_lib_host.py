@@ -104,3 +104,21 @@ def test_solver_workspace_coarse_choices():
     assert st == L.FEM_ERR_UNSUPPORTED
     st_m, b_m = ws(n_levels_used=2, precision="mixed")          # 16^3 coarse: dense, 31^3 dofs
     assert st_m == 0 and b_m > 31 ** 6 * 8
+
+
+@pytest.mark.parametrize("n,p", [(3, 1), (2, 2), (2, 3), (4, 2)])
+def test_csr_pattern_matches_oracle(n, p):
+    """The host CSR pattern equals the sparsity of the oracle's assembled stiffness matrix (the
+    union of the cells' dof couplings), row by row in the library's (lattice) dof order."""
+    import scipy.sparse as sp
+    from paper_2104_08012_amd import fem
+    from oracle import assemble
+    from oracle import mesh as om
+    m = fem.Mesh(n, 0, p, upload=False)
+    A = fem.CsrOperator(m, 0, upload=False)
+    rp, col = A.pattern()
+    lev = om.single_level(n, p)
+    S = sp.csr_matrix(assemble.stiffness(lev))
+    S.sort_indices()
+    assert A.n_rows == lev.n_dofs and A.nnz == S.nnz
+    assert np.array_equal(rp, S.indptr) and np.array_equal(col, S.indices)
