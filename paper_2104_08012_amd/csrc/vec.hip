@@ -568,6 +568,7 @@ size_t sym_packed_doubles(int64_t n) { return (size_t)sym_tiles(n) * ST * ST; }
 size_t sym_partial_doubles(int64_t n) { return (size_t)2 * sym_tiles(n) * ST; }
 
 void sym_pack_launch(int64_t n, const double* A, double* Ap, hipStream_t s) {
+    if (n <= 0) return;
     hipLaunchKernelGGL(k_sym_pack, dim3((unsigned)sym_tiles(n)), dim3(256), 0, s, n, A, Ap);
 }
 
@@ -575,9 +576,10 @@ void sym_solve_launch(int L, const double* Ap, const double* xl, double* xc, dou
                       hipStream_t s) {
     const int64_t M = L - 2, m = M * M * M, ntl = sym_tiles(m);
     const int nt = (int)((m + ST - 1) / ST);
-    hipLaunchKernelGGL(k_gather_interior, dim3(grid_for(m)), dim3(VT), 0, s, L, xl, xc);
     const int64_t N = (int64_t)L * L * L;
     hipLaunchKernelGGL((k_zero_boundary<double>), dim3(grid_for(N)), dim3(VT), 0, s, L, yl);
+    if (m == 0) return;   // every dof on the boundary
+    hipLaunchKernelGGL(k_gather_interior, dim3(grid_for(m)), dim3(VT), 0, s, L, xl, xc);
     double* prow = part;
     double* pcol = part + ntl * ST;
     hipLaunchKernelGGL(k_sym_tiles, dim3((unsigned)ntl), dim3(256), 0, s, m, Ap, (const double*)xc, prow, pcol);

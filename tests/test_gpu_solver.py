@@ -15,7 +15,7 @@ import pytest
 
 import fem_inputs
 from oracle import assemble, solvers
-from tests.gpu_util import banner, make_pair, rel
+from tests.gpu_util import banner, make_pair, oracle_A, rel
 
 torch = pytest.importorskip("torch")
 
@@ -213,3 +213,33 @@ def test_fmg_matches_oracle(p, kvar, used):
     xm, _ = Sm.fmg(_t(b))
     torch.cuda.synchronize()
     assert rel(xm.cpu().numpy(), x_ref) <= 1e-5
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("p", [1, 2])
+def test_smallest_meshes_and_zero_rhs(p):
+    """Degenerate cases: one cube (P1: no interior dof), a 1-cube coarse level under one
+    refinement (dense coarse block of size 0 for P1), a zero right-hand side, and full multigrid
+    on a single level (the exact coarse solve alone)."""
+    banner(f"smallest meshes p={p}")
+    from paper_2104_08012_amd import fem
+    mesh1, lv1 = make_pair(1, 0, p, 0.0)
+    x = fem_inputs.uniform_vector(lv1[0].n_dofs, 0)
+    y = mesh1.apply(_t(x), level=0)
+    torch.cuda.synchronize()
+    assert rel(y.cpu().numpy(), oracle_A(lv1[0]) @ x) <= 1e-12
+    S1 = fem.Solver(mesh1, fem.SolveOptions(rtol=1e-12)).setup()
+    b1 = _rhs(lv1[0])
+    u1, r1 = S1.fmg(_t(b1))
+    torch.cuda.synchronize()
+    assert rel(u1.cpu().numpy(), solvers.direct_solve(oracle_A(lv1[0]), b1)) <= 1e-12 or np.linalg.norm(b1) == 0
+    mesh, levels = make_pair(1, 1, p, 0.0)
+    lev = levels[-1]
+    b = _rhs(lev)
+    S = fem.Solver(mesh, fem.SolveOptions(rtol=1e-12)).setup()
+    u, res = S.solve(_t(b))
+    torch.cuda.synchronize()
+    assert rel(u.cpu().numpy(), solvers.direct_solve(oracle_A(lev), b)) <= 1e-10
+    z, rz = S.solve(torch.zeros(lev.n_dofs, dtype=torch.float64, device="cuda:0"))
+    torch.cuda.synchronize()
+    assert rz.iterations == 0 and float(z.abs().max()) == 0.0
