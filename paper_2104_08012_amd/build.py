@@ -31,7 +31,7 @@ def _flags():
     return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function",
-            "-Wno-unused-variable", "-Wno-unused-command-line-argument"]
+            "-Wno-unused-command-line-argument"]
 
 
 def _compile(src: str) -> str:

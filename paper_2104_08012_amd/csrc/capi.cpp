@@ -91,9 +91,6 @@ fem_status fem_mesh_upload(fem_mesh* m, void* dev, size_t bytes, void* stream) {
         return hipMemcpyAsync(base + off, src, nbytes, hipMemcpyHostToDevice, s);
     };
     hipError_t e = hipSuccess;
-    for (const auto& t : m->red) {
-        if (e == hipSuccess) e = put(t.d_first, t.first.data(), t.first.size() * 4);
-    }
     for (const auto& T : m->tab) {
         if (e == hipSuccess) e = put(T.d64, T.t64.data(), T.t64.size() * 8);
         if (e == hipSuccess) e = put(T.d32, T.t32.data(), T.t32.size() * 4);

@@ -60,7 +60,7 @@ __device__ __forceinline__ double recip(double d) {
 template <int P, int B, bool KVAR, typename T>
 __global__ void __launch_bounds__(B * B * B, FEM_CUBE_MIN_WAVES) k_cube_apply(SArgs<T> a) {
     constexpr int NL = nloc_of(P), NQ = nq_of(P, KVAR), PC = P + 1, NCP = PC * PC * PC;
-    constexpr int NT = B * B * B, PB = P * B, QS = PB + 1, Q = QS * QS * QS;
+    constexpr int NT = B * B * B, PB = P * B, QS = PB + 1;
     constexpr StiffTab<P, KVAR> TB{};
     constexpr CubeNodes<P> CN{};
     constexpr int ZERO = NCP * NT;

@@ -77,23 +77,4 @@ struct Incidence {
     }
 };
 
-// Compact index of a point on the boundary of the box [0, PB]^3 (QS = PB + 1 points per edge):
-// the two z faces, then the two y faces without their z edges, then the two x faces without
-// y or z edges.  Total QB = QS^3 - (QS - 2)^3.
-template <int PB>
-FEM_HD constexpr int box_slot(int a, int b, int c) {
-    constexpr int QS = PB + 1, QI = QS - 2;
-    if (c == 0) return a + QS * b;
-    if (c == PB) return QS * QS + a + QS * b;
-    if (b == 0) return 2 * QS * QS + a + QS * (c - 1);
-    if (b == PB) return 2 * QS * QS + QS * QI + a + QS * (c - 1);
-    if (a == 0) return 2 * QS * QS + 2 * QS * QI + (b - 1) + QI * (c - 1);
-    return 2 * QS * QS + 2 * QS * QI + QI * QI + (b - 1) + QI * (c - 1);
-}
-
-template <int PB>
-FEM_HD constexpr int box_slots() {
-    return (PB + 1) * (PB + 1) * (PB + 1) - (PB - 1) * (PB - 1) * (PB - 1);
-}
-
 }  // namespace fem

@@ -39,8 +39,6 @@ struct RedTable {
     int po = 0, B = 0, NC = 0, Q = 0, QB = 0;
     std::vector<int32_t> off, ent, slot;
     std::vector<int32_t> q_of;  // (cl * nloc(po) + i) -> q, used by the host validation
-    std::vector<int32_t> first; // per q: the first contribution, packed (i << 16) | cl
-    size_t d_first = 0;
 };
 
 // Quadrature tabulation for the stiffness-type kernels of degree p:

@@ -73,11 +73,6 @@ static void build_red(RedTable& t, int po, int B) {
     }
     t.off[t.Q] = (int32_t)t.ent.size();
     t.QB = nslot;
-    t.first.assign(t.Q, 0);
-    for (int q = 0; q < t.Q; ++q) {
-        const int e0 = t.ent[t.off[q]];
-        t.first[q] = ((e0 / t.NC) << 16) | (e0 % t.NC);
-    }
 }
 
 static int find_red(fem_mesh& m, int po, int B) {
@@ -343,9 +338,6 @@ fem_status build_mesh(const fem_mesh_desc& d, fem_mesh& m) {
         off = align256(off + bytes);
         return o;
     };
-    for (auto& t : m.red) {
-        t.d_first = take(t.first.size() * 4);
-    }
     for (auto& T : m.tab) {
         T.d64 = take(T.t64.size() * 8);
         T.d32 = take(T.t32.size() * 4);

@@ -96,7 +96,6 @@ fem_status run_kind(const fem_mesh& m, int level, bool kvar, const ScatterIO<T>&
     a.fine_mi = dptr<int32_t>(m, m.d_fine_mi);
     a.owner = (KIND == K_RESTRICT) ? dptr<uint32_t>(m, L.d_owner) : nullptr;
     a.slots = const_cast<T*>(dptr<T>(m, L.d_slots));
-    a.gfirst = dptr<int32_t>(m, m.red[L.red].d_first);
     a.mask_cols = io.mask_cols;
     a.Lin = (KIND == K_RESTRICT) ? m.lev[level + 1].L : 0;
     a.x = io.x;

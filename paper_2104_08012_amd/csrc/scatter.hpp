@@ -43,7 +43,6 @@ struct SArgs {
     const uint32_t* owner;           // restriction: SoA owner masks of the coarse cells
     T* slots;                        // interface partials: 8 arrays (side code) x if_tot points
     uint32_t if_c0, if_c01, if_tot;  // interface points on x planes; + y planes; + z planes
-    const int32_t* gfirst;           // per brick closure point: first (node, cell) reaching it
     int mask_cols;                   // gather boundary dofs as zero
     int Lin;                         // restriction: fine lattice size
     const T* x;                      // input field (u for the gradient)
@@ -328,7 +327,7 @@ __device__ __forceinline__ void reduce_type(const SArgs<T>& a, const T* ys, int 
     constexpr int ta = TY % PO, tb = (TY / PO) % PO, tc = TY / (PO * PO);
     constexpr int ea = B + (ta == 0), eb = B + (tb == 0), ec = B + (tc == 0);
     constexpr int NPTS = ea * eb * ec, CNT = INC.cnt[TY];
-    constexpr int NC = 6 * B * B * B, NT = brick_threads(B), PB = PO * B, QB = box_slots<PB>();
+    constexpr int NC = 6 * B * B * B, NT = brick_threads(B), PB = PO * B;
     const int64_t L = a.Lout;
     for (int idx = threadIdx.x; idx < NPTS; idx += NT) {
         const int ka = idx % ea, kb = (idx / ea) % eb, kc = idx / (ea * eb);
@@ -394,7 +393,7 @@ struct FixGeom {
 
 template <int PO, int B, typename T>
 __global__ void __launch_bounds__(256) k_fixup(SArgs<T> a, FixGeom fg) {
-    constexpr int PB = PO * B, QB = box_slots<PB>();
+    constexpr int PB = PO * B;
     const uint32_t t = blockIdx.x * 256u + threadIdx.x;
     if (t >= fg.total) return;
     const uint32_t L = fg.L.d, nb = (uint32_t)a.nb, np = fg.np.d;

@@ -69,16 +69,6 @@ __global__ void k_axpby(int64_t n, double a, const T* __restrict__ x, double b, 
     if (i < n) y[i] = (T)(a * (double)x[i] + b * (double)y[i]);
 }
 
-// x += alpha p ; r -= alpha q  (FP64 CG update)
-__global__ void k_cg_update(int64_t n, double alpha, const double* __restrict__ p, const double* __restrict__ q,
-                            double* __restrict__ x, double* __restrict__ r) {
-    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
-    if (i < n) {
-        x[i] += alpha * p[i];
-        r[i] -= alpha * q[i];
-    }
-}
-
 // Device-resident CG scalars (indices into the solver's scalar block, see vec.hpp).
 // alpha = rz / pq, or 0 with flag bit 1 when p^T A p is not positive and finite.
 __global__ void k_cg_alpha(double* sc) {
@@ -453,10 +443,6 @@ void axpby_launch(int64_t n, double a, const T* x, double b, T* y, hipStream_t s
 template void axpby_launch<double>(int64_t, double, const double*, double, double*, hipStream_t);
 template void axpby_launch<float>(int64_t, double, const float*, double, float*, hipStream_t);
 
-void cg_update_launch(int64_t n, double alpha, const double* p, const double* q, double* x, double* r, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_update, dim3(grid_for(n)), dim3(VT), 0, s, n, alpha, p, q, x, r);
-}
-
 void cg_alpha_launch(double* sc, hipStream_t s) { hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64), 0, s, sc); }
 void cg_beta_launch(double* sc, bool flexible, hipStream_t s) {
     hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64), 0, s, sc, flexible ? 1 : 0);
@@ -587,12 +573,5 @@ void sym_solve_launch(int L, const double* Ap, const double* xl, double* xc, dou
                        (const double*)pcol, yl);
 }
 
-template <typename T>
-void zero_boundary_launch(int L, T* y, hipStream_t s) {
-    const int64_t N = (int64_t)L * L * L;
-    hipLaunchKernelGGL((k_zero_boundary<T>), dim3(grid_for(N)), dim3(VT), 0, s, L, y);
-}
-template void zero_boundary_launch<double>(int, double*, hipStream_t);
-template void zero_boundary_launch<float>(int, float*, hipStream_t);
 
 }  // namespace fem

@@ -22,7 +22,6 @@ size_t dot_partial_doubles();
 
 template <typename T>
 void axpby_launch(int64_t n, double a, const T* x, double b, T* y, hipStream_t s);
-void cg_update_launch(int64_t n, double alpha, const double* p, const double* q, double* x, double* r, hipStream_t s);
 
 // CG scalars kept on the device (slots of the solver's scalar block), so that an iteration needs
 // no host round trip: alpha = rz / pq; beta and rz <- rz_new; flag bits 1 (p^T A p <= 0) and
@@ -61,7 +60,5 @@ size_t sym_partial_doubles(int64_t n);
 void sym_pack_launch(int64_t n, const double* A, double* Ap, hipStream_t s);
 void sym_solve_launch(int L, const double* Ap, const double* xl, double* xc, double* part, double* yl,
                       hipStream_t s);
-template <typename T>
-void zero_boundary_launch(int L, T* y, hipStream_t s);
 
 }  // namespace fem
