@@ -153,9 +153,15 @@ def roofline(p, kvar, C, N, NV, s, t, key):
 
 
 def cpu_baseline(n, p, kvar, max_seconds=30.0):
-    """The oracle's matrix-free FP64 action (numpy, one thread).  Levels above 2^21 cells are
-    sampled by a 64^3 mesh of the same degree (the oracle's cost is linear in the cells)."""
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    """The oracle's matrix-free FP64 action (numpy, one thread: BLAS pools limited to one thread).
+    Levels above 2^21 cells are sampled by a 64^3 mesh of the same degree (the oracle's cost is
+    linear in the cells)."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        return _cpu_baseline(n, p, kvar, max_seconds)
+
+
+def _cpu_baseline(n, p, kvar, max_seconds):
     import fem_inputs
     from oracle import assemble
     from oracle import mesh as om
