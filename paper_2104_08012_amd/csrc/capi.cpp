@@ -105,7 +105,6 @@ fem_status fem_mesh_upload(fem_mesh* m, void* dev, size_t bytes, void* stream) {
         if (e == hipSuccess) e = put(L.d_G64, L.G64.data(), L.G64.size() * 8);
         if (e == hipSuccess) e = put(L.d_G32, L.G32.data(), L.G32.size() * 4);
         if (e == hipSuccess) e = put(L.d_owner, L.owner.data(), L.owner.size() * 4);
-        if (e == hipSuccess) e = put(L.d_cmap, L.cmap.data(), L.cmap.size() * 4);
         if (e == hipSuccess) e = put(L.d_vsoa, L.vsoa.data(), L.vsoa.size() * 8);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -2,21 +2,25 @@
 //
 // Same result and the same deterministic two-kernel scheme as k_brick (brick workgroups, interior
 // points written directly, brick-face points through interface slots and k_fixup), organised to
-// cut memory traffic and instructions on gfx950's 64-wide VALU:
-//  * a thread gathers the cube's (p+1)^3 distinct dofs once (8 for P1, 27 for P2) through a per-cube
-//    structure-of-arrays dof map (entry j of every cube contiguous), instead of 6 nloc per-cell
-//    gathers;
-//  * the geometry is computed in the kernel from the FP64 coordinates of the cube's 8 vertices:
-//    for each tetrahedron the edge vectors e1, e2, e3 from its first vertex, the cofactor rows
-//    c1 = e2 x e3, c2 = e3 x e1, c3 = e1 x e2 (so that J^-1 has rows c_a / det), det = e1 . c1,
-//    and G = |det| J^-1 J^-T = [c_a . c_b] / |det|.  No per-cell geometric factors are read;
-//  * the six cells' contributions accumulate in registers at the cube's lattice points (the
-//    node-to-point map is a compile-time table);
-//  * quadrature tabulations are literals, so zero gradient entries generate no instructions;
-//  * the cubes' point values go to LDS once; then each closure point of the brick sums the values
-//    of the (up to 8) cubes containing it in a fixed order (so the result is reproducible), one
-//    lane per row of points along x with the x loop unrolled; the sums return to LDS and are
-//    written with consecutive lanes on consecutive points, so stores to y are contiguous runs;
+// cut memory instructions, registers and LDS on gfx950's 64-wide VALU:
+//  * one wave per brick of 4^3 cubes, lane = lx + 4 ly + 16 lz;
+//  * the dofs of a level are numbered by their lattice point, g = I + L (J + L K) with L = p n + 1,
+//    and the boundary is the lattice boundary, so no dof map is read: the wave loads the brick's
+//    closure of (4p + 1)^3 values of x (boundary values as zero when columns are masked) and the
+//    5^3 vertex coordinates of the brick into LDS, with consecutive lanes on consecutive points;
+//  * per tetrahedron each lane reads its corners and its nodes' values from LDS at compile-time
+//    offsets from one lane base, computes the geometry in FP64 from the cofactor rows
+//    c1 = e2 x e3, c2 = e3 x e1, c3 = e1 x e2 of the edge vectors (J^-1 has rows c_a / det,
+//    det = e1 . c1, G = |det| J^-1 J^-T = [c_a . c_b] / |det|), and accumulates the cell's
+//    contributions in registers at the cube's (p+1)^3 lattice points (compile-time node-to-point
+//    table, literal tabulations, zero gradient entries generate no instructions);
+//  * the cubes' point values are summed across lanes in three passes with cross-lane moves (DPP
+//    within a row of 16 lanes for x and y, ds_bpermute for z): after pass d, the point at local
+//    index 0 along d of every cube above the first holds the sum with the cube below, so each
+//    brick closure point ends in exactly one lane with the sum over the brick's cubes containing
+//    it, in a fixed order (bitwise reproducible);
+//  * the sums go to the LDS closure array and are written with consecutive lanes on consecutive
+//    points: interior points to y (contiguous runs), brick-face points to their slots;
 //  * loads use 32-bit offsets from uniform bases (the host keeps such levels below 4 GiB per array).
 #pragma once
 #include "scatter.hpp"
@@ -30,20 +34,6 @@ __device__ __forceinline__ T ldg(const T* base, uint32_t idx) {
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)(idx * (uint32_t)sizeof(T)));
 }
 
-// Contributions along one axis to closure coordinate l of a brick (lattice spacing h/P, cubes
-// 0..B-1): the cube with l / P and local index l % P, and, where l is a cube boundary above the
-// first, also the cube below with local index P.  off = local index * sj * B^3 + cube * sc is the
-// axis's share of the LDS offset (sj, sc: strides of the local point and cube indices).
-template <int P, int B>
-__device__ __forceinline__ void axis_terms(int l, int sj, int sc, int off[2], bool valid[2]) {
-    constexpr int NT = B * B * B;
-    const int c0 = l / P, a0 = l % P;
-    valid[0] = c0 < B;
-    off[0] = a0 * sj * NT + c0 * sc;
-    valid[1] = a0 == 0 && c0 > 0;
-    off[1] = P * sj * NT + (c0 - 1) * sc;
-}
-
 // 1 / d from the hardware reciprocal refined by two Newton steps r <- r + r (1 - d r) (quadratic
 // convergence: well below an ulp of error left for the accuracy the kernels need).
 __device__ __forceinline__ double recip(double d) {
@@ -54,64 +44,150 @@ __device__ __forceinline__ double recip(double d) {
     return fma(r, e, r);
 }
 
-#ifndef FEM_CUBE_MIN_WAVES
-#define FEM_CUBE_MIN_WAVES 2
-#endif
+// Cross-lane moves.  DPP row_shr:4 gives lane l the value of lane l - 4 inside its row of 16 lanes
+// and the old value (zero) to the first four lanes of a row; quad_perm [0,0,1,2] gives lane l the
+// value of lane l - 1 inside its quad (the first lane of a quad reads itself and is masked by the
+// caller); ds_bpermute reads any lane.
+template <int CTRL>
+__device__ __forceinline__ int dpp32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __builtin_bit_cast(float, dpp32<CTRL>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)dpp32<CTRL>((int)(uint32_t)b), hi = (uint32_t)dpp32<CTRL>((int)(uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ float lane_read(int addr, float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double lane_read(int addr, double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)b);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+// closure offset of cube point j = (ja, jb, jc) (ja fastest, P + 1 per axis) and LDS offset of
+// cube corner j (corner j at (j & 1, j >> 1 & 1, j >> 2)) in the brick's 5^3 vertex block
+template <int P, int QS>
+__host__ __device__ constexpr int xo_of(int j) {
+    return j % (P + 1) + QS * ((j / (P + 1)) % (P + 1) + QS * (j / ((P + 1) * (P + 1))));
+}
+template <int VS>
+__host__ __device__ constexpr int vo_of(int j) {
+    return (j & 1) + VS * (((j >> 1) & 1) + VS * (j >> 2));
+}
+
+constexpr int kQuadPrev = 0 | (0 << 2) | (1 << 4) | (2 << 6);   // quad_perm [0, 0, 1, 2]
+constexpr int kRowShr4 = 0x114;                                  // row_shr:4
+
+// Waves per SIMD the register allocation is held to (512 VGPRs per SIMD lane): what each variant
+// fits without spilling, the FP64 P2 accumulators (27 doubles) being the largest live state.
+template <int P, bool KVAR, typename T>
+constexpr int cube_min_waves() {
+    return (P == 1 || (sizeof(T) == 4 && !KVAR)) ? 4 : (sizeof(T) == 4 || !KVAR) ? 3 : 2;
+}
+
 template <int P, int B, bool KVAR, typename T>
-__global__ void __launch_bounds__(B * B * B, FEM_CUBE_MIN_WAVES) k_cube_apply(SArgs<T> a) {
+__global__ void __launch_bounds__(B * B * B, (cube_min_waves<P, KVAR, T>())) k_cube_apply(SArgs<T> a) {
+    static_assert(B == 4, "one wave per brick of 4^3 cubes");
     constexpr int NL = nloc_of(P), NQ = nq_of(P, KVAR), PC = P + 1, NCP = PC * PC * PC;
-    constexpr int NT = B * B * B, PB = P * B, QS = PB + 1;
+    constexpr int NT = B * B * B, PB = P * B, QS = PB + 1, NQ3 = QS * QS * QS;
+    constexpr int VS = B + 1, NV3 = VS * VS * VS;
     constexpr StiffTab<P, KVAR> TB{};
     constexpr CubeNodes<P> CN{};
-    constexpr int ZERO = NCP * NT;
-    __shared__ T part[NCP * NT + 1];   // cube point j of cube c at part[j * NT + c]; last: zero
+    __shared__ T xc[NQ3];            // closure values: x on input, the brick's sums on output
+    __shared__ double vc[3][NV3];    // vertex coordinates of the brick's 5^3 vertices
+    __shared__ T kl[KVAR ? NV3 : 1];  // coefficient at those vertices
     const int brick = brick_of_block(blockIdx.x, gridDim.x);
     const int nb = a.nb;
     const int bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
-    const int cube = threadIdx.x;
-    const int lx = cube % B, ly = (cube / B) % B, lz = cube / (B * B);
+    const int lane = threadIdx.x;
+    const int lx = lane % B, ly = (lane / B) % B, lz = lane / (B * B);
+    const uint32_t Lo = (uint32_t)a.Lout;
 
-    const uint32_t NCB = a.ncube;
-    const uint32_t cid = (uint32_t)(brick * NT + cube);
-    // gather the cube's distinct dofs
-    T xs[NCP];
-#pragma unroll
-    for (int j = 0; j < NCP; ++j) {
-        const int32_t m = ldg(a.cmap, (uint32_t)j * NCB + cid);
-        const T v = ldg(a.x, (uint32_t)m & 0x7fffffffu);
-        xs[j] = (a.mask_cols && m < 0) ? T(0) : v;
-    }
-    // corner coordinates relative to corner 0 (corner j at offset (j & 1, j >> 1 & 1, j >> 2))
-    const uint32_t n1 = (uint32_t)a.n + 1, NV = a.nv;
-    const uint32_t v0 = (uint32_t)(bx * B + lx) + n1 * ((uint32_t)(by * B + ly) + n1 * (uint32_t)(bz * B + lz));
-    double D[8][3];
+    // ---- stage the brick's closure values of x and its vertex data in LDS ----
+    // (all loads are issued before the first LDS store; indices past the end are clamped)
+    const uint32_t gb = (uint32_t)(bx * PB) + Lo * ((uint32_t)(by * PB) + Lo * (uint32_t)(bz * PB));
     {
-        const double p0x = ldg(a.vxyz, v0), p0y = ldg(a.vxyz, NV + v0), p0z = ldg(a.vxyz, 2 * NV + v0);
+        constexpr int NIT = (NQ3 + NT - 1) / NT;
+        T v[NIT];
 #pragma unroll
-        for (int j = 1; j < 8; ++j) {
-            const uint32_t v = v0 + (uint32_t)(j & 1) + n1 * ((uint32_t)((j >> 1) & 1) + n1 * (uint32_t)(j >> 2));
-            D[j][0] = ldg(a.vxyz, v) - p0x;
-            D[j][1] = ldg(a.vxyz, NV + v) - p0y;
-            D[j][2] = ldg(a.vxyz, 2 * NV + v) - p0z;
+        for (int it = 0; it < NIT; ++it) {
+            const int r = (lane + NT * it < NQ3) ? lane + NT * it : NQ3 - 1;
+            const int la = r % QS, q = r / QS, lb = q % QS, lc = q / QS;
+            v[it] = ldg(a.x, gb + (uint32_t)la + Lo * ((uint32_t)lb + Lo * (uint32_t)lc));
+        }
+        const uint32_t n1 = (uint32_t)a.n + 1, NV = a.nv;
+        const uint32_t vb = (uint32_t)(bx * B) + n1 * ((uint32_t)(by * B) + n1 * (uint32_t)(bz * B));
+        constexpr int NVIT = (NV3 + NT - 1) / NT;
+        double cx[NVIT], cy[NVIT], cz[NVIT];
+        T kv[NVIT];
+#pragma unroll
+        for (int it = 0; it < NVIT; ++it) {
+            const int r = (lane + NT * it < NV3) ? lane + NT * it : NV3 - 1;
+            const uint32_t w = vb + (uint32_t)(r % VS) + n1 * ((uint32_t)((r / VS) % VS) + n1 * (uint32_t)(r / (VS * VS)));
+            cx[it] = ldg(a.vxyz, w);
+            cy[it] = ldg(a.vxyz, NV + w);
+            cz[it] = ldg(a.vxyz, 2 * NV + w);
+            if constexpr (KVAR) kv[it] = ldg(a.k, w);
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it)
+            if (lane + NT * it < NQ3) xc[lane + NT * it] = v[it];
+#pragma unroll
+        for (int it = 0; it < NVIT; ++it) {
+            const int r = lane + NT * it;
+            if (r < NV3) {
+                vc[0][r] = cx[it];
+                vc[1][r] = cy[it];
+                vc[2][r] = cz[it];
+                if constexpr (KVAR) kl[r] = kv[it];
+            }
+        }
+        // masked columns: zero the closure faces that lie on the domain boundary
+        if (a.mask_cols && (bx == 0 || by == 0 || bz == 0 || bx == nb - 1 || by == nb - 1 || bz == nb - 1)) {
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                const int d = f >> 1, hi = f & 1;
+                const int bd = d == 0 ? bx : d == 1 ? by : bz;
+                if (bd != (hi ? nb - 1 : 0)) continue;
+                for (int r = lane; r < QS * QS; r += NT) {
+                    const int u = r % QS, w = r / QS, e = hi ? PB : 0;
+                    const int idx = d == 0 ? e + QS * (u + QS * w) : d == 1 ? u + QS * (e + QS * w) : u + QS * (w + QS * e);
+                    xc[idx] = T(0);
+                }
+            }
         }
     }
-    T kc[8];
-    if constexpr (KVAR) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-            kc[j] = ldg(a.k, v0 + (uint32_t)(j & 1) + n1 * ((uint32_t)((j >> 1) & 1) + n1 * (uint32_t)(j >> 2)));
-    }
+    __syncthreads();
+
+    // ---- the six tetrahedra of the lane's cube ----
+    const int xb = P * lx + QS * (P * ly + QS * P * lz);   // closure index of the cube's point 0
+    const int vbl = lx + VS * (ly + VS * lz);              // vertex index of the cube's corner 0
     T ys[NCP];
 #pragma unroll
     for (int j = 0; j < NCP; ++j) ys[j] = T(0);
 #pragma unroll
     for (int t = 0; t < 6; ++t) {
-        // path tetrahedron: v0 = corner 0, v1 = e_s0, v2 = e_s0 + e_s1, v3 = corner 7
+        // keep the LDS reads inside each tetrahedron, so they are not held in registers across it
+        __asm__ volatile("" ::: "memory");
+        // path tetrahedron: v0 = corner 0, v1 = e_s0, v2 = e_s0 + e_s1, v3 = corner 7 (corner j
+        // at offset (j & 1, j >> 1 & 1, j >> 2))
         const int s0 = perm_axis(t, 0), s1 = perm_axis(t, 1);
         const int j1 = 1 << s0, j2 = (1 << s0) | (1 << s1);
-        const double* e1 = D[j1];
-        const double* e2 = D[j2];
-        const double* e3 = D[7];
+        double e1[3], e2[3], e3[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double p0 = vc[d][vbl];
+            e1[d] = vc[d][vbl + vo_of<VS>(j1)] - p0;
+            e2[d] = vc[d][vbl + vo_of<VS>(j2)] - p0;
+            e3[d] = vc[d][vbl + vo_of<VS>(7)] - p0;
+        }
         const double c1x = e2[1] * e3[2] - e2[2] * e3[1], c1y = e2[2] * e3[0] - e2[0] * e3[2],
                      c1z = e2[0] * e3[1] - e2[1] * e3[0];
         const double c2x = e3[1] * e1[2] - e3[2] * e1[1], c2y = e3[2] * e1[0] - e3[0] * e1[2],
@@ -127,12 +203,16 @@ __global__ void __launch_bounds__(B * B * B, FEM_CUBE_MIN_WAVES) k_cube_apply(SA
         const T g01 = T((c1x * c2x + c1y * c2y + c1z * c2z) * inv);
         const T g02 = T((c1x * c3x + c1y * c3y + c1z * c3z) * inv);
         const T g12 = T((c2x * c3x + c2y * c3y + c2z * c3z) * inv);
+        // the cell's nodal values (cube point j = (ja, jb, jc) at closure offset ja + QS (jb + QS jc))
+        T xs[NL];
+#pragma unroll
+        for (int i = 0; i < NL; ++i) xs[i] = xc[xb + xo_of<P, QS>(CN.cp[t][i])];
         T kt[4];
         if constexpr (KVAR) {
-            kt[0] = kc[0];
-            kt[1] = kc[j1];
-            kt[2] = kc[j2];
-            kt[3] = kc[7];
+            kt[0] = kl[vbl];
+            kt[1] = kl[vbl + vo_of<VS>(j1)];
+            kt[2] = kl[vbl + vo_of<VS>(j2)];
+            kt[3] = kl[vbl + vo_of<VS>(7)];
         }
         if constexpr (P == 2 && !KVAR) {
             // reference gradient at the vertices, w_v = G g_v, mixed by the P1 mass matrix
@@ -144,10 +224,9 @@ __global__ void __launch_bounds__(B * B * B, FEM_CUBE_MIN_WAVES) k_cube_apply(SA
                 T gx = T(0), gy = T(0), gz = T(0);
 #pragma unroll
                 for (int i = 0; i < NL; ++i) {
-                    const T xv = xs[CN.cp[t][i]];
-                    if (VG.D[v][0][i] != 0.0) gx += T(VG.D[v][0][i]) * xv;
-                    if (VG.D[v][1][i] != 0.0) gy += T(VG.D[v][1][i]) * xv;
-                    if (VG.D[v][2][i] != 0.0) gz += T(VG.D[v][2][i]) * xv;
+                    if (VG.D[v][0][i] != 0.0) gx += T(VG.D[v][0][i]) * xs[i];
+                    if (VG.D[v][1][i] != 0.0) gy += T(VG.D[v][1][i]) * xs[i];
+                    if (VG.D[v][2][i] != 0.0) gz += T(VG.D[v][2][i]) * xs[i];
                 }
                 hx[v] = g00 * gx + g01 * gy + g02 * gz;
                 hy[v] = g01 * gx + g11 * gy + g12 * gz;
@@ -178,10 +257,9 @@ __global__ void __launch_bounds__(B * B * B, FEM_CUBE_MIN_WAVES) k_cube_apply(SA
                 T gx = T(0), gy = T(0), gz = T(0);
 #pragma unroll
                 for (int i = 0; i < NL; ++i) {
-                    const T xv = xs[CN.cp[t][i]];
-                    if (TB.D[q][0][i] != 0.0) gx += T(TB.D[q][0][i]) * xv;
-                    if (TB.D[q][1][i] != 0.0) gy += T(TB.D[q][1][i]) * xv;
-                    if (TB.D[q][2][i] != 0.0) gz += T(TB.D[q][2][i]) * xv;
+                    if (TB.D[q][0][i] != 0.0) gx += T(TB.D[q][0][i]) * xs[i];
+                    if (TB.D[q][1][i] != 0.0) gy += T(TB.D[q][1][i]) * xs[i];
+                    if (TB.D[q][2][i] != 0.0) gz += T(TB.D[q][2][i]) * xs[i];
                 }
                 T s = T(TB.w[q]);
                 if constexpr (KVAR)
@@ -201,93 +279,75 @@ __global__ void __launch_bounds__(B * B * B, FEM_CUBE_MIN_WAVES) k_cube_apply(SA
             }
         }
     }
+
+    // ---- sums over the brick's cubes, one axis at a time ----
+    // x: point (0, b, c) of cube lx > 0 adds point (P, b, c) of cube lx - 1
 #pragma unroll
-    for (int j = 0; j < NCP; ++j) part[j * NT + cube] = ys[j];
-    if (cube == 0) part[NCP * NT] = T(0);
-    __syncthreads();
-    // Closure points of the brick, each the sum of the values of the (up to 8) cubes containing it
-    // in a fixed order (absent terms read a zero entry, so the sum is branch-free).  The sums are
-    // formed one lane per row of points along x (interior rows, then the rows on the brick's y and
-    // z faces) with the x loop unrolled, so its cube terms are compile-time constants; the rows
-    // are then put back in LDS in closure order and written with consecutive lanes on
-    // consecutive points: interior points to y (contiguous runs), face points to their slots.
-    constexpr int QI = PB - 1, NFR = QS * QS - QI * QI;
-    T rowv[2][QS];
-    int rowq[2];
+    for (int j = 0; j < PC * PC; ++j) {
+        const T v = dpp_move<kQuadPrev>(ys[P + PC * j]);
+        ys[PC * j] += (lx == 0) ? T(0) : v;
+    }
+    // y: point (a, 0, c) of cube ly > 0 adds point (a, P, c) of cube ly - 1 (lanes with ly = 0
+    // receive zero from the row shift)
 #pragma unroll
-    for (int round = 0; round < 2; ++round) {
-        const int r = threadIdx.x;
-        int lb = 0, lc = 0;
-        rowq[round] = -1;
-        if (round == 0) {
-            if (r >= QI * QI) continue;
-            lb = 1 + r % QI;
-            lc = 1 + r / QI;
-        } else {
-            if (r >= NFR) continue;
-            if (r < 2 * QS) {                 // z faces: lc = 0 or PB, all lb
-                lb = r % QS;
-                lc = r < QS ? 0 : PB;
-            } else {                          // y faces: lb = 0 or PB, lc inside
-                const int u = r - 2 * QS;
-                lc = 1 + u % QI;
-                lb = u < QI ? 0 : PB;
-            }
-        }
-        rowq[round] = QS * (lb + QS * lc);
-        int oy[2], oz[2];
-        bool vy[2], vz[2];
-        axis_terms<P, B>(lb, PC, B, oy, vy);
-        axis_terms<P, B>(lc, PC * PC, B * B, oz, vz);
-        int oyz[4];
+    for (int c = 0; c < PC; ++c)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) oyz[k] = (vy[k & 1] && vz[k >> 1]) ? oy[k & 1] + oz[k >> 1] : -1;
+        for (int a0 = 0; a0 < PC; ++a0) ys[a0 + PC * PC * c] += dpp_move<kRowShr4>(ys[a0 + PC * (P + PC * c)]);
+    // z: point (a, b, 0) of cube lz > 0 adds point (a, b, P) of cube lz - 1
+    {
+        const int addr = 4 * (lz == 0 ? lane : lane - B * B);
 #pragma unroll
-        for (int la = 0; la < QS; ++la) {
-            const int cx = la / P, ax = la % P;
-            T v = T(0);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (cx < B) v += part[oyz[k] >= 0 ? oyz[k] + ax * NT + cx : ZERO];
-                if (ax == 0 && cx > 0) v += part[oyz[k] >= 0 ? oyz[k] + P * NT + cx - 1 : ZERO];
-            }
-            rowv[round][la] = v;
+        for (int j = 0; j < PC * PC; ++j) {
+            const T v = lane_read(addr, ys[j + PC * PC * P]);
+            ys[j] += (lz == 0) ? T(0) : v;
         }
     }
+    // Each closure point (la, lb, lc) of the brick is now held by the cube min(la / P, B - 1)
+    // (and likewise in y, z) at local index la - P * that cube.
     __syncthreads();
 #pragma unroll
-    for (int round = 0; round < 2; ++round)
-        if (rowq[round] >= 0)
-#pragma unroll
-            for (int la = 0; la < QS; ++la) part[rowq[round] + la] = rowv[round][la];
-    __syncthreads();
-    const int64_t L = a.Lout;
-    constexpr int NIN = QI * QI * QI;
-    for (int r = threadIdx.x; r < NIN; r += NT) {
-        const int la = 1 + r % QI, lb = 1 + (r / QI) % QI, lc = 1 + r / (QI * QI);
-        const int64_t g = (bx * PB + la) + L * ((by * PB + lb) + L * (int64_t)(bz * PB + lc));
-        finalize(a, g, part[la + QS * (lb + QS * lc)], false);
+    for (int j = 0; j < NCP; ++j) {
+        const int ja = j % PC, jb = (j / PC) % PC, jc = j / (PC * PC);
+        if ((ja < P || lx == B - 1) && (jb < P || ly == B - 1) && (jc < P || lz == B - 1))
+            xc[xb + xo_of<P, QS>(j)] = ys[j];
     }
-    constexpr int NZF = 2 * QS * QS, NYF = 2 * QS * QI, NXF = 2 * QI * QI;
-    for (int r = threadIdx.x; r < NZF + NYF + NXF; r += NT) {
-        int la, lb, lc;
-        if (r < NZF) {                       // z faces: all (la, lb)
-            const int u = r % (QS * QS);
-            la = u % QS;
-            lb = u / QS;
-            lc = r < QS * QS ? 0 : PB;
-        } else if (r < NZF + NYF) {          // y faces: all la, lc inside
-            const int u = (r - NZF) % (QS * QI);
-            la = u % QS;
-            lc = 1 + u / QS;
-            lb = r - NZF < QS * QI ? 0 : PB;
-        } else {                             // x faces: lb, lc inside
-            const int u = (r - NZF - NYF) % (QI * QI);
-            lb = 1 + u % QI;
-            lc = 1 + u / QI;
-            la = r - NZF - NYF < QI * QI ? 0 : PB;
+    __syncthreads();
+
+    // ---- write-out: interior points to y, brick-face points to their slots ----
+    constexpr int QI = PB - 1, NIN = QI * QI * QI;
+    const T alpha = a.alpha, beta = a.beta;
+#pragma unroll
+    for (int it = 0; it < (NIN + NT - 1) / NT; ++it) {
+        const int r = lane + NT * it;
+        if (r < NIN) {
+            const int la = 1 + r % QI, q = r / QI, lb = 1 + q % QI, lc = 1 + q / QI;
+            const uint32_t g = gb + (uint32_t)la + Lo * ((uint32_t)lb + Lo * (uint32_t)lc);
+            T v = alpha * xc[la + QS * (lb + QS * lc)];
+            if (beta != T(0)) v += beta * ldg(a.z, g);
+            *reinterpret_cast<T*>(reinterpret_cast<char*>(a.y) + g * (uint32_t)sizeof(T)) = v;
         }
-        put_slot<PB, T>(a, bx, by, bz, la, lb, lc, part[la + QS * (lb + QS * lc)]);
+    }
+    // Face points, one face family at a time (the slot index is affine within a face); the
+    // slot plane is code = [la == 0] + 2 [lb == 0] + 4 [lc == 0].
+    const uint32_t nbu = (uint32_t)nb, np = Lo - nbu - 1, tot = a.if_tot;
+    T* __restrict__ slots = a.slots;
+    for (int r = lane; r < 2 * QS * QS; r += NT) {                 // x faces: la = 0, PB
+        const int sd = r / (QS * QS), u = r % (QS * QS), lb = u % QS, lc = u / QS, la = sd * PB;
+        const uint32_t t = iface_x0<PB>(bx, by, bz, sd, Lo) + (uint32_t)lb + Lo * (uint32_t)lc;
+        const uint32_t code = (sd == 0 ? 1u : 0u) | (lb == 0 ? 2u : 0u) | (lc == 0 ? 4u : 0u);
+        slots[(size_t)code * tot + t] = xc[la + QS * (lb + QS * lc)];
+    }
+    for (int r = lane; r < 2 * QI * QS; r += NT) {                 // y faces: lb = 0, PB; la inside
+        const int sd = r / (QI * QS), u = r % (QI * QS), la = 1 + u % QI, lc = u / QI, lb = sd * PB;
+        const uint32_t t = iface_y0<PB>(bx, by, bz, sd, Lo, nbu, a.if_c0) + (uint32_t)la + np * (uint32_t)lc;
+        const uint32_t code = (sd == 0 ? 2u : 0u) | (lc == 0 ? 4u : 0u);
+        slots[(size_t)code * tot + t] = xc[la + QS * (lb + QS * lc)];
+    }
+    for (int r = lane; r < 2 * QI * QI; r += NT) {                 // z faces: lc = 0, PB; la, lb inside
+        const int sd = r / (QI * QI), u = r % (QI * QI), la = 1 + u % QI, lb = 1 + u / QI, lc = sd * PB;
+        const uint32_t t = iface_z0<PB>(bx, by, bz, sd, Lo, nbu, a.if_c01) + (uint32_t)la + np * (uint32_t)lb;
+        const uint32_t code = sd == 0 ? 4u : 0u;
+        slots[(size_t)code * tot + t] = xc[la + QS * (lb + QS * lc)];
     }
 }
 

@@ -59,16 +59,13 @@ struct HostLevel {
     std::vector<float> G32;
     std::vector<uint32_t> owner;   // SoA nwords * C: fine points owned by this (coarse) cell
     int nwords = 0;
-    // Cube-kernel data (P1/P2 on 4-cube bricks): the (p+1)^3 distinct dofs of each Kuhn cube,
-    // SoA by cube point (cmap[j * ncube + cube], boundary flag in the sign bit, cubes numbered
-    // brick by brick), and the vertex coordinates SoA (x[NV], y[NV], z[NV]) in FP64.
+    // Cube-kernel data (P1/P2 on 4-cube bricks, whose dofs are addressed by their lattice point):
+    // the vertex coordinates SoA (x[NV], y[NV], z[NV]) in FP64.
     bool cube = false;
-    int64_t ncube = 0;
-    std::vector<int32_t> cmap;
     std::vector<double> vsoa;
     int red = -1, red1 = -1;       // reduction tables for degree p and for degree 1 output
     int64_t slot_elems = 0;        // interface partial slots (max over the tables used)
-    size_t d_map = 0, d_G64 = 0, d_G32 = 0, d_slots = 0, d_owner = 0, d_cmap = 0, d_vsoa = 0;
+    size_t d_map = 0, d_G64 = 0, d_G32 = 0, d_slots = 0, d_owner = 0, d_vsoa = 0;
 };
 
 }  // namespace fem

@@ -171,20 +171,9 @@ static void build_level(HostLevel& L, const std::vector<std::array<int, 4>>& mi)
     }
 }
 
-// Per-cube dof map of the cube kernel: the entry of cube point j is read from the cell-to-dof map
-// of the first tetrahedron of the cube that has a node there.
-template <int P>
-static void build_cube_map(HostLevel& L) {
-    constexpr CubeNodes<P> CN{};
-    constexpr int NCP = CubeNodes<P>::NCP;
-    const int64_t NT = (int64_t)L.B * L.B * L.B;
-    L.ncube = L.C / 6;
-    L.cmap.assign((size_t)NCP * L.ncube, 0);
-    for (int64_t cube = 0; cube < L.ncube; ++cube) {
-        const int64_t c0 = (cube / NT) * 6 * NT + cube % NT;
-        for (int j = 0; j < NCP; ++j)
-            L.cmap[(size_t)j * L.ncube + cube] = L.map[(size_t)CN.first_i[j] * L.C + c0 + CN.first_t[j] * NT];
-    }
+// Cube-kernel data: the vertex coordinates in structure-of-arrays order.  The kernel addresses dofs
+// by their lattice point, the numbering validate_level checks for every map entry.
+static void build_cube_data(HostLevel& L) {
     const int64_t NV = L.NV;
     L.vsoa.assign((size_t)3 * NV, 0.0);
     for (int64_t v = 0; v < NV; ++v)
@@ -299,11 +288,9 @@ fem_status build_mesh(const fem_mesh_desc& d, fem_mesh& m) {
         L.red = find_red(m, p, L.B);
         L.red1 = find_red(m, 1, L.B);
         validate_level(L, m.red[L.red]);
-        // the cube kernel addresses x, its dof map and the coordinates with 32-bit byte offsets
-        const int64_t ncp = (int64_t)(p + 1) * (p + 1) * (p + 1);
-        const bool fits = L.N * 8 < (1LL << 32) && ncp * (L.C / 6) * 4 < (1LL << 32) && 3 * L.NV * 8 < (1LL << 32);
-        if (fits && L.B == 4 && p == 1) build_cube_map<1>(L);
-        if (fits && L.B == 4 && p == 2) build_cube_map<2>(L);
+        // the cube kernel addresses x, y and the coordinates with 32-bit byte offsets
+        const bool fits = L.N * 8 < (1LL << 32) && 3 * L.NV * 8 < (1LL << 32);
+        if (fits && L.B == 4 && p <= 2) build_cube_data(L);
         // interface slots: 8 side codes x the interface points of the degree-p and degree-1 lattices
         auto iface = [&](int po) {
             const int64_t Lo = (int64_t)po * L.n + 1, nb = L.nb, np = Lo - nb - 1;
@@ -353,7 +340,6 @@ fem_status build_mesh(const fem_mesh_desc& d, fem_mesh& m) {
         L.d_G32 = take(L.G32.size() * 4);
         L.d_slots = take((size_t)L.slot_elems * 8);
         L.d_owner = take(L.owner.size() * 4);
-        L.d_cmap = take(L.cmap.size() * 4);
         L.d_vsoa = take(L.vsoa.size() * 8);
     }
     m.bytes = off;

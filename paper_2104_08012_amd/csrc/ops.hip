@@ -13,7 +13,7 @@ template <int KIND, typename T, int P, int B, bool KV>
 void launch_main(const SArgs<T>& a, int64_t nbricks, hipStream_t s) {
     if constexpr (KIND == K_APPLY && P <= 2 && B == 4) {
         // one thread per cube for the low degrees (see cube.hpp), where the level has the cube data
-        if (a.cmap) {
+        if (a.vxyz) {
             hipLaunchKernelGGL((k_cube_apply<P, B, KV, T>), dim3((unsigned)nbricks), dim3(B * B * B), 0, s, a);
             return;
         }
@@ -107,9 +107,7 @@ fem_status run_kind(const fem_mesh& m, int level, bool kvar, const ScatterIO<T>&
     a.beta = (T)io.beta;
     a.row_mode = io.row_mode;
     a.xid = io.xid;
-    a.cmap = L.cube ? dptr<int32_t>(m, L.d_cmap) : nullptr;
     a.vxyz = L.cube ? dptr<double>(m, L.d_vsoa) : nullptr;
-    a.ncube = (uint32_t)L.ncube;
     a.nv = (uint32_t)L.NV;
     const int64_t Lo = a.Lout, nb = L.nb, np = Lo - nb - 1;
     const int64_t c0 = (nb + 1) * Lo * Lo, c1 = (nb + 1) * np * Lo, c2 = (nb + 1) * np * np;

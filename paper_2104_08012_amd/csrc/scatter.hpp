@@ -26,6 +26,7 @@
 #include <utility>
 
 #include "common.hpp"
+#include "iface.hpp"
 #include "incidence.hpp"
 #include "tabulate.hpp"
 
@@ -53,9 +54,8 @@ struct SArgs {
     T alpha, beta;
     int row_mode;                    // RowMode for boundary rows of the output
     const T* xid;                    // values of identity rows
-    const int32_t* cmap;             // cube kernel: SoA (p+1)^3 * ncube dofs of each cube, or null
     const double* vxyz;              // cube kernel: vertex coordinates SoA x[nv], y[nv], z[nv]
-    uint32_t ncube, nv;
+    uint32_t nv;
 };
 
 constexpr int brick_threads(int B) { return B == 4 ? 384 : 64; }
@@ -96,26 +96,6 @@ __device__ __forceinline__ T gather(const T* __restrict__ x, int32_t m, int mask
 
 template <int KIND, int P, int B, bool KVAR, typename T>
 struct Producer;
-
-// Interface points (lattice points on a brick plane, coordinate = 0 mod PB in some direction) are
-// numbered family by family: points on x planes (x fastest within (plane, z, y)... see below),
-// then points on y planes but no x plane, then points on z planes only:
-//   x planes: t = (I/PB) L^2 + K L + J
-//   y planes: t = c0 + (J/PB) np L + K np + iu           (iu: rank of I among non-plane values)
-//   z planes: t = c01 + (K/PB) np^2 + ju np + iu
-// with np = L - nb - 1 non-plane coordinates per direction.  A brick's contribution to point t
-// is stored at slots[code * if_tot + t], code = sum_d [the brick is the upper one along d] << d,
-// so each (point, brick) pair has its own slot and the fix-up reads them contiguously.
-template <int PB>
-__device__ __forceinline__ uint32_t iface_index(uint32_t I, uint32_t J, uint32_t K, uint32_t L, uint32_t nb,
-                                                uint32_t c0, uint32_t c01) {
-    const uint32_t np = L - nb - 1;
-    if (I % PB == 0) return (I / PB) * L * L + K * L + J;
-    const uint32_t iu = (I / PB) * (PB - 1) + I % PB - 1;
-    if (J % PB == 0) return c0 + (J / PB) * np * L + K * np + iu;
-    const uint32_t ju = (J / PB) * (PB - 1) + J % PB - 1;
-    return c01 + (K / PB) * np * np + ju * np + iu;
-}
 
 // store the brick's partial sum at closure point (la, lb, lc) of brick (bx, by, bz)
 template <int PB, typename T>

@@ -170,16 +170,13 @@ struct VertexGrad {
     }
 };
 
-// Local node i of the path tetrahedron t sits at cube-lattice point (pa, pb, pc) in [0, P]^3;
-// each cube point is listed with the first (t, i) that reaches it.
+// Local node i of the path tetrahedron t sits at cube-lattice point (pa, pb, pc) in [0, P]^3.
 template <int P>
 struct CubeNodes {
     static constexpr int NL = nloc_of(P), PC = P + 1, NCP = PC * PC * PC;
     int cp[6][NL];        // tetrahedron t, node i -> cube point index
-    int first_t[NCP], first_i[NCP];
-    constexpr CubeNodes() : cp{}, first_t{}, first_i{} {
+    constexpr CubeNodes() : cp{} {
         const NodeList<P> nodes{};
-        for (int j = 0; j < NCP; ++j) first_t[j] = -1;
         for (int t = 0; t < 6; ++t) {
             const int s0 = perm_axis(t, 0), s1 = perm_axis(t, 1);
             int V[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {1, 1, 1}};
@@ -192,10 +189,6 @@ struct CubeNodes {
                     for (int k = 0; k < 3; ++k) X[k] += nodes.m[i][v] * V[v][k];
                 const int j = X[0] + PC * (X[1] + PC * X[2]);
                 cp[t][i] = j;
-                if (first_t[j] < 0) {
-                    first_t[j] = t;
-                    first_i[j] = i;
-                }
             }
         }
     }
