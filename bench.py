@@ -103,7 +103,7 @@ def flops_per_cell(p, kvar):
 
 def kernel_sources_sha():
     h = hashlib.sha256()
-    for f in ("cube.hpp", "scatter.hpp", "tabulate.hpp", "incidence.hpp", "common.hpp", "ops.hip"):
+    for f in ("cube.hpp", "scatter.hpp", "tabulate.hpp", "incidence.hpp", "iface.hpp", "common.hpp", "ops.hip"):
         with open(os.path.join(ROOT, "paper_2104_08012_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -125,9 +125,12 @@ def traffic_from_profiles(key):
 
 
 def action_bytes(p, n, C, N, NV, s, kvar):
-    """Algorithmic bytes of one action for the layout the library uses at this size."""
+    """Algorithmic bytes of one action for the layout the library uses at this size: for the cube
+    kernel (P1/P2 on 4-cube bricks, dofs addressed by lattice point) x and y once, the FP64 vertex
+    coordinates and the vertex coefficient; otherwise also the cell-to-dof map and the geometric
+    factors of every cell."""
     if p <= 2 and n % 4 == 0:
-        return 2 * N * s + 4 * (p + 1) ** 3 * (C // 6) + 24 * NV + (NV * s if kvar else 0)
+        return 2 * N * s + 24 * NV + (NV * s if kvar else 0)
     return balg_bytes(C, N, nloc_of(p), s, NV if kvar else 0)
 
 

@@ -71,15 +71,38 @@ __device__ __forceinline__ double lane_read(int addr, double v) {
     const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(b >> 32));
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
-// closure offset of cube point j = (ja, jb, jc) (ja fastest, P + 1 per axis) and LDS offset of
-// cube corner j (corner j at (j & 1, j >> 1 & 1, j >> 2)) in the brick's 5^3 vertex block
-template <int P, int QS>
-__host__ __device__ constexpr int xo_of(int j) {
-    return j % (P + 1) + QS * ((j / (P + 1)) % (P + 1) + QS * (j / ((P + 1) * (P + 1))));
-}
+// LDS offset of cube corner j (corner j at (j & 1, j >> 1 & 1, j >> 2)) in the brick's 5^3
+// vertex block
+
 template <int VS>
 __host__ __device__ constexpr int vo_of(int j) {
     return (j & 1) + VS * (((j >> 1) & 1) + VS * (j >> 2));
+}
+
+// LDS layout of the brick's closure values.  Lane (lx, ly, lz) reads the points P lx + ja,
+// P ly + jb, P lz + jc; for P = 2 the even and odd x coordinates are stored in two separate
+// blocks with rows of 6 doubles, so a lane's base is lx + 12 ly + 108 lz and the 16 lanes of a
+// row of the wave hit 16 different 8-byte bank pairs (row stride 6 -> 12 ly = 0, 12, 8, 4 mod 16).
+// For P = 1 rows are padded to 6 as well.
+template <int P>
+struct ClosureLayout {
+    static constexpr int QS = 4 * P + 1;
+    static constexpr int RS = 6;                          // row stride (lb)
+    static constexpr int PS = RS * QS;                    // plane stride (lc)
+    static constexpr int HALF = PS * QS;                  // offset of the odd-x block (P = 2)
+    static constexpr int SIZE = (P == 2 ? 2 : 1) * HALF;
+    __host__ __device__ static constexpr int idx(int la, int lb, int lc) {
+        return (P == 2 ? (la & 1) * HALF + (la >> 1) : la) + RS * lb + PS * lc;
+    }
+};
+
+// LDS offset of cube point j = (ja, jb, jc) (ja fastest, P + 1 per axis) from the lane's base
+// XL::idx(P lx, P ly, P lz): with P lx even the parity of the x coordinate is that of ja.
+template <int P>
+__host__ __device__ constexpr int xo_of(int j) {
+    using XL = ClosureLayout<P>;
+    const int ja = j % (P + 1), jb = (j / (P + 1)) % (P + 1), jc = j / ((P + 1) * (P + 1));
+    return XL::idx(ja, jb, jc) - XL::idx(0, 0, 0);
 }
 
 constexpr int kQuadPrev = 0 | (0 << 2) | (1 << 4) | (2 << 6);   // quad_perm [0, 0, 1, 2]
@@ -100,7 +123,8 @@ __global__ void __launch_bounds__(B * B * B, (cube_min_waves<P, KVAR, T>())) k_c
     constexpr int VS = B + 1, NV3 = VS * VS * VS;
     constexpr StiffTab<P, KVAR> TB{};
     constexpr CubeNodes<P> CN{};
-    __shared__ T xc[NQ3];            // closure values: x on input, the brick's sums on output
+    using XL = ClosureLayout<P>;
+    __shared__ T xc[XL::SIZE];       // closure values: x on input, the brick's sums on output
     __shared__ double vc[3][NV3];    // vertex coordinates of the brick's 5^3 vertices
     __shared__ T kl[KVAR ? NV3 : 1];  // coefficient at those vertices
     const int brick = brick_of_block(blockIdx.x, gridDim.x);
@@ -116,11 +140,13 @@ __global__ void __launch_bounds__(B * B * B, (cube_min_waves<P, KVAR, T>())) k_c
     {
         constexpr int NIT = (NQ3 + NT - 1) / NT;
         T v[NIT];
+        int li[NIT];
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             const int r = (lane + NT * it < NQ3) ? lane + NT * it : NQ3 - 1;
             const int la = r % QS, q = r / QS, lb = q % QS, lc = q / QS;
             v[it] = ldg(a.x, gb + (uint32_t)la + Lo * ((uint32_t)lb + Lo * (uint32_t)lc));
+            li[it] = XL::idx(la, lb, lc);
         }
         const uint32_t n1 = (uint32_t)a.n + 1, NV = a.nv;
         const uint32_t vb = (uint32_t)(bx * B) + n1 * ((uint32_t)(by * B) + n1 * (uint32_t)(bz * B));
@@ -138,7 +164,7 @@ __global__ void __launch_bounds__(B * B * B, (cube_min_waves<P, KVAR, T>())) k_c
         }
 #pragma unroll
         for (int it = 0; it < NIT; ++it)
-            if (lane + NT * it < NQ3) xc[lane + NT * it] = v[it];
+            if (lane + NT * it < NQ3) xc[li[it]] = v[it];
 #pragma unroll
         for (int it = 0; it < NVIT; ++it) {
             const int r = lane + NT * it;
@@ -158,8 +184,7 @@ __global__ void __launch_bounds__(B * B * B, (cube_min_waves<P, KVAR, T>())) k_c
                 if (bd != (hi ? nb - 1 : 0)) continue;
                 for (int r = lane; r < QS * QS; r += NT) {
                     const int u = r % QS, w = r / QS, e = hi ? PB : 0;
-                    const int idx = d == 0 ? e + QS * (u + QS * w) : d == 1 ? u + QS * (e + QS * w) : u + QS * (w + QS * e);
-                    xc[idx] = T(0);
+                    xc[d == 0 ? XL::idx(e, u, w) : d == 1 ? XL::idx(u, e, w) : XL::idx(u, w, e)] = T(0);
                 }
             }
         }
@@ -167,7 +192,7 @@ __global__ void __launch_bounds__(B * B * B, (cube_min_waves<P, KVAR, T>())) k_c
     __syncthreads();
 
     // ---- the six tetrahedra of the lane's cube ----
-    const int xb = P * lx + QS * (P * ly + QS * P * lz);   // closure index of the cube's point 0
+    const int xb = XL::idx(P * lx, P * ly, P * lz);       // LDS index of the cube's point 0
     const int vbl = lx + VS * (ly + VS * lz);              // vertex index of the cube's corner 0
     T ys[NCP];
 #pragma unroll
@@ -203,10 +228,11 @@ __global__ void __launch_bounds__(B * B * B, (cube_min_waves<P, KVAR, T>())) k_c
         const T g01 = T((c1x * c2x + c1y * c2y + c1z * c2z) * inv);
         const T g02 = T((c1x * c3x + c1y * c3y + c1z * c3z) * inv);
         const T g12 = T((c2x * c3x + c2y * c3y + c2z * c3z) * inv);
-        // the cell's nodal values (cube point j = (ja, jb, jc) at closure offset ja + QS (jb + QS jc))
+        // the cell's nodal values, read once the geometry is done (fewer values live at once)
+        __asm__ volatile("" ::: "memory");
         T xs[NL];
 #pragma unroll
-        for (int i = 0; i < NL; ++i) xs[i] = xc[xb + xo_of<P, QS>(CN.cp[t][i])];
+        for (int i = 0; i < NL; ++i) xs[i] = xc[xb + xo_of<P>(CN.cp[t][i])];
         T kt[4];
         if constexpr (KVAR) {
             kt[0] = kl[vbl];
@@ -309,7 +335,7 @@ __global__ void __launch_bounds__(B * B * B, (cube_min_waves<P, KVAR, T>())) k_c
     for (int j = 0; j < NCP; ++j) {
         const int ja = j % PC, jb = (j / PC) % PC, jc = j / (PC * PC);
         if ((ja < P || lx == B - 1) && (jb < P || ly == B - 1) && (jc < P || lz == B - 1))
-            xc[xb + xo_of<P, QS>(j)] = ys[j];
+            xc[xb + xo_of<P>(j)] = ys[j];
     }
     __syncthreads();
 
@@ -322,7 +348,7 @@ __global__ void __launch_bounds__(B * B * B, (cube_min_waves<P, KVAR, T>())) k_c
         if (r < NIN) {
             const int la = 1 + r % QI, q = r / QI, lb = 1 + q % QI, lc = 1 + q / QI;
             const uint32_t g = gb + (uint32_t)la + Lo * ((uint32_t)lb + Lo * (uint32_t)lc);
-            T v = alpha * xc[la + QS * (lb + QS * lc)];
+            T v = alpha * xc[XL::idx(la, lb, lc)];
             if (beta != T(0)) v += beta * ldg(a.z, g);
             *reinterpret_cast<T*>(reinterpret_cast<char*>(a.y) + g * (uint32_t)sizeof(T)) = v;
         }
@@ -335,19 +361,19 @@ __global__ void __launch_bounds__(B * B * B, (cube_min_waves<P, KVAR, T>())) k_c
         const int sd = r / (QS * QS), u = r % (QS * QS), lb = u % QS, lc = u / QS, la = sd * PB;
         const uint32_t t = iface_x0<PB>(bx, by, bz, sd, Lo) + (uint32_t)lb + Lo * (uint32_t)lc;
         const uint32_t code = (sd == 0 ? 1u : 0u) | (lb == 0 ? 2u : 0u) | (lc == 0 ? 4u : 0u);
-        slots[(size_t)code * tot + t] = xc[la + QS * (lb + QS * lc)];
+        slots[(size_t)code * tot + t] = xc[XL::idx(la, lb, lc)];
     }
     for (int r = lane; r < 2 * QI * QS; r += NT) {                 // y faces: lb = 0, PB; la inside
         const int sd = r / (QI * QS), u = r % (QI * QS), la = 1 + u % QI, lc = u / QI, lb = sd * PB;
         const uint32_t t = iface_y0<PB>(bx, by, bz, sd, Lo, nbu, a.if_c0) + (uint32_t)la + np * (uint32_t)lc;
         const uint32_t code = (sd == 0 ? 2u : 0u) | (lc == 0 ? 4u : 0u);
-        slots[(size_t)code * tot + t] = xc[la + QS * (lb + QS * lc)];
+        slots[(size_t)code * tot + t] = xc[XL::idx(la, lb, lc)];
     }
     for (int r = lane; r < 2 * QI * QI; r += NT) {                 // z faces: lc = 0, PB; la, lb inside
         const int sd = r / (QI * QI), u = r % (QI * QI), la = 1 + u % QI, lb = 1 + u / QI, lc = sd * PB;
         const uint32_t t = iface_z0<PB>(bx, by, bz, sd, Lo, nbu, a.if_c01) + (uint32_t)la + np * (uint32_t)lb;
         const uint32_t code = sd == 0 ? 4u : 0u;
-        slots[(size_t)code * tot + t] = xc[la + QS * (lb + QS * lc)];
+        slots[(size_t)code * tot + t] = xc[XL::idx(la, lb, lc)];
     }
 }
 
