@@ -163,7 +163,9 @@ fem_status make_layout(const fem_mesh& m, const fem_solve_opts& o, int top, Layo
         L.dense_n = nI;
         L.dense = take((size_t)nI * nI * 8);
         L.dense_xc = take(std::max<int64_t>(nI, 1) * 8);
-        L.dense_packed = take(sym_packed_doubles(nI) * 8);
+        // the packed inverse: FP64, or FP32 in mixed precision (the coarse correction is part of
+        // the FP32 preconditioner; products are still accumulated in FP64)
+        L.dense_packed = take(sym_packed_doubles(nI) * ts);
         L.dense_part = take(sym_partial_doubles(nI) * 8);
     }
     L.total = off;
@@ -370,7 +372,10 @@ fem_status fem_solver::coarse_solve(const double* b64, double* x64) {
         return FEM_OK;
     }
     const HostLevel& C = m->lev[L.lo];
-    sym_solve_launch(C.L, p<double>(L.dense_packed), b64, p<double>(L.dense_xc), p<double>(L.dense_part), x64, s);
+    if (L.mixed)
+        sym_solve_launch(C.L, p<float>(L.dense_packed), b64, p<double>(L.dense_xc), p<double>(L.dense_part), x64, s);
+    else
+        sym_solve_launch(C.L, p<double>(L.dense_packed), b64, p<double>(L.dense_xc), p<double>(L.dense_part), x64, s);
     return check_launch("coarse solve");
 }
 
@@ -558,7 +563,8 @@ fem_status fem_solver::setup(const double* k_top) {
                         probe_extract_launch(C.L, P, S, c0, c1, c2, y, A, s);
                     }
             FEM_TRY(dense_invert(nd, A, nullptr, s));
-            sym_pack_launch(nd, A, p<double>(L.dense_packed), s);
+            if (L.mixed) sym_pack_launch(nd, A, p<float>(L.dense_packed), s);
+            else sym_pack_launch(nd, A, p<double>(L.dense_packed), s);
         }
     }
     const hipError_t e = hipStreamSynchronize(s);

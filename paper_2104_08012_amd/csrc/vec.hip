@@ -321,21 +321,32 @@ __device__ __forceinline__ void tile_of(int64_t t, int& I, int& J) {
     J = (int)(t - (int64_t)i * (i + 1) / 2);
 }
 
-// Ap tile (I, J) = (A_IJ + A_JI^T) / 2: the symmetric part of the computed inverse.
-__global__ void __launch_bounds__(256) k_sym_pack(int64_t n, const double* __restrict__ A, double* __restrict__ Ap) {
+// Ap tile (I, J) = (A_IJ + A_JI^T) / 2: the symmetric part of the computed inverse, stored in TO
+// (FP64, or FP32 for the mixed-precision preconditioner: rounded once from the FP64 inverse).
+template <typename TO>
+__global__ void __launch_bounds__(256) k_sym_pack(int64_t n, const double* __restrict__ A, TO* __restrict__ Ap) {
     int I, J;
     tile_of(blockIdx.x, I, J);
-    double* out = Ap + (int64_t)blockIdx.x * ST * ST;
+    TO* out = Ap + (int64_t)blockIdx.x * ST * ST;
     for (int e = threadIdx.x; e < ST * ST; e += 256) {
         const int64_t i = (int64_t)I * ST + e / ST, j = (int64_t)J * ST + e % ST;
-        out[e] = (i < n && j < n) ? 0.5 * (A[i * n + j] + A[j * n + i]) : 0.0;
+        out[e] = (TO)((i < n && j < n) ? 0.5 * (A[i * n + j] + A[j * n + i]) : 0.0);
     }
 }
 
+template <typename TA>
+struct Pair;
+template <>
+struct Pair<double> { using type = double2; };
+template <>
+struct Pair<float> { using type = float2; };
+
 // Per tile t = (I, J): prow[t] = A_IJ x_J and, off the diagonal, pcol[t] = A_IJ^T x_I
-// (64 entries each).  The tile is staged in LDS; thread (e, q) of the 256 sums a quarter
-// (16 terms, fixed order) of row e and of column e, and the quarters are added in order q = 0..3.
-__global__ void __launch_bounds__(256) k_sym_tiles(int64_t n, const double* __restrict__ Ap,
+// (64 entries each), accumulated in FP64 whatever the tile's storage type TA.  The tile is staged
+// in LDS; thread (e, q) of the 256 sums a quarter (16 terms, fixed order) of row e and of column
+// e, and the quarters are added in order q = 0..3.
+template <typename TA>
+__global__ void __launch_bounds__(256) k_sym_tiles(int64_t n, const TA* __restrict__ Ap,
                                                    const double* __restrict__ xc, double* __restrict__ prow,
                                                    double* __restrict__ pcol) {
     __shared__ double sa[ST][ST + 1];
@@ -343,9 +354,10 @@ __global__ void __launch_bounds__(256) k_sym_tiles(int64_t n, const double* __re
     __shared__ double sq[2][4][ST];
     int I, J;
     tile_of(blockIdx.x, I, J);
-    const double2* tile = reinterpret_cast<const double2*>(Ap + (int64_t)blockIdx.x * ST * ST);
+    using P2 = typename Pair<TA>::type;
+    const P2* tile = reinterpret_cast<const P2*>(Ap + (int64_t)blockIdx.x * ST * ST);
     for (int e = threadIdx.x; e < ST * ST / 2; e += 256) {
-        const double2 v = tile[e];
+        const P2 v = tile[e];
         const int r = (2 * e) / ST, c = (2 * e) % ST;
         sa[r][c] = v.x;
         sa[r][c + 1] = v.y;
@@ -553,12 +565,16 @@ int64_t sym_tiles(int64_t n) {
 size_t sym_packed_doubles(int64_t n) { return (size_t)sym_tiles(n) * ST * ST; }
 size_t sym_partial_doubles(int64_t n) { return (size_t)2 * sym_tiles(n) * ST; }
 
-void sym_pack_launch(int64_t n, const double* A, double* Ap, hipStream_t s) {
+template <typename TA>
+void sym_pack_launch(int64_t n, const double* A, TA* Ap, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_sym_pack, dim3((unsigned)sym_tiles(n)), dim3(256), 0, s, n, A, Ap);
+    hipLaunchKernelGGL((k_sym_pack<TA>), dim3((unsigned)sym_tiles(n)), dim3(256), 0, s, n, A, Ap);
 }
+template void sym_pack_launch<double>(int64_t, const double*, double*, hipStream_t);
+template void sym_pack_launch<float>(int64_t, const double*, float*, hipStream_t);
 
-void sym_solve_launch(int L, const double* Ap, const double* xl, double* xc, double* part, double* yl,
+template <typename TA>
+void sym_solve_launch(int L, const TA* Ap, const double* xl, double* xc, double* part, double* yl,
                       hipStream_t s) {
     const int64_t M = L - 2, m = M * M * M, ntl = sym_tiles(m);
     const int nt = (int)((m + ST - 1) / ST);
@@ -568,10 +584,12 @@ void sym_solve_launch(int L, const double* Ap, const double* xl, double* xc, dou
     hipLaunchKernelGGL(k_gather_interior, dim3(grid_for(m)), dim3(VT), 0, s, L, xl, xc);
     double* prow = part;
     double* pcol = part + ntl * ST;
-    hipLaunchKernelGGL(k_sym_tiles, dim3((unsigned)ntl), dim3(256), 0, s, m, Ap, (const double*)xc, prow, pcol);
+    hipLaunchKernelGGL((k_sym_tiles<TA>), dim3((unsigned)ntl), dim3(256), 0, s, m, Ap, (const double*)xc, prow, pcol);
     hipLaunchKernelGGL(k_sym_reduce, dim3((unsigned)nt), dim3(4 * ST), 0, s, L, m, nt, (const double*)prow,
                        (const double*)pcol, yl);
 }
+template void sym_solve_launch<double>(int, const double*, const double*, double*, double*, double*, hipStream_t);
+template void sym_solve_launch<float>(int, const float*, const double*, double*, double*, double*, hipStream_t);
 
 
 }  // namespace fem

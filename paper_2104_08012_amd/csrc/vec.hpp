@@ -55,10 +55,12 @@ fem_status dense_invert(int64_t n, double* A, double* tmp, hipStream_t s);
 // Coarse inverse kept as the packed lower 64 x 64 tiles of its symmetric part; the solve reads
 // each stored tile once (y_I += A_IJ x_J and y_J += A_IJ^T x_I through per-tile partials summed in
 // a fixed order).  yl: lattice vector, boundary entries set to zero.
-size_t sym_packed_doubles(int64_t n);
+size_t sym_packed_doubles(int64_t n);   // entries of the packed tiles (FP64 or FP32 storage)
 size_t sym_partial_doubles(int64_t n);
-void sym_pack_launch(int64_t n, const double* A, double* Ap, hipStream_t s);
-void sym_solve_launch(int L, const double* Ap, const double* xl, double* xc, double* part, double* yl,
+template <typename TA>
+void sym_pack_launch(int64_t n, const double* A, TA* Ap, hipStream_t s);
+template <typename TA>
+void sym_solve_launch(int L, const TA* Ap, const double* xl, double* xc, double* part, double* yl,
                       hipStream_t s);
 
 }  // namespace fem
