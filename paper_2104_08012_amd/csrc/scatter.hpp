@@ -403,31 +403,44 @@ __global__ void __launch_bounds__(256) k_fixup(SArgs<T> a, FixGeom fg) {
             J = ju;
         }
     }
-    int cb[3][2], cloc[3][2], cn[3];
-    const uint32_t X[3] = {I, J, K};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const uint32_t x = X[d], q = x / PB, r = x - q * PB;
-        if (r == 0) {
-            cn[d] = 0;
-            if (q >= 1) { cb[d][cn[d]] = (int)q - 1; cloc[d][cn[d]] = PB; ++cn[d]; }
-            if (q < nb) { cb[d][cn[d]] = (int)q; cloc[d][cn[d]] = 0; ++cn[d]; }
-        } else {
-            cn[d] = 1;
-            cb[d][0] = (int)q;
-            cloc[d][0] = (int)r;
-        }
-    }
-    T acc = T(0);
-    for (int iz = 0; iz < cn[2]; ++iz)
-        for (int iy = 0; iy < cn[1]; ++iy)
-            for (int ix = 0; ix < cn[0]; ++ix) {
-                const uint32_t code = (cloc[0][ix] == 0 ? 1u : 0u) | (cloc[1][iy] == 0 ? 2u : 0u) | (cloc[2][iz] == 0 ? 4u : 0u);
-                acc += a.slots[(size_t)code * fg.total + t];
-            }
     const int64_t g = I + (int64_t)L * (J + (int64_t)L * K);
     const bool bnd = I == 0 || J == 0 || K == 0 || I == L - 1 || J == L - 1 || K == L - 1;
-    finalize(a, g, acc, bnd);
+    // a boundary row whose value the row mode replaces needs no slots; its identity value and z
+    // are read before the sum, so every load of the thread is in flight at once
+    const bool need = !(bnd && a.row_mode != ROW_NONE);
+    const T xv = (bnd && a.row_mode == ROW_IDENTITY) ? a.xid[g] : T(0);
+    const T zv = (a.beta != T(0)) ? a.z[g] : T(0);
+    // Along each axis the point has a lower-brick candidate (side bit 0: valid off a brick plane,
+    // or on a plane above the first brick) and an upper-brick candidate (side bit 1: on a plane
+    // below the last brick).  The bricks containing the point, in ascending brick order (z, then
+    // y, then x), are therefore the side codes 0..7 whose three bits are valid: all eight
+    // (predicated) loads are issued together and summed in code order.
+    const uint32_t X[3] = {I, J, K};
+    bool lo[3], hi[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const uint32_t q = X[d] / PB, r = X[d] - q * PB;
+        lo[d] = r != 0 || q >= 1;
+        hi[d] = r == 0 && q < nb;
+    }
+    T v[8];
+#pragma unroll
+    for (int code = 0; code < 8; ++code) {
+        const bool ok = need && ((code & 1) ? hi[0] : lo[0]) && ((code & 2) ? hi[1] : lo[1]) &&
+                        ((code & 4) ? hi[2] : lo[2]);
+        v[code] = ok ? a.slots[(size_t)code * fg.total + t] : T(0);
+    }
+    T acc = v[0];
+#pragma unroll
+    for (int code = 1; code < 8; ++code) acc += v[code];
+    if (bnd) {
+        if (a.row_mode == ROW_IDENTITY) acc = xv;
+        else if (a.row_mode == ROW_ZERO) acc = T(0);
+        else if (a.row_mode == ROW_ONE) acc = T(1);
+    }
+    T r = a.alpha * acc;
+    if (a.beta != T(0)) r += a.beta * zv;
+    a.y[g] = r;
 }
 
 // Prolongation, one thread per coarse cell: x_f[fine dof of m] += sum_j P_loc[m][j] x_c[map_j]
