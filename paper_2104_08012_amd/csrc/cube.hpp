@@ -138,15 +138,30 @@ __global__ void __launch_bounds__(B * B * B, (cube_min_waves<P, KVAR, T>())) k_c
     // (all loads are issued before the first LDS store; indices past the end are clamped)
     const uint32_t gb = (uint32_t)(bx * PB) + Lo * ((uint32_t)(by * PB) + Lo * (uint32_t)(bz * PB));
     {
-        constexpr int NIT = (NQ3 + NT - 1) / NT;
+        // P2: part A, lanes (la, lb) = (lane % 9, lane / 9) for lb < 7, every plane lc; part B,
+        // lanes (la, lb, lc0) with lb = 7, 8 and lc = lc0 + 3 it.  A plane's offset is uniform,
+        // so the loads and LDS stores need no per-load address arithmetic.  P1: flat.
+        constexpr int NIT = P == 2 ? QS + 3 : (NQ3 + NT - 1) / NT;
         T v[NIT];
         int li[NIT];
+        const uint32_t LL = Lo * Lo;
+        const int la = lane % QS, rA = lane / QS, rB = rA < 5 ? rA : 5;
+        const int lbB = 7 + rB % 2, lc0 = rB / 2;
+        if constexpr (P == 2) {
+            const uint32_t oA = gb + (uint32_t)la + Lo * (uint32_t)rA;
+            const uint32_t oB = gb + (uint32_t)la + Lo * (uint32_t)lbB + LL * (uint32_t)lc0;
 #pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-            const int r = (lane + NT * it < NQ3) ? lane + NT * it : NQ3 - 1;
-            const int la = r % QS, q = r / QS, lb = q % QS, lc = q / QS;
-            v[it] = ldg(a.x, gb + (uint32_t)la + Lo * ((uint32_t)lb + Lo * (uint32_t)lc));
-            li[it] = XL::idx(la, lb, lc);
+            for (int lc = 0; lc < QS; ++lc) v[lc] = ldg(a.x + (size_t)lc * LL, oA);
+#pragma unroll
+            for (int it = 0; it < 3; ++it) v[QS + it] = ldg(a.x + (size_t)(3 * it) * LL, oB);
+        } else {
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const int r = (lane + NT * it < NQ3) ? lane + NT * it : NQ3 - 1;
+                const int ra = r % QS, q = r / QS, rb = q % QS, rc = q / QS;
+                v[it] = ldg(a.x, gb + (uint32_t)ra + Lo * ((uint32_t)rb + Lo * (uint32_t)rc));
+                li[it] = XL::idx(ra, rb, rc);
+            }
         }
         const uint32_t n1 = (uint32_t)a.n + 1, NV = a.nv;
         const uint32_t vb = (uint32_t)(bx * B) + n1 * ((uint32_t)(by * B) + n1 * (uint32_t)(bz * B));
@@ -162,9 +177,19 @@ __global__ void __launch_bounds__(B * B * B, (cube_min_waves<P, KVAR, T>())) k_c
             cz[it] = ldg(a.vxyz, 2 * NV + w);
             if constexpr (KVAR) kv[it] = ldg(a.k, w);
         }
+        if constexpr (P == 2) {
+            const int iA = XL::idx(la, rA, 0), iB = XL::idx(la, lbB, lc0);
+            if (lane < 7 * QS)
 #pragma unroll
-        for (int it = 0; it < NIT; ++it)
-            if (lane + NT * it < NQ3) xc[li[it]] = v[it];
+                for (int lc = 0; lc < QS; ++lc) xc[iA + XL::PS * lc] = v[lc];
+            if (lane < 6 * QS)
+#pragma unroll
+                for (int it = 0; it < 3; ++it) xc[iB + 3 * XL::PS * it] = v[QS + it];
+        } else {
+#pragma unroll
+            for (int it = 0; it < NIT; ++it)
+                if (lane + NT * it < NQ3) xc[li[it]] = v[it];
+        }
 #pragma unroll
         for (int it = 0; it < NVIT; ++it) {
             const int r = lane + NT * it;
@@ -342,38 +367,92 @@ __global__ void __launch_bounds__(B * B * B, (cube_min_waves<P, KVAR, T>())) k_c
     // ---- write-out: interior points to y, brick-face points to their slots ----
     constexpr int QI = PB - 1, NIN = QI * QI * QI;
     const T alpha = a.alpha, beta = a.beta;
-#pragma unroll
-    for (int it = 0; it < (NIN + NT - 1) / NT; ++it) {
-        const int r = lane + NT * it;
-        if (r < NIN) {
-            const int la = 1 + r % QI, q = r / QI, lb = 1 + q % QI, lc = 1 + q / QI;
-            const uint32_t g = gb + (uint32_t)la + Lo * ((uint32_t)lb + Lo * (uint32_t)lc);
-            T v = alpha * xc[XL::idx(la, lb, lc)];
-            if (beta != T(0)) v += beta * ldg(a.z, g);
-            *reinterpret_cast<T*>(reinterpret_cast<char*>(a.y) + g * (uint32_t)sizeof(T)) = v;
-        }
-    }
-    // Face points, one face family at a time (the slot index is affine within a face); the
-    // slot plane is code = [la == 0] + 2 [lb == 0] + 4 [lc == 0].
     const uint32_t nbu = (uint32_t)nb, np = Lo - nbu - 1, tot = a.if_tot;
     T* __restrict__ slots = a.slots;
-    for (int r = lane; r < 2 * QS * QS; r += NT) {                 // x faces: la = 0, PB
-        const int sd = r / (QS * QS), u = r % (QS * QS), lb = u % QS, lc = u / QS, la = sd * PB;
-        const uint32_t t = iface_x0<PB>(bx, by, bz, sd, Lo) + (uint32_t)lb + Lo * (uint32_t)lc;
-        const uint32_t code = (sd == 0 ? 1u : 0u) | (lb == 0 ? 2u : 0u) | (lc == 0 ? 4u : 0u);
-        slots[(size_t)code * tot + t] = xc[XL::idx(la, lb, lc)];
-    }
-    for (int r = lane; r < 2 * QI * QS; r += NT) {                 // y faces: lb = 0, PB; la inside
-        const int sd = r / (QI * QS), u = r % (QI * QS), la = 1 + u % QI, lc = u / QI, lb = sd * PB;
-        const uint32_t t = iface_y0<PB>(bx, by, bz, sd, Lo, nbu, a.if_c0) + (uint32_t)la + np * (uint32_t)lc;
-        const uint32_t code = (sd == 0 ? 2u : 0u) | (lc == 0 ? 4u : 0u);
-        slots[(size_t)code * tot + t] = xc[XL::idx(la, lb, lc)];
-    }
-    for (int r = lane; r < 2 * QI * QI; r += NT) {                 // z faces: lc = 0, PB; la, lb inside
-        const int sd = r / (QI * QI), u = r % (QI * QI), la = 1 + u % QI, lb = 1 + u / QI, lc = sd * PB;
-        const uint32_t t = iface_z0<PB>(bx, by, bz, sd, Lo, nbu, a.if_c01) + (uint32_t)la + np * (uint32_t)lb;
-        const uint32_t code = sd == 0 ? 4u : 0u;
-        slots[(size_t)code * tot + t] = xc[XL::idx(la, lb, lc)];
+    if constexpr (P == 2) {
+        // lane tiles whose per-iteration offsets are uniform (plane, face) or compile-time (LDS)
+        const uint32_t LL = Lo * Lo;
+        {   // interior: lanes (la, lb) in [1, 7]^2, planes lc = 1..7
+            const int la = 1 + lane % QI, lb = 1 + lane / QI;
+            const uint32_t o = gb + (uint32_t)la + Lo * (uint32_t)lb;
+            const int i0 = XL::idx(la, lb, 0);
+            if (lane < QI * QI)
+#pragma unroll
+                for (int lc = 1; lc <= QI; ++lc) {
+                    T v = alpha * xc[i0 + XL::PS * lc];
+                    if (beta != T(0)) v += beta * ldg(a.z + (size_t)lc * LL, o);
+                    *reinterpret_cast<T*>(reinterpret_cast<char*>(a.y + (size_t)lc * LL) + o * (uint32_t)sizeof(T)) = v;
+                }
+        }
+        {   // x faces (la = 0, PB): lanes (lb, c) = (lane % 9, lane / 9), lc = c + 7 blk
+            const int lb = lane % QS, c = lane / QS;
+            const uint32_t o = (uint32_t)lb + Lo * (uint32_t)c;
+#pragma unroll
+            for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+                for (int blk = 0; blk < 2; ++blk) {
+                    if (lane < 7 * QS && (blk == 0 || c < 2)) {
+                        const uint32_t code = (sd == 0 ? 1u : 0u) | (lb == 0 ? 2u : 0u) | (blk == 0 && c == 0 ? 4u : 0u);
+                        const uint32_t t = iface_x0<PB>(bx, by, bz, sd, Lo) + 7 * blk * Lo + o;
+                        slots[(size_t)code * tot + t] = xc[XL::idx(sd * PB, lb, c) + 7 * blk * XL::PS];
+                    }
+                }
+        }
+        {   // y faces (lb = 0, PB): lanes (la, lc) = (1 + lane % 7, lane / 7)
+            const int la = 1 + lane % QI, lc = lane / QI;
+            const uint32_t o = (uint32_t)la + np * (uint32_t)lc;
+            const uint32_t code = lc == 0 ? 4u : 0u;
+            const int i0 = XL::idx(la, 0, lc);
+            if (lane < QI * QS)
+#pragma unroll
+                for (int sd = 0; sd < 2; ++sd) {
+                    const uint32_t t = iface_y0<PB>(bx, by, bz, sd, Lo, nbu, a.if_c0) + o;
+                    slots[(size_t)(code | (sd == 0 ? 2u : 0u)) * tot + t] = xc[i0 + XL::RS * PB * sd];
+                }
+        }
+        {   // z faces (lc = 0, PB): lanes (la, lb) in [1, 7]^2
+            const int la = 1 + lane % QI, lb = 1 + lane / QI;
+            const uint32_t o = (uint32_t)la + np * (uint32_t)lb;
+            const int i0 = XL::idx(la, lb, 0);
+            if (lane < QI * QI)
+#pragma unroll
+                for (int sd = 0; sd < 2; ++sd) {
+                    const uint32_t t = iface_z0<PB>(bx, by, bz, sd, Lo, nbu, a.if_c01) + o;
+                    slots[(size_t)(sd == 0 ? 4u : 0u) * tot + t] = xc[i0 + XL::PS * PB * sd];
+                }
+        }
+    } else {
+#pragma unroll
+        for (int it = 0; it < (NIN + NT - 1) / NT; ++it) {
+            const int r = lane + NT * it;
+            if (r < NIN) {
+                const int la = 1 + r % QI, q = r / QI, lb = 1 + q % QI, lc = 1 + q / QI;
+                const uint32_t g = gb + (uint32_t)la + Lo * ((uint32_t)lb + Lo * (uint32_t)lc);
+                T v = alpha * xc[XL::idx(la, lb, lc)];
+                if (beta != T(0)) v += beta * ldg(a.z, g);
+                *reinterpret_cast<T*>(reinterpret_cast<char*>(a.y) + g * (uint32_t)sizeof(T)) = v;
+            }
+        }
+        // Face points, one face family at a time (the slot index is affine within a face); the
+        // slot plane is code = [la == 0] + 2 [lb == 0] + 4 [lc == 0].
+        for (int r = lane; r < 2 * QS * QS; r += NT) {                 // x faces: la = 0, PB
+            const int sd = r / (QS * QS), u = r % (QS * QS), lb = u % QS, lc = u / QS, la = sd * PB;
+            const uint32_t t = iface_x0<PB>(bx, by, bz, sd, Lo) + (uint32_t)lb + Lo * (uint32_t)lc;
+            const uint32_t code = (sd == 0 ? 1u : 0u) | (lb == 0 ? 2u : 0u) | (lc == 0 ? 4u : 0u);
+            slots[(size_t)code * tot + t] = xc[XL::idx(la, lb, lc)];
+        }
+        for (int r = lane; r < 2 * QI * QS; r += NT) {                 // y faces: lb = 0, PB; la inside
+            const int sd = r / (QI * QS), u = r % (QI * QS), la = 1 + u % QI, lc = u / QI, lb = sd * PB;
+            const uint32_t t = iface_y0<PB>(bx, by, bz, sd, Lo, nbu, a.if_c0) + (uint32_t)la + np * (uint32_t)lc;
+            const uint32_t code = (sd == 0 ? 2u : 0u) | (lc == 0 ? 4u : 0u);
+            slots[(size_t)code * tot + t] = xc[XL::idx(la, lb, lc)];
+        }
+        for (int r = lane; r < 2 * QI * QI; r += NT) {                 // z faces: lc = 0, PB; la, lb inside
+            const int sd = r / (QI * QI), u = r % (QI * QI), la = 1 + u % QI, lb = 1 + u / QI, lc = sd * PB;
+            const uint32_t t = iface_z0<PB>(bx, by, bz, sd, Lo, nbu, a.if_c01) + (uint32_t)la + np * (uint32_t)lb;
+            const uint32_t code = sd == 0 ? 4u : 0u;
+            slots[(size_t)code * tot + t] = xc[XL::idx(la, lb, lc)];
+        }
     }
 }
 
