@@ -342,47 +342,66 @@ template <>
 struct Pair<float> { using type = float2; };
 
 // Per tile t = (I, J): prow[t] = A_IJ x_J and, off the diagonal, pcol[t] = A_IJ^T x_I
-// (64 entries each), accumulated in FP64 whatever the tile's storage type TA.  The tile is staged
-// in LDS; thread (e, q) of the 256 sums a quarter (16 terms, fixed order) of row e and of column
-// e, and the quarters are added in order q = 0..3.
+// (64 entries each), accumulated in FP64 whatever the tile's storage type TA.  Persistent blocks:
+// block b takes tiles b, b + gridDim.x, ...; the next tile is loaded into registers while the
+// current one, staged in LDS, is multiplied, so the stream of tile reads does not stop for the
+// arithmetic.  Thread (e, q) of the 256 sums a quarter (16 terms, fixed order) of row e and of
+// column e, and the quarters are added in order q = 0..3.
 template <typename TA>
-__global__ void __launch_bounds__(256) k_sym_tiles(int64_t n, const TA* __restrict__ Ap,
+__global__ void __launch_bounds__(256) k_sym_tiles(int64_t n, int64_t ntiles, const TA* __restrict__ Ap,
                                                    const double* __restrict__ xc, double* __restrict__ prow,
                                                    double* __restrict__ pcol) {
-    __shared__ double sa[ST][ST + 1];
+    using P2 = typename Pair<TA>::type;
+    constexpr int NPT = ST * ST / 2 / 256;   // pairs per thread and tile
+    __shared__ TA sa[ST][ST + 1];
     __shared__ double sx[2][ST];
     __shared__ double sq[2][4][ST];
-    int I, J;
-    tile_of(blockIdx.x, I, J);
-    using P2 = typename Pair<TA>::type;
-    const P2* tile = reinterpret_cast<const P2*>(Ap + (int64_t)blockIdx.x * ST * ST);
-    for (int e = threadIdx.x; e < ST * ST / 2; e += 256) {
-        const P2 v = tile[e];
-        const int r = (2 * e) / ST, c = (2 * e) % ST;
-        sa[r][c] = v.x;
-        sa[r][c + 1] = v.y;
-    }
-    if (threadIdx.x < ST) {
-        const int64_t jj = (int64_t)J * ST + threadIdx.x, ii = (int64_t)I * ST + threadIdx.x;
-        sx[0][threadIdx.x] = jj < n ? xc[jj] : 0.0;
-        sx[1][threadIdx.x] = ii < n ? xc[ii] : 0.0;
-    }
-    __syncthreads();
-    const int e = threadIdx.x % ST, q = threadIdx.x / ST;
-    double ar = 0.0, ac = 0.0;
+    int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    P2 cur[NPT];
+    {
+        const P2* tile = reinterpret_cast<const P2*>(Ap + t * ST * ST);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const int c = q * 16 + k;
-        ar += sa[e][c] * sx[0][c];
-        ac += sa[c][e] * sx[1][c];
+        for (int k = 0; k < NPT; ++k) cur[k] = tile[threadIdx.x + 256 * k];
     }
-    sq[0][q][e] = ar;
-    sq[1][q][e] = ac;
-    __syncthreads();
-    if (q == 0) {
-        prow[(int64_t)blockIdx.x * ST + e] = ((sq[0][0][e] + sq[0][1][e]) + sq[0][2][e]) + sq[0][3][e];
-    } else if (q == 1 && I != J) {
-        pcol[(int64_t)blockIdx.x * ST + e] = ((sq[1][0][e] + sq[1][1][e]) + sq[1][2][e]) + sq[1][3][e];
+    const int e = threadIdx.x % ST, q = threadIdx.x / ST;
+    for (; t < ntiles; t += gridDim.x) {
+        int I, J;
+        tile_of(t, I, J);
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int pe = threadIdx.x + 256 * k, r = (2 * pe) / ST, c = (2 * pe) % ST;
+            sa[r][c] = cur[k].x;
+            sa[r][c + 1] = cur[k].y;
+        }
+        if (threadIdx.x < ST) {
+            const int64_t jj = (int64_t)J * ST + threadIdx.x, ii = (int64_t)I * ST + threadIdx.x;
+            sx[0][threadIdx.x] = jj < n ? xc[jj] : 0.0;
+            sx[1][threadIdx.x] = ii < n ? xc[ii] : 0.0;
+        }
+        __syncthreads();
+        const int64_t tn = t + gridDim.x;
+        if (tn < ntiles) {
+            const P2* tile = reinterpret_cast<const P2*>(Ap + tn * ST * ST);
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) cur[k] = tile[threadIdx.x + 256 * k];
+        }
+        double ar = 0.0, ac = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int c = q * 16 + k;
+            ar += (double)sa[e][c] * sx[0][c];
+            ac += (double)sa[c][e] * sx[1][c];
+        }
+        sq[0][q][e] = ar;
+        sq[1][q][e] = ac;
+        __syncthreads();
+        if (q == 0) {
+            prow[t * ST + e] = ((sq[0][0][e] + sq[0][1][e]) + sq[0][2][e]) + sq[0][3][e];
+        } else if (q == 1 && I != J) {
+            pcol[t * ST + e] = ((sq[1][0][e] + sq[1][1][e]) + sq[1][2][e]) + sq[1][3][e];
+        }
+        __syncthreads();
     }
 }
 
@@ -584,7 +603,11 @@ void sym_solve_launch(int L, const TA* Ap, const double* xl, double* xc, double*
     hipLaunchKernelGGL(k_gather_interior, dim3(grid_for(m)), dim3(VT), 0, s, L, xl, xc);
     double* prow = part;
     double* pcol = part + ntl * ST;
-    hipLaunchKernelGGL((k_sym_tiles<TA>), dim3((unsigned)ntl), dim3(256), 0, s, m, Ap, (const double*)xc, prow, pcol);
+    // persistent blocks, as many as are resident at once on 256 CUs: 4 per CU for FP64 tiles
+    // (36 KB of LDS each), 6 for FP32 tiles (80 VGPRs: 6 waves per SIMD)
+    const int64_t nblk = std::min<int64_t>(ntl, sizeof(TA) == 8 ? 1024 : 1536);
+    hipLaunchKernelGGL((k_sym_tiles<TA>), dim3((unsigned)nblk), dim3(256), 0, s, m, ntl, Ap, (const double*)xc,
+                       prow, pcol);
     hipLaunchKernelGGL(k_sym_reduce, dim3((unsigned)nt), dim3(4 * ST), 0, s, L, m, nt, (const double*)prow,
                        (const double*)pcol, yl);
 }
