@@ -184,14 +184,17 @@ typedef struct {
     double* history;             /* host, may be NULL: relative residual per iteration          */
     int32_t history_cap;
     int32_t preconditioner;      /* FEM_PC_MG (V-cycle) or FEM_PC_JACOBI (diag(A)^-1 on the finest level) */
+    int32_t level_timing;        /* 1: record HIP events around every level of every V-cycle and
+                                    report fem_solve_stats.level_ms (costs a few microseconds per
+                                    level transition); 0 (default): level_ms stay zero            */
 } fem_solve_opts;
 
 typedef struct {
     int32_t iterations;
     int32_t coarse_iterations;   /* nested coarse solver iterations, summed                  */
     double rel_residual_true;    /* ||b - A x|| / ||b|| in FP64 at exit                        */
-    double setup_ms, solve_ms, coarse_ms;
-    double level_ms[8];          /* time spent per mesh level in the V-cycles                  */
+    double setup_ms, solve_ms, coarse_ms; /* coarse_ms: with level_timing = 1                   */
+    double level_ms[8];          /* time spent per mesh level in the V-cycles (level_timing = 1) */
     double lambda_max[8];
 } fem_solve_stats;
 
@@ -224,6 +227,9 @@ fem_status fem_solver_vcycle(fem_solver* s, const double* r, double* z, void* st
  * solve_ms.  Host-synchronous; needs the multigrid preconditioner (FEM_ERR_UNSUPPORTED for
  * Jacobi). */
 fem_status fem_solver_fmg(fem_solver* s, const double* b, double* x, fem_solve_stats* stats, void* stream);
+/* Switch the per-level timing of later solves on (1) or off (0), as fem_solve_opts.level_timing
+ * does at creation.  FEM_ERR_INVALID_ARG for a NULL solver. */
+fem_status fem_solver_set_level_timing(fem_solver* s, int32_t on);
 void fem_solver_destroy(fem_solver* s);
 
 /* One-shot: create, set up, solve, destroy. */

@@ -53,7 +53,7 @@ class SolveOpts(C.Structure):
                 ("coarse_method", C.c_int32), ("lambda_max_override", C.POINTER(C.c_double)),
                 ("coarse_rtol", C.c_double), ("replace_every", C.c_int32), ("flexible", C.c_int32),
                 ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int32),
-                ("preconditioner", C.c_int32)]
+                ("preconditioner", C.c_int32), ("level_timing", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -92,6 +92,7 @@ SIGNATURES = {
     "fem_solver_solve": (_st, [_vp, _vp, _vp, C.POINTER(SolveStats), _vp]),
     "fem_solver_vcycle": (_st, [_vp, _vp, _vp, _vp]),
     "fem_solver_fmg": (_st, [_vp, _vp, _vp, C.POINTER(SolveStats), _vp]),
+    "fem_solver_set_level_timing": (_st, [_vp, _i32]),
     "fem_solver_destroy": (None, [_vp]),
     "fem_mg_cg_solve": (_st, [_vp, _vp, _vp, _vp, C.POINTER(SolveOpts), _vp, C.c_size_t,
                               C.POINTER(SolveStats), _vp]),

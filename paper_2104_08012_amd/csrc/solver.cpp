@@ -244,7 +244,7 @@ struct fem_solver {
     int evset = 0;
     int ev_per_set() const { return 4 * m->nlev + 2; }
     hipEvent_t* evs(int set) { return &ev[(size_t)set * ev_per_set()]; }
-    bool timing = true;
+    bool timing = false;   // per-level events (fem_solve_opts.level_timing)
     std::unique_ptr<fem_solver> inner;   // nested coarse solver over levels 0..L.lo
 
     ~fem_solver() {
@@ -328,6 +328,7 @@ fem_status fem_solver::init(const fem_mesh* mesh, const fem_solve_opts& opts, in
             return FEM_ERR_HIP;
         }
     level_ms.assign(nl, 0.0);
+    timing = o.level_timing != 0;
     if (L.nested) {
         inner.reset(new fem_solver());
         FEM_TRY(inner->init(m, inner_opts(*m, o, L.lo), L.lo, ws + L.inner, L.inner_bytes));
@@ -819,6 +820,7 @@ void fem_solve_opts_default(fem_solve_opts* o) {
     o->history = nullptr;
     o->history_cap = 0;
     o->preconditioner = FEM_PC_MG;
+    o->level_timing = 0;
 }
 
 static fem_status check_opts(const fem_mesh* m, const fem_solve_opts* o) {
@@ -986,6 +988,15 @@ fem_status fem_solver_fmg(fem_solver* S, const double* b, double* x, fem_solve_s
         for (int l = 0; l < S->m->nlev && l < 8; ++l)
             stats->lambda_max[l] = S->lmax.size() > (size_t)l ? S->lmax[l] : 0.0;
     }
+    return FEM_OK;
+}
+
+fem_status fem_solver_set_level_timing(fem_solver* S, int32_t on) {
+    if (!S) {
+        set_error("fem_solver_set_level_timing: NULL solver");
+        return FEM_ERR_INVALID_ARG;
+    }
+    S->timing = on != 0;
     return FEM_OK;
 }
 

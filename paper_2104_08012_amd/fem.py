@@ -236,6 +236,7 @@ class SolveOptions:
     flexible: bool | None = None   # default: Polak-Ribiere beta in mixed precision
     history_cap: int = 1000
     preconditioner: str = "mg"     # "mg" or "jacobi"
+    level_timing: bool = False     # per-level V-cycle times in SolveResult.level_ms (adds events)
 
     def to_c(self):
         o = L.SolveOpts()
@@ -260,6 +261,7 @@ class SolveOptions:
         o.history = C.cast(hist, C.POINTER(C.c_double))
         o.history_cap = self.history_cap
         o.preconditioner = L.FEM_PC_JACOBI if self.preconditioner == "jacobi" else L.FEM_PC_MG
+        o.level_timing = 1 if self.level_timing else 0
         keep.append(hist)
         return o, keep, hist
 
@@ -317,6 +319,11 @@ class Solver:
                           [self._hist[i] for i in range(min(it + 1, self.opts.history_cap))],
                           st.coarse_iterations, status)
         return x, res
+
+    def set_level_timing(self, on: bool):
+        """Per-level V-cycle times (SolveResult.level_ms, coarse_ms) for later solves."""
+        check(lib().fem_solver_set_level_timing(self._h, 1 if on else 0), "fem_solver_set_level_timing")
+        return self
 
     def fmg(self, b: torch.Tensor, x: torch.Tensor | None = None):
         """One full-multigrid cycle as the solver (the paper's Listing 2 configuration)."""
