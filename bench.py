@@ -152,6 +152,11 @@ def roofline(p, kvar, C, N, NV, s, t, key):
                     "flops_per_action": F})
     else:
         out["alu_frac"] = round(tf / peak, 4)
+    # the same time against the bytes of the per-cell-factor layout (cell-to-dof map and six
+    # geometric factors per cell read, x and y once): the reference design's byte count
+    Bc = balg_bytes(C, N, nloc_of(p), s, NV if kvar else 0)
+    out["percell_layout_bytes"] = Bc
+    out["percell_layout_hbm_frac"] = round(Bc / t / 1e9 / HBM_PEAK_GBS, 4)
     return out
 
 

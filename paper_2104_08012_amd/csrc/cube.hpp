@@ -115,22 +115,30 @@ constexpr int cube_min_waves() {
     return (P == 1 || (sizeof(T) == 4 && !KVAR)) ? 4 : (sizeof(T) == 4 || !KVAR) ? 3 : 2;
 }
 
-template <int P, int B, bool KVAR, typename T>
-__global__ void __launch_bounds__(B * B * B, (cube_min_waves<P, KVAR, T>())) k_cube_apply(SArgs<T> a) {
+template <int P, int B, int R, bool KVAR, typename T>
+__global__ void __launch_bounds__(B * B * B * R, (cube_min_waves<P, KVAR, T>())) k_cube_apply(SArgs<T> a) {
     static_assert(B == 4, "one wave per brick of 4^3 cubes");
+    static_assert(R == 1 || P == 2, "bricks are merged along x for P2 only");
     constexpr int NL = nloc_of(P), NQ = nq_of(P, KVAR), PC = P + 1, NCP = PC * PC * PC;
     constexpr int NT = B * B * B, PB = P * B, QS = PB + 1, NQ3 = QS * QS * QS;
     constexpr int VS = B + 1, NV3 = VS * VS * VS;
     constexpr StiffTab<P, KVAR> TB{};
     constexpr CubeNodes<P> CN{};
     using XL = ClosureLayout<P>;
-    __shared__ T xc[XL::SIZE];       // closure values: x on input, the brick's sums on output
-    __shared__ double vc[3][NV3];    // vertex coordinates of the brick's 5^3 vertices
-    __shared__ T kl[KVAR ? NV3 : 1];  // coefficient at those vertices
-    const int brick = brick_of_block(blockIdx.x, gridDim.x);
-    const int nb = a.nb;
-    const int bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
-    const int lane = threadIdx.x;
+    // per wave: closure values (x on input, the brick's sums on output), the coordinates of the
+    // brick's 5^3 vertices and the coefficient there
+    __shared__ T xcs[R][XL::SIZE];
+    __shared__ double vcs[R][3][NV3];
+    __shared__ T kls[R][KVAR ? NV3 : 1];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / NT), lane = threadIdx.x % NT;
+    T* __restrict__ xc = xcs[wave];
+    double(*__restrict__ vc)[NV3] = vcs[wave];
+    T* __restrict__ kl = kls[wave];
+    // workgroup = R bricks along x (wave w: brick R px + w)
+    const int pid = brick_of_block(blockIdx.x, gridDim.x);
+    const int nb = a.nb, nbx = a.nbx;
+    const int px = pid % nbx, by = (pid / nbx) % nb, bz = pid / (nbx * nb);
+    const int bx = px * R + wave;
     const int lx = lane % B, ly = (lane / B) % B, lz = lane / (B * B);
     const uint32_t Lo = (uint32_t)a.Lout;
 
@@ -364,19 +372,35 @@ __global__ void __launch_bounds__(B * B * B, (cube_min_waves<P, KVAR, T>())) k_c
     }
     __syncthreads();
 
-    // ---- write-out: interior points to y, brick-face points to their slots ----
-    constexpr int QI = PB - 1, NIN = QI * QI * QI;
+    // ---- write-out: interior points to y, face points to their slots ----
+    constexpr int QI = PB - 1, NIN = QI * QI * QI, PBX = R * PB;
     const T alpha = a.alpha, beta = a.beta;
-    const uint32_t nbu = (uint32_t)nb, np = Lo - nbu - 1, tot = a.if_tot;
+    const uint32_t nbu = (uint32_t)nb, nbxu = (uint32_t)nbx, npx = Lo - nbxu - 1, tot = a.if_tot;
     T* __restrict__ slots = a.slots;
     if constexpr (P == 2) {
-        // lane tiles whose per-iteration offsets are uniform (plane, face) or compile-time (LDS)
+        // x faces shared by the workgroup's bricks: wave w > 0 adds the upper x face of wave w - 1
+        // (lower brick first) to its own lower x face, which is then complete and written to y
+        // as part of the interior; wave w < R - 1 leaves its upper x face to wave w + 1
+        if constexpr (R > 1) {
+            if (wave > 0) {
+                const T* __restrict__ xp = xcs[wave - 1];
+                for (int r = lane; r < QS * QS; r += NT) {
+                    const int lb = r % QS, lc = r / QS;
+                    const int i = XL::idx(0, lb, lc);
+                    xc[i] = xp[XL::idx(PB, lb, lc)] + xc[i];
+                }
+            }
+        }
+        // lane tiles whose per-iteration offsets are uniform (plane, face) or compile-time (LDS);
+        // la runs over [la_lo, PB - 1]: la = 0 is a workgroup face only for wave 0
+        const int la_lo = wave == 0 ? 1 : 0;
         const uint32_t LL = Lo * Lo;
-        {   // interior: lanes (la, lb) in [1, 7]^2, planes lc = 1..7
-            const int la = 1 + lane % QI, lb = 1 + lane / QI;
+        const uint32_t LA0 = (uint32_t)(wave * PB);   // workgroup-local x of the brick's la = 0
+        {   // interior: lanes (la, lb) = (lane % 8, 1 + lane / 8), lb <= 7, planes lc = 1..7
+            const int la = lane % PB, lb = 1 + lane / PB;
             const uint32_t o = gb + (uint32_t)la + Lo * (uint32_t)lb;
             const int i0 = XL::idx(la, lb, 0);
-            if (lane < QI * QI)
+            if (lb <= QI && la >= la_lo)
 #pragma unroll
                 for (int lc = 1; lc <= QI; ++lc) {
                     T v = alpha * xc[i0 + XL::PS * lc];
@@ -384,40 +408,47 @@ __global__ void __launch_bounds__(B * B * B, (cube_min_waves<P, KVAR, T>())) k_c
                     *reinterpret_cast<T*>(reinterpret_cast<char*>(a.y + (size_t)lc * LL) + o * (uint32_t)sizeof(T)) = v;
                 }
         }
-        {   // x faces (la = 0, PB): lanes (lb, c) = (lane % 9, lane / 9), lc = c + 7 blk
+        {   // workgroup x faces (wave 0: la = 0; wave R - 1: la = PB): lanes (lb, c) = (lane % 9,
+            // lane / 9), lc = c + 7 blk
             const int lb = lane % QS, c = lane / QS;
             const uint32_t o = (uint32_t)lb + Lo * (uint32_t)c;
 #pragma unroll
-            for (int sd = 0; sd < 2; ++sd)
+            for (int sd = 0; sd < 2; ++sd) {
+                if (sd == 0 ? wave != 0 : wave != R - 1) continue;
 #pragma unroll
                 for (int blk = 0; blk < 2; ++blk) {
                     if (lane < 7 * QS && (blk == 0 || c < 2)) {
                         const uint32_t code = (sd == 0 ? 1u : 0u) | (lb == 0 ? 2u : 0u) | (blk == 0 && c == 0 ? 4u : 0u);
-                        const uint32_t t = iface_x0<PB>(bx, by, bz, sd, Lo) + 7 * blk * Lo + o;
+                        const uint32_t t = iface_x0<PBX, PB>(px, by, bz, sd, Lo) + 7 * blk * Lo + o;
                         slots[(size_t)code * tot + t] = xc[XL::idx(sd * PB, lb, c) + 7 * blk * XL::PS];
                     }
                 }
+            }
         }
-        {   // y faces (lb = 0, PB): lanes (la, lc) = (1 + lane % 7, lane / 7)
-            const int la = 1 + lane % QI, lc = lane / QI;
-            const uint32_t o = (uint32_t)la + np * (uint32_t)lc;
-            const uint32_t code = lc == 0 ? 4u : 0u;
+        {   // y faces (lb = 0, PB): lanes (la, lc) = (lane % 8, lane / 8) for lc <= 7, then lc = 8
+            const int la = lane % PB, lc = lane / PB;
+            const uint32_t o = LA0 + (uint32_t)la + npx * (uint32_t)lc;
             const int i0 = XL::idx(la, 0, lc);
-            if (lane < QI * QS)
+            const uint32_t code = lc == 0 ? 4u : 0u;
+            if (la >= la_lo) {
 #pragma unroll
                 for (int sd = 0; sd < 2; ++sd) {
-                    const uint32_t t = iface_y0<PB>(bx, by, bz, sd, Lo, nbu, a.if_c0) + o;
-                    slots[(size_t)(code | (sd == 0 ? 2u : 0u)) * tot + t] = xc[i0 + XL::RS * PB * sd];
+                    const uint32_t ty = iface_y0<PBX, PB>(px, by, bz, sd, Lo, nbxu, a.if_c0);
+                    slots[(size_t)(code | (sd == 0 ? 2u : 0u)) * tot + ty + o] = xc[i0 + XL::RS * PB * sd];
+                    if (lane < PB)   // lc = PB
+                        slots[(size_t)(sd == 0 ? 2u : 0u) * tot + ty + o + npx * PB] =
+                            xc[i0 + XL::RS * PB * sd + XL::PS * PB];
                 }
+            }
         }
-        {   // z faces (lc = 0, PB): lanes (la, lb) in [1, 7]^2
-            const int la = 1 + lane % QI, lb = 1 + lane / QI;
-            const uint32_t o = (uint32_t)la + np * (uint32_t)lb;
+        {   // z faces (lc = 0, PB): lanes (la, lb) = (lane % 8, 1 + lane / 8), lb <= 7
+            const int la = lane % PB, lb = 1 + lane / PB;
+            const uint32_t o = LA0 + (uint32_t)la + npx * (uint32_t)lb;
             const int i0 = XL::idx(la, lb, 0);
-            if (lane < QI * QI)
+            if (lb <= QI && la >= la_lo)
 #pragma unroll
                 for (int sd = 0; sd < 2; ++sd) {
-                    const uint32_t t = iface_z0<PB>(bx, by, bz, sd, Lo, nbu, a.if_c01) + o;
+                    const uint32_t t = iface_z0<PBX, PB>(px, by, bz, sd, Lo, nbxu, nbu, a.if_c01) + o;
                     slots[(size_t)(sd == 0 ? 4u : 0u) * tot + t] = xc[i0 + XL::PS * PB * sd];
                 }
         }
@@ -437,19 +468,19 @@ __global__ void __launch_bounds__(B * B * B, (cube_min_waves<P, KVAR, T>())) k_c
         // slot plane is code = [la == 0] + 2 [lb == 0] + 4 [lc == 0].
         for (int r = lane; r < 2 * QS * QS; r += NT) {                 // x faces: la = 0, PB
             const int sd = r / (QS * QS), u = r % (QS * QS), lb = u % QS, lc = u / QS, la = sd * PB;
-            const uint32_t t = iface_x0<PB>(bx, by, bz, sd, Lo) + (uint32_t)lb + Lo * (uint32_t)lc;
+            const uint32_t t = iface_x0<PB, PB>(bx, by, bz, sd, Lo) + (uint32_t)lb + Lo * (uint32_t)lc;
             const uint32_t code = (sd == 0 ? 1u : 0u) | (lb == 0 ? 2u : 0u) | (lc == 0 ? 4u : 0u);
             slots[(size_t)code * tot + t] = xc[XL::idx(la, lb, lc)];
         }
         for (int r = lane; r < 2 * QI * QS; r += NT) {                 // y faces: lb = 0, PB; la inside
             const int sd = r / (QI * QS), u = r % (QI * QS), la = 1 + u % QI, lc = u / QI, lb = sd * PB;
-            const uint32_t t = iface_y0<PB>(bx, by, bz, sd, Lo, nbu, a.if_c0) + (uint32_t)la + np * (uint32_t)lc;
+            const uint32_t t = iface_y0<PB, PB>(bx, by, bz, sd, Lo, nbu, a.if_c0) + (uint32_t)la + npx * (uint32_t)lc;
             const uint32_t code = (sd == 0 ? 2u : 0u) | (lc == 0 ? 4u : 0u);
             slots[(size_t)code * tot + t] = xc[XL::idx(la, lb, lc)];
         }
         for (int r = lane; r < 2 * QI * QI; r += NT) {                 // z faces: lc = 0, PB; la, lb inside
             const int sd = r / (QI * QI), u = r % (QI * QI), la = 1 + u % QI, lb = 1 + u / QI, lc = sd * PB;
-            const uint32_t t = iface_z0<PB>(bx, by, bz, sd, Lo, nbu, a.if_c01) + (uint32_t)la + np * (uint32_t)lb;
+            const uint32_t t = iface_z0<PB, PB>(bx, by, bz, sd, Lo, nbu, nbu, a.if_c01) + (uint32_t)la + npx * (uint32_t)lb;
             const uint32_t code = sd == 0 ? 4u : 0u;
             slots[(size_t)code * tot + t] = xc[XL::idx(la, lb, lc)];
         }

@@ -12,9 +12,16 @@ namespace {
 template <int KIND, typename T, int P, int B, bool KV>
 void launch_main(const SArgs<T>& a, int64_t nbricks, hipStream_t s) {
     if constexpr (KIND == K_APPLY && P <= 2 && B == 4) {
-        // one thread per cube for the low degrees (see cube.hpp), where the level has the cube data
+        // one thread per cube for the low degrees (see cube.hpp), where the level has the cube
+        // data; R = nb / nbx bricks along x per workgroup
         if (a.vxyz) {
-            hipLaunchKernelGGL((k_cube_apply<P, B, KV, T>), dim3((unsigned)nbricks), dim3(B * B * B), 0, s, a);
+            const int R = a.nb / a.nbx;
+            const unsigned grid = (unsigned)(nbricks / R);
+            if constexpr (P == 2) {
+                if (R == 4) { hipLaunchKernelGGL((k_cube_apply<P, B, 4, KV, T>), dim3(grid), dim3(4 * 64), 0, s, a); return; }
+                if (R == 2) { hipLaunchKernelGGL((k_cube_apply<P, B, 2, KV, T>), dim3(grid), dim3(2 * 64), 0, s, a); return; }
+            }
+            hipLaunchKernelGGL((k_cube_apply<P, B, 1, KV, T>), dim3(grid), dim3(64), 0, s, a);
             return;
         }
     }
@@ -48,9 +55,14 @@ void launch_p(int P, int B, bool kv, const SArgs<T>& a, int64_t nbricks, hipStre
 template <typename T, int PO>
 void launch_fix_b(int B, const SArgs<T>& a, const FixGeom& fg, hipStream_t s) {
     const unsigned grid = (fg.total + 255) / 256;
-    if (B == 4) hipLaunchKernelGGL((k_fixup<PO, 4, T>), dim3(grid), dim3(256), 0, s, a, fg);
-    else if (B == 2) hipLaunchKernelGGL((k_fixup<PO, 2, T>), dim3(grid), dim3(256), 0, s, a, fg);
-    else hipLaunchKernelGGL((k_fixup<PO, 1, T>), dim3(grid), dim3(256), 0, s, a, fg);
+    const int R = a.nb / a.nbx;
+    if constexpr (PO == 2) {
+        if (B == 4 && R == 4) { hipLaunchKernelGGL((k_fixup<PO, 4, 4, T>), dim3(grid), dim3(256), 0, s, a, fg); return; }
+        if (B == 4 && R == 2) { hipLaunchKernelGGL((k_fixup<PO, 4, 2, T>), dim3(grid), dim3(256), 0, s, a, fg); return; }
+    }
+    if (B == 4) hipLaunchKernelGGL((k_fixup<PO, 4, 1, T>), dim3(grid), dim3(256), 0, s, a, fg);
+    else if (B == 2) hipLaunchKernelGGL((k_fixup<PO, 2, 1, T>), dim3(grid), dim3(256), 0, s, a, fg);
+    else hipLaunchKernelGGL((k_fixup<PO, 1, 1, T>), dim3(grid), dim3(256), 0, s, a, fg);
 }
 
 template <typename T>
@@ -109,21 +121,26 @@ fem_status run_kind(const fem_mesh& m, int level, bool kvar, const ScatterIO<T>&
     a.xid = io.xid;
     a.vxyz = L.cube ? dptr<double>(m, L.d_vsoa) : nullptr;
     a.nv = (uint32_t)L.NV;
-    const int64_t Lo = a.Lout, nb = L.nb, np = Lo - nb - 1;
-    const int64_t c0 = (nb + 1) * Lo * Lo, c1 = (nb + 1) * np * Lo, c2 = (nb + 1) * np * np;
-    a.if_c0 = (uint32_t)c0;
-    a.if_c01 = (uint32_t)(c0 + c1);
-    a.if_tot = (uint32_t)(c0 + c1 + c2);
+    // the P2 cube kernel merges R = 4 (or 2) bricks along x in one workgroup; the interface
+    // numbering then has bricks of span R p B along x (iface.hpp)
+    const int R = (KIND == K_APPLY && m.p == 2 && L.B == 4 && L.cube) ? (L.nb % 4 == 0 ? 4 : L.nb % 2 == 0 ? 2 : 1) : 1;
+    a.nbx = L.nb / R;
+    const int64_t Lo = a.Lout, nb = L.nb, nbx = a.nbx, np = Lo - nb - 1, npx = Lo - nbx - 1;
+    const IfaceCounts ic = iface_counts((uint32_t)Lo, (uint32_t)nbx, (uint32_t)nb);
+    a.if_c0 = ic.c0;
+    a.if_c01 = ic.c01;
+    a.if_tot = ic.total;
     launch_p<KIND, T>(m.p, L.B, kvar, a, L.nbricks, s);
     FixGeom fg;
-    fg.cnt0 = (uint32_t)c0;
-    fg.cnt01 = (uint32_t)(c0 + c1);
-    fg.total = (uint32_t)(c0 + c1 + c2);
+    fg.cnt0 = ic.c0;
+    fg.cnt01 = ic.c01;
+    fg.total = ic.total;
+    fg.nbx = (uint32_t)nbx;
     fg.L = make_div((uint32_t)Lo);
     fg.LL = make_div((uint32_t)(Lo * Lo));
-    fg.np = make_div((uint32_t)std::max<int64_t>(np, 1));
-    fg.npL = make_div((uint32_t)std::max<int64_t>(np * Lo, 1));
-    fg.npnp = make_div((uint32_t)std::max<int64_t>(np * np, 1));
+    fg.npx = make_div((uint32_t)std::max<int64_t>(npx, 1));
+    fg.npxL = make_div((uint32_t)std::max<int64_t>(npx * Lo, 1));
+    fg.npnpx = make_div((uint32_t)std::max<int64_t>(np * npx, 1));
     launch_fix<T>(po, L.B, a, fg, s);
     return check_launch("scatter kernel");
 }

@@ -35,6 +35,7 @@ namespace fem {
 template <typename T>
 struct SArgs {
     int n, nb, Lout;                 // cubes per direction, bricks per direction, output lattice
+    int nbx;                         // bricks along x of the interface numbering (nb / R)
     int64_t C;                       // cells of the level the kernel loops over
     const int32_t* map;              // SoA nloc * C (sign bit: boundary dof)
     const T* G;                      // SoA 6 * C
@@ -101,7 +102,7 @@ struct Producer;
 template <int PB, typename T>
 __device__ __forceinline__ void put_slot(const SArgs<T>& a, int bx, int by, int bz, int la, int lb, int lc, T v) {
     const uint32_t I = (uint32_t)(bx * PB + la), J = (uint32_t)(by * PB + lb), K = (uint32_t)(bz * PB + lc);
-    const uint32_t t = iface_index<PB>(I, J, K, (uint32_t)a.Lout, (uint32_t)a.nb, a.if_c0, a.if_c01);
+    const uint32_t t = iface_index<PB, PB>(I, J, K, (uint32_t)a.Lout, (uint32_t)a.nb, (uint32_t)a.nb, a.if_c0, a.if_c01);
     const uint32_t code = (la == 0 ? 1u : 0u) | (lb == 0 ? 2u : 0u) | (lc == 0 ? 4u : 0u);
     a.slots[(size_t)code * a.if_tot + t] = v;
 }
@@ -368,40 +369,37 @@ __device__ __forceinline__ uint32_t udiv(uint32_t n, Div v) {
 
 struct FixGeom {
     uint32_t cnt0, cnt01, total;   // family boundaries: x planes, + y planes, + z planes
-    Div L, LL, np, npL, npnp;
+    uint32_t nbx;                  // bricks along x (of span R PB)
+    Div L, LL, npx, npxL, npnpx;   // L, L^2, non-x-plane count npx, L npx, np npx
 };
 
-template <int PO, int B, typename T>
+// R: bricks merged along x by the kernel that wrote the slots (the x span of a brick is R PB).
+template <int PO, int B, int R, typename T>
 __global__ void __launch_bounds__(256) k_fixup(SArgs<T> a, FixGeom fg) {
-    constexpr int PB = PO * B;
+    constexpr int PB = PO * B, PBX = R * PB;
     const uint32_t t = blockIdx.x * 256u + threadIdx.x;
     if (t >= fg.total) return;
-    const uint32_t L = fg.L.d, nb = (uint32_t)a.nb, np = fg.np.d;
+    const uint32_t L = fg.L.d, nb = (uint32_t)a.nb, nbx = fg.nbx, npx = fg.npx.d;
     uint32_t I, J, K;
     if (t < fg.cnt0) {
         const uint32_t pl = udiv(t, fg.LL), r = t - pl * fg.LL.d;
-        I = pl * PB;
+        I = pl * PBX;
         K = udiv(r, fg.L);
         J = r - K * L;
     } else if (t < fg.cnt01) {
         const uint32_t u = t - fg.cnt0;
-        const uint32_t pl = udiv(u, fg.npL), r = u - pl * fg.npL.d;
+        const uint32_t pl = udiv(u, fg.npxL), r = u - pl * fg.npxL.d;
         J = pl * PB;
-        K = udiv(r, fg.np);
-        const uint32_t iu = r - K * np;
-        if constexpr (PB > 1) I = (iu / (PB - 1)) * PB + iu % (PB - 1) + 1; else I = iu;
+        K = udiv(r, fg.npx);
+        const uint32_t iu = r - K * npx;
+        if constexpr (PBX > 1) I = (iu / (PBX - 1)) * PBX + iu % (PBX - 1) + 1; else I = iu;
     } else {
         const uint32_t u = t - fg.cnt01;
-        const uint32_t pl = udiv(u, fg.npnp), r = u - pl * fg.npnp.d;
+        const uint32_t pl = udiv(u, fg.npnpx), r = u - pl * fg.npnpx.d;
         K = pl * PB;
-        const uint32_t ju = udiv(r, fg.np), iu = r - ju * np;
-        if constexpr (PB > 1) {
-            I = (iu / (PB - 1)) * PB + iu % (PB - 1) + 1;
-            J = (ju / (PB - 1)) * PB + ju % (PB - 1) + 1;
-        } else {
-            I = iu;
-            J = ju;
-        }
+        const uint32_t ju = udiv(r, fg.npx), iu = r - ju * npx;
+        if constexpr (PBX > 1) I = (iu / (PBX - 1)) * PBX + iu % (PBX - 1) + 1; else I = iu;
+        if constexpr (PB > 1) J = (ju / (PB - 1)) * PB + ju % (PB - 1) + 1; else J = ju;
     }
     const int64_t g = I + (int64_t)L * (J + (int64_t)L * K);
     const bool bnd = I == 0 || J == 0 || K == 0 || I == L - 1 || J == L - 1 || K == L - 1;
@@ -419,9 +417,10 @@ __global__ void __launch_bounds__(256) k_fixup(SArgs<T> a, FixGeom fg) {
     bool lo[3], hi[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const uint32_t q = X[d] / PB, r = X[d] - q * PB;
+        const uint32_t span = d == 0 ? PBX : PB, nbd = d == 0 ? nbx : nb;
+        const uint32_t q = X[d] / span, r = X[d] - q * span;
         lo[d] = r != 0 || q >= 1;
-        hi[d] = r == 0 && q < nb;
+        hi[d] = r == 0 && q < nbd;
     }
     T v[8];
 #pragma unroll

@@ -1,6 +1,8 @@
-"""The per-face affine numbering of interface slots (the cube kernel's write-out) equals the
-point-wise numbering, stays inside the slot array and gives every (brick, face point) pair its own
-slot, for brick spans PB = 1, 2, 3, 4, 8, 12 and 1-5 bricks per direction."""
+"""Interface numbering (iface.hpp): the per-face affine indices equal the point-wise numbering,
+stay inside the slot array and give every (brick, face point) pair its own slot, for cubic bricks
+(span 1-12, 1-5 per direction) and bricks merged along x (span 2-4 PB); and the merged-brick
+write-out regions of the cube kernel write every non-interface point to y exactly once and every
+(brick, interface point) slot exactly once."""
 import os
 import shutil
 import subprocess
