@@ -3,7 +3,9 @@
 Tolerances: FP64 actions 1e-12 relative (2-norm, random x ~ U(-1,1)); FP32 actions 2e-6
 relative (single-precision rounding of ~30 terms per entry on the uniform mesh); transfers,
 diagonal, mass and gradient 1e-12 in FP64.  Mesh sizes span several bricks and odd sizes that
-fall back to smaller bricks (n = 5: 1-cube bricks, n = 6: 2-cube bricks).
+fall back to smaller bricks (n = 5: 1-cube bricks, n = 6: 2-cube bricks); for P2 the cube kernel
+merges R bricks along x per workgroup: n = 16 (4 bricks per direction) R = 4, n = 8 R = 2,
+n = 12 (3 bricks) R = 1.
 """
 import numpy as np
 import pytest
@@ -15,7 +17,8 @@ from tests.gpu_util import banner, make_pair, oracle_A, rel
 
 torch = pytest.importorskip("torch")
 
-CASES = [(5, 1, 0.0), (6, 2, 0.15), (8, 1, 0.0), (8, 2, 0.15), (8, 3, 0.15), (12, 2, 0.0), (4, 3, 0.0)]
+CASES = [(5, 1, 0.0), (6, 2, 0.15), (8, 1, 0.0), (8, 2, 0.15), (8, 3, 0.15), (12, 2, 0.0), (16, 2, 0.15),
+         (4, 3, 0.0)]
 
 
 def _t(a, dtype=torch.float64):
@@ -40,7 +43,7 @@ def test_apply_fp64_parity(n, p, jit, kvar):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("n,p,jit", [(8, 2, 0.15), (6, 3, 0.0), (5, 1, 0.15)])
+@pytest.mark.parametrize("n,p,jit", [(8, 2, 0.15), (16, 2, 0.15), (6, 3, 0.0), (5, 1, 0.15)])
 @pytest.mark.parametrize("kvar", [False, True])
 def test_apply_fp32_parity(n, p, jit, kvar):
     banner(f"apply fp32 n={n} p={p} kvar={kvar}")
@@ -55,9 +58,10 @@ def test_apply_fp32_parity(n, p, jit, kvar):
 
 
 @pytest.mark.gpu
-def test_apply_axpby_and_determinism():
-    banner("apply axpby / determinism")
-    mesh, levels = make_pair(8, 0, 2, 0.15)
+@pytest.mark.parametrize("n", [8, 16])
+def test_apply_axpby_and_determinism(n):
+    banner(f"apply axpby / determinism n={n}")
+    mesh, levels = make_pair(n, 0, 2, 0.15)
     lev = levels[0]
     x = fem_inputs.uniform_vector(lev.n_dofs, 0)
     z = fem_inputs.uniform_vector(lev.n_dofs, 7)
