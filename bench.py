@@ -152,6 +152,11 @@ def roofline(p, kvar, C, N, NV, s, t, key):
                     "flops_per_action": F})
     else:
         out["alu_frac"] = round(tf / peak, 4)
+    # what was timed: one action = the cell kernel and the fix-up, bracketed together by HIP
+    # events on the library's stream (the kernel trace in profiles/ lists the two separately)
+    cube = p <= 2 and n % 4 == 0
+    out["kernels"] = ("k_cube_apply + k_fixup" if cube else "k_brick + k_fixup") + " (one action)"
+    out["duration_us"] = round(t * 1e6, 2)
     # the same time against the bytes of the per-cell-factor layout (cell-to-dof map and six
     # geometric factors per cell read, x and y once): the reference design's byte count
     Bc = balg_bytes(C, N, nloc_of(p), s, NV if kvar else 0)
