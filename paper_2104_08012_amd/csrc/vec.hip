@@ -334,45 +334,61 @@ __global__ void __launch_bounds__(256) k_sym_pack(int64_t n, const double* __res
     }
 }
 
+// 16-byte vector of tile entries
 template <typename TA>
-struct Pair;
+struct Vec16;
 template <>
-struct Pair<double> { using type = double2; };
+struct Vec16<double> {
+    using type = double2;
+    static constexpr int n = 2;
+    __device__ static double get(const double2& v, int k) { return k == 0 ? v.x : v.y; }
+};
 template <>
-struct Pair<float> { using type = float2; };
+struct Vec16<float> {
+    using type = float4;
+    static constexpr int n = 4;
+    __device__ static float get(const float4& v, int k) { return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w; }
+};
 
 // Per tile t = (I, J): prow[t] = A_IJ x_J and, off the diagonal, pcol[t] = A_IJ^T x_I
 // (64 entries each), accumulated in FP64 whatever the tile's storage type TA.  Persistent blocks:
-// block b takes tiles b, b + gridDim.x, ...; the next tile is loaded into registers while the
-// current one, staged in LDS, is multiplied, so the stream of tile reads does not stop for the
-// arithmetic.  Thread (e, q) of the 256 sums a quarter (16 terms, fixed order) of row e and of
-// column e, and the quarters are added in order q = 0..3.
-template <typename TA>
+// block b takes tiles b, b + gridDim.x, ...; the next two tiles are loaded into registers (16-byte
+// loads) while the current one, staged in LDS, is multiplied, so the stream of tile reads does not
+// stop for the arithmetic.  Thread (e, q) of the 256 sums a quarter (16 terms, fixed order) of row
+// e and of column e, and the quarters are added in order q = 0..3.
+template <typename TA, int DEPTH>
 __global__ void __launch_bounds__(256) k_sym_tiles(int64_t n, int64_t ntiles, const TA* __restrict__ Ap,
                                                    const double* __restrict__ xc, double* __restrict__ prow,
                                                    double* __restrict__ pcol) {
-    using P2 = typename Pair<TA>::type;
-    constexpr int NPT = ST * ST / 2 / 256;   // pairs per thread and tile
+    using V = Vec16<TA>;
+    using VT16 = typename V::type;
+    constexpr int NPT = ST * ST / V::n / 256;   // vectors per thread and tile
     __shared__ TA sa[ST][ST + 1];
     __shared__ double sx[2][ST];
     __shared__ double sq[2][4][ST];
+    const int64_t G = gridDim.x;
     int64_t t = blockIdx.x;
     if (t >= ntiles) return;
-    P2 cur[NPT];
+    VT16 cur[NPT], nxt[NPT];
     {
-        const P2* tile = reinterpret_cast<const P2*>(Ap + t * ST * ST);
+        const VT16* tile = reinterpret_cast<const VT16*>(Ap + t * ST * ST);
 #pragma unroll
         for (int k = 0; k < NPT; ++k) cur[k] = tile[threadIdx.x + 256 * k];
+        if (DEPTH == 2 && t + G < ntiles) {
+            const VT16* tn = reinterpret_cast<const VT16*>(Ap + (t + G) * ST * ST);
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) nxt[k] = tn[threadIdx.x + 256 * k];
+        }
     }
     const int e = threadIdx.x % ST, q = threadIdx.x / ST;
-    for (; t < ntiles; t += gridDim.x) {
+    for (; t < ntiles; t += G) {
         int I, J;
         tile_of(t, I, J);
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-            const int pe = threadIdx.x + 256 * k, r = (2 * pe) / ST, c = (2 * pe) % ST;
-            sa[r][c] = cur[k].x;
-            sa[r][c + 1] = cur[k].y;
+            const int pe = threadIdx.x + 256 * k, r = (V::n * pe) / ST, c = (V::n * pe) % ST;
+#pragma unroll
+            for (int u = 0; u < V::n; ++u) sa[r][c + u] = V::get(cur[k], u);
         }
         if (threadIdx.x < ST) {
             const int64_t jj = (int64_t)J * ST + threadIdx.x, ii = (int64_t)I * ST + threadIdx.x;
@@ -380,9 +396,17 @@ __global__ void __launch_bounds__(256) k_sym_tiles(int64_t n, int64_t ntiles, co
             sx[1][threadIdx.x] = ii < n ? xc[ii] : 0.0;
         }
         __syncthreads();
-        const int64_t tn = t + gridDim.x;
-        if (tn < ntiles) {
-            const P2* tile = reinterpret_cast<const P2*>(Ap + tn * ST * ST);
+        if constexpr (DEPTH == 2) {
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) cur[k] = nxt[k];
+            const int64_t t2 = t + 2 * G;
+            if (t2 < ntiles) {
+                const VT16* tile = reinterpret_cast<const VT16*>(Ap + t2 * ST * ST);
+#pragma unroll
+                for (int k = 0; k < NPT; ++k) nxt[k] = tile[threadIdx.x + 256 * k];
+            }
+        } else if (t + G < ntiles) {
+            const VT16* tile = reinterpret_cast<const VT16*>(Ap + (t + G) * ST * ST);
 #pragma unroll
             for (int k = 0; k < NPT; ++k) cur[k] = tile[threadIdx.x + 256 * k];
         }
@@ -592,6 +616,17 @@ void sym_pack_launch(int64_t n, const double* A, TA* Ap, hipStream_t s) {
 template void sym_pack_launch<double>(int64_t, const double*, double*, hipStream_t);
 template void sym_pack_launch<float>(int64_t, const double*, float*, hipStream_t);
 
+#ifndef FEM_TILE_DEPTH64
+#define FEM_TILE_DEPTH64 1
+#endif
+#ifndef FEM_TILE_DEPTH32
+#define FEM_TILE_DEPTH32 2
+#endif
+// tiles loaded ahead per block: the FP64 instance keeps 4 blocks per CU with one, the FP32 one
+// (16-byte loads of four entries) gains from two
+template <typename TA>
+constexpr int kTileDepth = sizeof(TA) == 8 ? FEM_TILE_DEPTH64 : FEM_TILE_DEPTH32;
+
 template <typename TA>
 void sym_solve_launch(int L, const TA* Ap, const double* xl, double* xc, double* part, double* yl,
                       hipStream_t s) {
@@ -603,10 +638,21 @@ void sym_solve_launch(int L, const TA* Ap, const double* xl, double* xc, double*
     hipLaunchKernelGGL(k_gather_interior, dim3(grid_for(m)), dim3(VT), 0, s, L, xl, xc);
     double* prow = part;
     double* pcol = part + ntl * ST;
-    // persistent blocks, as many as are resident at once on 256 CUs: 4 per CU for FP64 tiles
-    // (36 KB of LDS each), 6 for FP32 tiles (80 VGPRs: 6 waves per SIMD)
-    const int64_t nblk = std::min<int64_t>(ntl, sizeof(TA) == 8 ? 1024 : 1536);
-    hipLaunchKernelGGL((k_sym_tiles<TA>), dim3((unsigned)nblk), dim3(256), 0, s, m, ntl, Ap, (const double*)xc,
+    // persistent blocks: as many as are resident at once (occupancy of this instance times the
+    // CU count, queried once per tile type)
+    static int resident = 0;
+    if (resident == 0) {
+        int dev = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sym_tiles<TA, kTileDepth<TA>>, 256, 0) == hipSuccess && cus > 0 &&
+            per > 0)
+            resident = cus * per;
+        else
+            resident = 256;
+    }
+    const int64_t nblk = std::min<int64_t>(ntl, resident);
+    hipLaunchKernelGGL((k_sym_tiles<TA, kTileDepth<TA>>), dim3((unsigned)nblk), dim3(256), 0, s, m, ntl, Ap, (const double*)xc,
                        prow, pcol);
     hipLaunchKernelGGL(k_sym_reduce, dim3((unsigned)nt), dim3(4 * ST), 0, s, L, m, nt, (const double*)prow,
                        (const double*)pcol, yl);
