@@ -83,7 +83,8 @@ typedef struct fem_mesh fem_mesh;
 /* Build a mesh hierarchy on the host: topology, numbering, per-cell geometric factors
  * G = |det J| J^-1 J^-T, cell-to-dof maps, brick reduction and transfer tables.
  * Section 2, Listing 1 (UnitCubeMesh, MeshHierarchy, FunctionSpace).  Host only.
- * Errors: FEM_ERR_INVALID_ARG (NULL, n < 1, degree outside 1..3, sizes beyond int32 indexing),
+ * Errors: FEM_ERR_INVALID_ARG (NULL, n < 1, degree outside 1..3, a level with 2^29 cells or
+ *         dofs or more: the kernels use 32-bit byte offsets per array),
  *         FEM_ERR_INVALID_ARG when jitter inverts a cell. */
 fem_status fem_mesh_create(const fem_mesh_desc* desc, fem_mesh** out);
 

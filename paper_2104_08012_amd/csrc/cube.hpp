@@ -28,12 +28,6 @@
 
 namespace fem {
 
-// load with a 32-bit byte offset from a uniform base (scalar-base addressing)
-template <typename T>
-__device__ __forceinline__ T ldg(const T* base, uint32_t idx) {
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)(idx * (uint32_t)sizeof(T)));
-}
-
 // 1 / d from the hardware reciprocal refined by two Newton steps r <- r + r (1 - d r) (quadratic
 // convergence: well below an ulp of error left for the accuracy the kernels need).
 __device__ __forceinline__ double recip(double d) {
@@ -42,6 +36,15 @@ __device__ __forceinline__ double recip(double d) {
     r = fma(r, e, r);
     e = fma(-d, r, 1.0);
     return fma(r, e, r);
+}
+
+// Order a wave's own LDS stores before its later LDS loads (a wave's LDS operations execute in
+// issue order; this keeps the compiler from moving memory operations across the point).  Used
+// where a wave only reads back its own region, so the other waves of the workgroup need not wait.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Cross-lane moves.  DPP row_shr:4 gives lane l the value of lane l - 4 inside its row of 16 lanes
@@ -222,7 +225,7 @@ __global__ void __launch_bounds__(B * B * B * R, (cube_min_waves<P, KVAR, T>()))
             }
         }
     }
-    __syncthreads();
+    wave_sync();   // each wave reads back only its own staged data
 
     // ---- the six tetrahedra of the lane's cube ----
     const int xb = XL::idx(P * lx, P * ly, P * lz);       // LDS index of the cube's point 0
@@ -363,14 +366,14 @@ __global__ void __launch_bounds__(B * B * B * R, (cube_min_waves<P, KVAR, T>()))
     }
     // Each closure point (la, lb, lc) of the brick is now held by the cube min(la / P, B - 1)
     // (and likewise in y, z) at local index la - P * that cube.
-    __syncthreads();
+    wave_sync();   // the held points overwrite this wave's own closure values
 #pragma unroll
     for (int j = 0; j < NCP; ++j) {
         const int ja = j % PC, jb = (j / PC) % PC, jc = j / (PC * PC);
         if ((ja < P || lx == B - 1) && (jb < P || ly == B - 1) && (jc < P || lz == B - 1))
             xc[xb + xo_of<P>(j)] = ys[j];
     }
-    __syncthreads();
+    __syncthreads();   // the exchange reads the neighbouring wave's closure
 
     // ---- write-out: interior points to y, face points to their slots ----
     constexpr int QI = PB - 1, NIN = QI * QI * QI, PBX = R * PB;

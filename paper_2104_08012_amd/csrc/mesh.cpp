@@ -108,6 +108,10 @@ static void build_level(HostLevel& L, const std::vector<std::array<int, 4>>& mi)
     L.L = p * n + 1;
     L.C = 6LL * n * n * n;
     L.N = (int64_t)L.L * L.L * L.L;
+    // the kernels address every array (and every structure-of-arrays plane) with 32-bit byte
+    // offsets of 8-byte entries
+    if (L.C >= (1LL << 29) || L.N >= (1LL << 29))
+        throw std::runtime_error("level too large: at most 2^29 cells and 2^29 dofs per level");
     L.NI = (int64_t)(L.L - 2) * (L.L - 2) * (L.L - 2);
     L.NV = (int64_t)(n + 1) * (n + 1) * (n + 1);
     L.nbricks = (int64_t)L.nb * L.nb * L.nb;

@@ -86,10 +86,27 @@ __device__ __forceinline__ void cell_vertices(int bx, int by, int bz, int cl, in
     }
 }
 
+// Loads with a 32-bit element offset from a uniform base, so the base stays in scalar registers
+// and each lane adds one 32-bit offset (mesh creation keeps every level below 2^29 cells and
+// dofs, so each array and each structure-of-arrays plane is addressed within 4 GiB).
+template <typename T>
+__device__ __forceinline__ T ldg(const T* base, uint32_t idx) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)(idx * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void stg(T* base, uint32_t idx, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(idx * (uint32_t)sizeof(T))) = v;
+}
+// entry c of plane k of a structure-of-arrays field with C entries per plane
+template <typename T>
+__device__ __forceinline__ T soa(const T* p, int k, int64_t C, int64_t c) {
+    return ldg(p + (size_t)k * (size_t)C, (uint32_t)c);
+}
+
 template <typename T>
 __device__ __forceinline__ T gather(const T* __restrict__ x, int32_t m, int mask) {
     const uint32_t u = (uint32_t)m;
-    const T v = x[u & 0x7fffffffu];
+    const T v = ldg(x, u & 0x7fffffffu);
     return (mask && (m < 0)) ? T(0) : v;
 }
 
@@ -116,11 +133,11 @@ struct Producer<K_APPLY, P, B, KVAR, T> {
                                                T* out) {
         constexpr StiffTab<P, KVAR> TB{};
         const int64_t C = a.C;
-        const T g00 = a.G[c], g11 = a.G[C + c], g22 = a.G[2 * C + c];
-        const T g01 = a.G[3 * C + c], g02 = a.G[4 * C + c], g12 = a.G[5 * C + c];
+        const T g00 = soa(a.G, 0, C, c), g11 = soa(a.G, 1, C, c), g22 = soa(a.G, 2, C, c);
+        const T g01 = soa(a.G, 3, C, c), g02 = soa(a.G, 4, C, c), g12 = soa(a.G, 5, C, c);
         T xs[NL];
 #pragma unroll
-        for (int i = 0; i < NL; ++i) xs[i] = gather(a.x, a.map[i * C + c], a.mask_cols);
+        for (int i = 0; i < NL; ++i) xs[i] = gather(a.x, soa(a.map, i, C, c), a.mask_cols);
         T kv[4] = {T(1), T(1), T(1), T(1)};
         if constexpr (KVAR) {
             int V[4][3];
@@ -167,8 +184,8 @@ struct Producer<K_DIAG, P, B, KVAR, T> {
                                                T* out) {
         const T* __restrict__ tab = a.tab;
         const int64_t C = a.C;
-        const T g00 = a.G[c], g11 = a.G[C + c], g22 = a.G[2 * C + c];
-        const T g01 = a.G[3 * C + c], g02 = a.G[4 * C + c], g12 = a.G[5 * C + c];
+        const T g00 = soa(a.G, 0, C, c), g11 = soa(a.G, 1, C, c), g22 = soa(a.G, 2, C, c);
+        const T g01 = soa(a.G, 3, C, c), g02 = soa(a.G, 4, C, c), g12 = soa(a.G, 5, C, c);
         T kv[4] = {T(1), T(1), T(1), T(1)};
         if constexpr (KVAR) {
             int V[4][3];
@@ -200,12 +217,12 @@ struct Producer<K_MASS, P, B, KVAR, T> {
     static constexpr int NL = nloc_of(P);
     __device__ __forceinline__ static void run(const SArgs<T>& a, int64_t c, int, int, int, int, T* out) {
         const int64_t C = a.C;
-        const T g00 = a.G[c], g11 = a.G[C + c], g22 = a.G[2 * C + c];
-        const T g01 = a.G[3 * C + c], g02 = a.G[4 * C + c], g12 = a.G[5 * C + c];
+        const T g00 = soa(a.G, 0, C, c), g11 = soa(a.G, 1, C, c), g22 = soa(a.G, 2, C, c);
+        const T g01 = soa(a.G, 3, C, c), g02 = soa(a.G, 4, C, c), g12 = soa(a.G, 5, C, c);
         const T det = g00 * (g11 * g22 - g12 * g12) - g01 * (g01 * g22 - g12 * g02) + g02 * (g01 * g12 - g11 * g02);
         T xs[NL];
 #pragma unroll
-        for (int i = 0; i < NL; ++i) xs[i] = gather(a.x, a.map[i * C + c], a.mask_cols);
+        for (int i = 0; i < NL; ++i) xs[i] = gather(a.x, soa(a.map, i, C, c), a.mask_cols);
 #pragma unroll
         for (int i = 0; i < NL; ++i) {
             T s = T(0);
@@ -227,7 +244,7 @@ struct Producer<K_RESTRICT, P, B, KVAR, T> {
         cell_vertices<B>(bx, by, bz, cl, V);
         uint32_t w[NW];
 #pragma unroll
-        for (int i = 0; i < NW; ++i) w[i] = a.owner[i * a.C + c];
+        for (int i = 0; i < NW; ++i) w[i] = soa(a.owner, i, a.C, c);
 #pragma unroll
         for (int j = 0; j < NL; ++j) out[j] = T(0);
         const int64_t Lf = a.Lin;
@@ -254,12 +271,12 @@ struct Producer<K_GRAD, P, B, KVAR, T> {
     __device__ __forceinline__ static void run(const SArgs<T>& a, int64_t c, int, int, int, int, T* out) {
         const T* __restrict__ tab = a.tab;
         const int64_t C = a.C;
-        const T g00 = a.G[c], g11 = a.G[C + c], g22 = a.G[2 * C + c];
-        const T g01 = a.G[3 * C + c], g02 = a.G[4 * C + c], g12 = a.G[5 * C + c];
+        const T g00 = soa(a.G, 0, C, c), g11 = soa(a.G, 1, C, c), g22 = soa(a.G, 2, C, c);
+        const T g01 = soa(a.G, 3, C, c), g02 = soa(a.G, 4, C, c), g12 = soa(a.G, 5, C, c);
         T us[NL], ls[NL];
 #pragma unroll
         for (int i = 0; i < NL; ++i) {
-            const int32_t m = a.map[i * C + c];
+            const int32_t m = soa(a.map, i, C, c);
             us[i] = gather(a.x, m, 1);
             ls[i] = gather(a.x2, m, 1);
         }
@@ -287,16 +304,16 @@ struct Producer<K_GRAD, P, B, KVAR, T> {
 };
 
 template <typename T>
-__device__ __forceinline__ void finalize(const SArgs<T>& a, int64_t g, T acc, bool bnd) {
+__device__ __forceinline__ void finalize(const SArgs<T>& a, uint32_t g, T acc, bool bnd) {
     T v = acc;
     if (bnd) {
-        if (a.row_mode == ROW_IDENTITY) v = a.xid[g];
+        if (a.row_mode == ROW_IDENTITY) v = ldg(a.xid, g);
         else if (a.row_mode == ROW_ZERO) v = T(0);
         else if (a.row_mode == ROW_ONE) v = T(1);
     }
     T r = a.alpha * v;
-    if (a.beta != T(0)) r += a.beta * a.z[g];
-    a.y[g] = r;
+    if (a.beta != T(0)) r += a.beta * ldg(a.z, g);
+    stg(a.y, g, r);
 }
 
 // Sum, for every closure point of one type, the LDS entries of the cells that contain it (in the
@@ -323,7 +340,7 @@ __device__ __forceinline__ void reduce_type(const SArgs<T>& a, const T* ys, int 
         if (la == 0 || la == PB || lb == 0 || lb == PB || lc == 0 || lc == PB) {
             put_slot<PB, T>(a, bx, by, bz, la, lb, lc, acc);
         } else {
-            const int64_t g = (bx * PB + la) + L * ((by * PB + lb) + L * (int64_t)(bz * PB + lc));
+            const uint32_t g = (uint32_t)(bx * PB + la) + (uint32_t)L * ((uint32_t)(by * PB + lb) + (uint32_t)L * (uint32_t)(bz * PB + lc));
             finalize(a, g, acc, false);
         }
     }
@@ -401,13 +418,13 @@ __global__ void __launch_bounds__(256) k_fixup(SArgs<T> a, FixGeom fg) {
         if constexpr (PBX > 1) I = (iu / (PBX - 1)) * PBX + iu % (PBX - 1) + 1; else I = iu;
         if constexpr (PB > 1) J = (ju / (PB - 1)) * PB + ju % (PB - 1) + 1; else J = ju;
     }
-    const int64_t g = I + (int64_t)L * (J + (int64_t)L * K);
+    const uint32_t g = I + L * (J + L * K);
     const bool bnd = I == 0 || J == 0 || K == 0 || I == L - 1 || J == L - 1 || K == L - 1;
     // a boundary row whose value the row mode replaces needs no slots; its identity value and z
     // are read before the sum, so every load of the thread is in flight at once
     const bool need = !(bnd && a.row_mode != ROW_NONE);
-    const T xv = (bnd && a.row_mode == ROW_IDENTITY) ? a.xid[g] : T(0);
-    const T zv = (a.beta != T(0)) ? a.z[g] : T(0);
+    const T xv = (bnd && a.row_mode == ROW_IDENTITY) ? ldg(a.xid, g) : T(0);
+    const T zv = (a.beta != T(0)) ? ldg(a.z, g) : T(0);
     // Along each axis the point has a lower-brick candidate (side bit 0: valid off a brick plane,
     // or on a plane above the first brick) and an upper-brick candidate (side bit 1: on a plane
     // below the last brick).  The bricks containing the point, in ascending brick order (z, then
@@ -439,7 +456,7 @@ __global__ void __launch_bounds__(256) k_fixup(SArgs<T> a, FixGeom fg) {
     }
     T r = a.alpha * acc;
     if (a.beta != T(0)) r += a.beta * zv;
-    a.y[g] = r;
+    stg(a.y, g, r);
 }
 
 // Prolongation, one thread per coarse cell: x_f[fine dof of m] += sum_j P_loc[m][j] x_c[map_j]
@@ -467,10 +484,10 @@ __global__ void __launch_bounds__(256) k_prolong(PArgs<T> a) {
     cell_vertices<B>(brick % nb, (brick / nb) % nb, brick / (nb * nb), cl, V);
     T e[NL];
 #pragma unroll
-    for (int j = 0; j < NL; ++j) e[j] = gather(a.xc, a.map[j * a.C + c], 0);
+    for (int j = 0; j < NL; ++j) e[j] = gather(a.xc, soa(a.map, j, a.C, c), 0);
     uint32_t w[NW];
 #pragma unroll
-    for (int i = 0; i < NW; ++i) w[i] = a.owner[i * a.C + c];
+    for (int i = 0; i < NW; ++i) w[i] = soa(a.owner, i, a.C, c);
     const int64_t Lf = a.Lf;
 #pragma unroll
     for (int m = 0; m < NP; ++m) {
