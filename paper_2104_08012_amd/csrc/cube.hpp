@@ -313,6 +313,38 @@ __global__ void __launch_bounds__(B * B * B * R, (cube_min_waves<P, KVAR, T>()))
                 }
                 ys[CN.cp[t][i]] = acc_i;
             }
+        } else if constexpr (P == 1) {
+            // one point (the gradient is constant): G g = C (C^T g) / |det| with C the cofactor
+            // rows, cheaper than forming G (21 instead of 33 multiply-adds)
+            constexpr int q = 0;
+            T gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                if (TB.D[q][0][i] != 0.0) gx += T(TB.D[q][0][i]) * xs[i];
+                if (TB.D[q][1][i] != 0.0) gy += T(TB.D[q][1][i]) * xs[i];
+                if (TB.D[q][2][i] != 0.0) gz += T(TB.D[q][2][i]) * xs[i];
+            }
+            T s = T(TB.w[q]);
+            if constexpr (KVAR)
+                s *= T(TB.lam[q][0]) * kt[0] + T(TB.lam[q][1]) * kt[1] + T(TB.lam[q][2]) * kt[2] +
+                     T(TB.lam[q][3]) * kt[3];
+            const T a1x = T(c1x), a1y = T(c1y), a1z = T(c1z), a2x = T(c2x), a2y = T(c2y), a2z = T(c2z),
+                    a3x = T(c3x), a3y = T(c3y), a3z = T(c3z);
+            const T vx = gx * a1x + gy * a2x + gz * a3x;
+            const T vy = gx * a1y + gy * a2y + gz * a3y;
+            const T vz = gx * a1z + gy * a2z + gz * a3z;
+            const T sc = s * T(inv);
+            const T wx = sc * (a1x * vx + a1y * vy + a1z * vz);
+            const T wy = sc * (a2x * vx + a2y * vy + a2z * vz);
+            const T wz = sc * (a3x * vx + a3y * vy + a3z * vz);
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                T acc_i = ys[CN.cp[t][i]];
+                if (TB.D[q][0][i] != 0.0) acc_i += T(TB.D[q][0][i]) * wx;
+                if (TB.D[q][1][i] != 0.0) acc_i += T(TB.D[q][1][i]) * wy;
+                if (TB.D[q][2][i] != 0.0) acc_i += T(TB.D[q][2][i]) * wz;
+                ys[CN.cp[t][i]] = acc_i;
+            }
         } else {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {

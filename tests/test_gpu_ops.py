@@ -43,7 +43,7 @@ def test_apply_fp64_parity(n, p, jit, kvar):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("n,p,jit", [(8, 2, 0.15), (16, 2, 0.15), (6, 3, 0.0), (5, 1, 0.15)])
+@pytest.mark.parametrize("n,p,jit", [(8, 2, 0.15), (16, 2, 0.15), (6, 3, 0.0), (5, 1, 0.15), (8, 1, 0.15)])
 @pytest.mark.parametrize("kvar", [False, True])
 def test_apply_fp32_parity(n, p, jit, kvar):
     banner(f"apply fp32 n={n} p={p} kvar={kvar}")
