@@ -1,0 +1,74 @@
+"""Additive vertex-star patch preconditioner (test infrastructure only).
+
+Only tests/, the smoke check and the benchmark's CPU baseline use this module;
+the library never calls it.
+
+Follows Section 2, Listing 2: the multigrid smoother's preconditioner is the
+patch preconditioner with star patches built around mesh vertices
+(construct_type star, construct_dim 0), combined additively.  Definition:
+
+* The patch of vertex v holds the degrees of freedom carried by the mesh
+  entities whose closure contains v (v itself and the edges, faces and cells
+  incident to it).  In a cell where v is local vertex i, the node with
+  barycentric multi-index m belongs to that entity set exactly when m_i > 0.
+* Dirichlet (boundary) dofs belong to no patch.
+* With R_v the restriction to the patch and A_v = R_v A R_v^T,
+      z = sum_v R_v^T A_v^{-1} R_v r      on interior dofs.
+
+Reading (listed in the design doc): the system matrix carries identity rows for the
+boundary dofs; the preconditioner passes those entries through, z_B = r_B
+(each boundary dof acts as a patch of its own with matrix 1).
+
+Pins (tests/test_oracle_patch.py): for P1 every star holds one dof, so the
+preconditioner is point Jacobi; the star sizes of an interior vertex follow
+from the link of a vertex in the cube split (14 vertices, 36 edges, 24
+triangles); with A = I every dof is counted once per vertex of the entity that
+carries it; patch matrices equal the sum of the element matrices of the cells
+around v; the preconditioner is symmetric positive definite.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import refelem
+from .mesh import Level
+
+
+def star_patches(level: Level) -> list[np.ndarray]:
+    """Interior dof ids of every vertex star, indexed by vertex id (sorted, possibly empty)."""
+    mi = np.array(refelem.node_multi_indices(level.p), dtype=np.int64)   # (nloc, 4)
+    verts, dofs = [], []
+    for i in range(4):
+        sel = mi[:, i] > 0
+        d = level.cell_dofs[:, sel]                                         # (C, ns)
+        verts.append(np.repeat(level.cell_vert[:, i], d.shape[1]))
+        dofs.append(d.ravel())
+    verts = np.concatenate(verts)
+    dofs = np.concatenate(dofs)
+    keep = ~level.boundary[dofs]
+    pairs = np.unique(np.stack([verts[keep], dofs[keep]], axis=1), axis=0)
+    out = [np.zeros(0, dtype=np.int64) for _ in range(level.n_vertices)]
+    if pairs.size:
+        starts = np.searchsorted(pairs[:, 0], np.arange(level.n_vertices + 1))
+        for v in range(level.n_vertices):
+            out[v] = pairs[starts[v]:starts[v + 1], 1]
+    return out
+
+
+def patch_inverses(A: sp.csr_matrix, patches: list[np.ndarray]) -> list[np.ndarray]:
+    """A_v^{-1} for every patch (dense), A_v the principal submatrix of A on the patch."""
+    A = sp.csr_matrix(A)
+    return [np.linalg.inv(A[idx][:, idx].toarray()) if idx.size else np.zeros((0, 0)) for idx in patches]
+
+
+def apply_patch_pc(patches: list[np.ndarray], inverses: list[np.ndarray], boundary: np.ndarray,
+                   r: np.ndarray) -> np.ndarray:
+    """z = sum_v R_v^T A_v^{-1} R_v r on interior dofs, z_B = r_B."""
+    r = np.asarray(r, dtype=np.float64)
+    z = np.zeros_like(r)
+    z[boundary] = r[boundary]
+    for idx, inv in zip(patches, inverses):
+        if idx.size:
+            z[idx] += inv @ r[idx]
+    return z
