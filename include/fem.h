@@ -245,6 +245,27 @@ fem_status fem_mg_cg_solve(const fem_mesh* mesh, const double* k_vertex, const d
 fem_status fem_adjoint_grad_k(const fem_mesh* mesh, int32_t level, const double* k_vertex,
                               const double* u, const double* lambda, double* grad, void* stream);
 
+/* Additive vertex-star patch preconditioner (Section 2, Listing 2: the smoother's preconditioner
+ * is the patch preconditioner with star patches around vertices, construct_dim 0):
+ *     z = sum_v R_v^T A_v^{-1} R_v r on interior dofs,  z_B = r_B,
+ * R_v restricting to the interior dofs whose carrying entity contains vertex v, A_v = R_v A R_v^T
+ * with A the stiffness matrix of k.  Degree 2 only (15 dofs per interior star; other degrees
+ * return FEM_ERR_UNSUPPORTED).
+ * fem_patch_bytes: size of the caller-owned patch buffer of `level` for dtype (the packed
+ * lower triangles of the 15x15 star inverses, 120 entries per vertex, plus 15 partial results per
+ * vertex), 256-byte aligned parts.
+ * fem_patch_setup: fills the buffer for k_vertex (FP64 device, n_vertices; NULL => k = 1); the
+ * inverses are computed in FP64 and stored in dtype.  FEM_ERR_WORKSPACE for a NULL or short
+ * buffer.  Stream-ordered.
+ * fem_apply_patch: z = B_patch r (r, z device, n_dofs of `level`, dtype; z overwritten, z != r).
+ * Writes the partial-result part of the buffer, so two applications that share one buffer must
+ * not run concurrently.  Stream-ordered. */
+fem_status fem_patch_bytes(const fem_mesh* mesh, int32_t level, fem_dtype dtype, size_t* bytes);
+fem_status fem_patch_setup(const fem_mesh* mesh, int32_t level, fem_dtype dtype, const double* k_vertex,
+                           void* patch, size_t bytes, void* stream);
+fem_status fem_apply_patch(const fem_mesh* mesh, int32_t level, fem_dtype dtype, void* patch, size_t bytes,
+                           const void* r, void* z, void* stream);
+
 const char* fem_status_string(fem_status s);
 const char* fem_last_error(void);
 

@@ -104,6 +104,9 @@ SIGNATURES = {
     "fem_csr_assemble": (_st, [_vp, _i32, _vp, _vp, _vp]),
     "fem_csr_spmv": (_st, [_vp, _i32, _vp, _vp, _vp, _vp]),
     "fem_csr_destroy": (None, [_vp]),
+    "fem_patch_bytes": (_st, [_vp, _i32, _i32, C.POINTER(C.c_size_t)]),
+    "fem_patch_setup": (_st, [_vp, _i32, _i32, _vp, _vp, C.c_size_t, _vp]),
+    "fem_apply_patch": (_st, [_vp, _i32, _i32, _vp, C.c_size_t, _vp, _vp, _vp]),
 }
 
 _lib = None

@@ -33,4 +33,11 @@ fem_status run_prolong(const fem_mesh& m, int fine_level, const T* xc, T* xf, hi
 
 fem_status check_launch(const char* what);
 
+// Additive vertex-star patch preconditioner, degree 2 (patch.hip).
+size_t patch_bytes(const HostLevel& H, size_t ts);
+template <typename T>
+fem_status patch_setup(const fem_mesh& m, int level, const double* k, void* buf, hipStream_t s);
+template <typename T>
+fem_status patch_apply(const fem_mesh& m, int level, void* buf, const T* r, T* z, hipStream_t s);
+
 }  // namespace fem

@@ -168,6 +168,37 @@ class Mesh:
             pass
 
 
+class PatchPreconditioner:
+    """Additive vertex-star patch preconditioner of one P2 mesh level (Section 2, Listing 2: star
+    patches around vertices): z = sum_v R_v^T A_v^{-1} R_v r on interior dofs, z_B = r_B.  The
+    star inverses and partial results live in a device buffer owned by this object."""
+
+    def __init__(self, mesh: Mesh, level: int = -1, k: torch.Tensor | None = None, dtype=torch.float64):
+        self.mesh = mesh
+        self.level = mesh._lev(level)
+        self.dtype = dtype
+        nb = C.c_size_t()
+        check(lib().fem_patch_bytes(mesh.handle, self.level, _DT[dtype], C.byref(nb)), "fem_patch_bytes")
+        self.nbytes = nb.value
+        self.buffer = torch.empty(max(256, self.nbytes), dtype=torch.uint8, device=mesh.device)
+        self.setup(k)
+
+    def setup(self, k: torch.Tensor | None = None):
+        if k is not None:
+            _need(k, self.mesh.n_vertices(self.level), torch.float64, "patch k")
+        check(lib().fem_patch_setup(self.mesh.handle, self.level, _DT[self.dtype], _ptr(k), _ptr(self.buffer),
+                                    self.nbytes, _stream(self.mesh.device)), "fem_patch_setup")
+
+    def apply(self, r: torch.Tensor, out=None) -> torch.Tensor:
+        n = self.mesh.n_dofs(self.level)
+        _need(r, n, self.dtype, "patch r")
+        z = torch.empty_like(r) if out is None else out
+        _need(z, n, self.dtype, "patch z")
+        check(lib().fem_apply_patch(self.mesh.handle, self.level, _DT[self.dtype], _ptr(self.buffer), self.nbytes,
+                                    _ptr(r), _ptr(z), _stream(r.device)), "fem_apply_patch")
+        return z
+
+
 class CsrOperator:
     """Assembled CSR matrix of A_bc(k) on one mesh level (host pattern, device values)."""
 

@@ -122,3 +122,24 @@ def test_csr_pattern_matches_oracle(n, p):
     S.sort_indices()
     assert A.n_rows == lev.n_dofs and A.nnz == S.nnz
     assert np.array_equal(rp, S.indptr) and np.array_equal(col, S.indices)
+
+
+def test_patch_buffer_bytes_and_degree_check():
+    import ctypes as C
+    from paper_2104_08012_amd import fem
+    from paper_2104_08012_amd._lib import FEM_ERR_UNSUPPORTED, FEM_OK, lib
+
+    def a256(x):
+        return (x + 255) // 256 * 256
+
+    m = fem.Mesh(6, 1, 2, upload=False)
+    nb = C.c_size_t()
+    for level, n in ((0, 6), (1, 12)):
+        NV = (n + 1) ** 3
+        for dt, s in ((0, 8), (1, 4)):
+            assert lib().fem_patch_bytes(m.handle, level, dt, C.byref(nb)) == FEM_OK
+            assert nb.value == a256(120 * NV * s) + a256(15 * NV * s)
+    for p in (1, 3):
+        mp = fem.Mesh(2, 0, p, upload=False)
+        assert lib().fem_patch_bytes(mp.handle, 0, 0, C.byref(nb)) == FEM_ERR_UNSUPPORTED
+    assert lib().fem_patch_bytes(m.handle, 2, 0, C.byref(nb)) != FEM_OK
