@@ -30,7 +30,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from . import assemble, transfer
+from . import assemble, patch, transfer
 from .mesh import Level
 
 
@@ -69,15 +69,17 @@ def cg(A, b, rtol=1e-10, max_it=10000, M=None, x0=None, flexible=False):
 
 
 def chebyshev_smooth(A, dinv, b, x, lmax, degree=2, lo=0.1, hi=1.1):
-    """`degree` Chebyshev steps for A x = b, preconditioner diag^-1, on
-    [lo*lmax, hi*lmax] (Saad Alg. 12.1).  Returns the new x."""
+    """`degree` Chebyshev steps for A x = b, preconditioner diag^-1 (dinv an array) or a
+    callable r -> B r (the star patches of Listing 2), on [lo*lmax, hi*lmax] (Saad Alg. 12.1).
+    Returns the new x."""
+    prec = dinv if callable(dinv) else (lambda v: dinv * v)
     alpha, beta = lo * lmax, hi * lmax
     theta = 0.5 * (beta + alpha)
     delta = 0.5 * (beta - alpha)
     sigma = theta / delta
     rho = 1.0 / sigma
     r = b - A @ x
-    d = dinv * r / theta
+    d = prec(r) / theta
     x = x.copy()
     for k in range(degree):
         x = x + d
@@ -85,7 +87,7 @@ def chebyshev_smooth(A, dinv, b, x, lmax, degree=2, lo=0.1, hi=1.1):
             break
         r = r - A @ d
         rho_new = 1.0 / (2.0 * sigma - rho)
-        d = rho_new * rho * d + (2.0 * rho_new / delta) * (dinv * r)
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * prec(r)
         rho = rho_new
     return x
 
@@ -114,6 +116,39 @@ def lanczos_lmax(A, dinv, steps=10, seed=5):
     return float(np.max(np.linalg.eigvalsh(Tm)))
 
 
+def pcg_lanczos_lmax(A, prec, steps=10, seed=5):
+    """Largest Ritz value of B A (B = prec, symmetric positive definite) from `steps` steps of
+    preconditioned CG on A e = v, v random: the CG coefficients alpha_j, beta_j define the
+    Lanczos tridiagonal with diagonal 1/alpha_j + beta_{j-1}/alpha_{j-1} and off-diagonal
+    sqrt(beta_j)/alpha_j (Saad, Iterative Methods for Sparse Linear Systems, 6.7.3)."""
+    r = np.random.default_rng(seed).standard_normal(A.shape[0])
+    z = prec(r)
+    p = z.copy()
+    rz = r @ z
+    alphas, betas = [], []
+    for it in range(steps):
+        q = A @ p
+        pq = p @ q
+        if not pq > 0:
+            break
+        alphas.append(rz / pq)
+        if it == steps - 1:
+            break
+        r = r - alphas[-1] * q
+        z = prec(r)
+        rz_new = r @ z
+        if not rz_new > 0:
+            break
+        betas.append(rz_new / rz)
+        rz = rz_new
+        p = z + betas[-1] * p
+    k = len(alphas)
+    diag = [1.0 / alphas[j] + (betas[j - 1] / alphas[j - 1] if j > 0 else 0.0) for j in range(k)]
+    off = [np.sqrt(betas[j]) / alphas[j] for j in range(k - 1)]
+    Tm = np.diag(diag) + np.diag(off, 1) + np.diag(off, -1)
+    return float(np.max(np.linalg.eigvalsh(Tm)))
+
+
 @dataclass
 class MGLevel:
     level: Level
@@ -127,17 +162,29 @@ class MGHierarchy:
     """Rediscretised operators, prolongations and smoother data per level."""
 
     def __init__(self, levels, k_fine_vertex=None, lmax=None, eig_steps=10,
-                 cheb_degree=2, cheb_lo=0.1, cheb_hi=1.1):
+                 cheb_degree=2, cheb_lo=0.1, cheb_hi=1.1, smoother="jacobi"):
+        """smoother: "jacobi" (diag^-1) or "patch" (Listing 2's additive vertex-star patches,
+        oracle/patch.py) as the Chebyshev preconditioner; lambda_max of B A by Lanczos on
+        D^-1 A, or by CG-Lanczos for the patches."""
         self.cheb = (cheb_degree, cheb_lo, cheb_hi)
         ks = _inject_k(levels, k_fine_vertex)
         self.levels = []
         for ell, lev in enumerate(levels):
             A = assemble.apply_bc(assemble.stiffness(lev, ks[ell]), lev.boundary)
             dinv = 1.0 / A.diagonal()
+            if smoother == "patch" and ell > 0:
+                pts = patch.star_patches(lev)
+                inv = patch.patch_inverses(A, pts)
+                dinv = (lambda v, pts=pts, inv=inv, bnd=lev.boundary: patch.apply_patch_pc(pts, inv, bnd, v))
             m = MGLevel(lev, A, dinv)
             if ell > 0:
                 m.P = transfer.prolongation(levels[ell - 1], lev)
-                m.lmax = (lmax[ell] if lmax is not None else lanczos_lmax(A, dinv, eig_steps))
+                if lmax is not None and lmax[ell] > 0:
+                    m.lmax = lmax[ell]
+                elif callable(dinv):
+                    m.lmax = pcg_lanczos_lmax(A, dinv, eig_steps)
+                else:
+                    m.lmax = lanczos_lmax(A, dinv, eig_steps)
             self.levels.append(m)
         A0 = self.levels[0].A
         if A0.shape[0] <= 4000:

@@ -126,3 +126,38 @@ def test_preconditioner_symmetric_positive_definite():
     P = np.stack([patch.apply_patch_pc(pts, inv, lv.boundary, e) for e in np.eye(N)], axis=1)
     np.testing.assert_allclose(P, P.T, rtol=0, atol=1e-12 * np.abs(P).max())
     assert np.linalg.eigvalsh(0.5 * (P + P.T)).min() > 0
+
+
+def test_cg_lanczos_reaches_largest_eigenvalue():
+    # with as many CG steps as needed the CG-Lanczos estimate is the largest eigenvalue of B A,
+    # computed here by a dense eigen-solver (patches) and checked for B = D^-1 as well
+    from oracle import solvers
+    lv = _level(2, 2, jitter=0.1)
+    k = fem_inputs.k_exp_fourier(lv.vert_xyz, seed=1)
+    A = _abc(lv, k)
+    pts = patch.star_patches(lv)
+    inv = patch.patch_inverses(A, pts)
+    N = lv.n_dofs
+    prec = lambda v: patch.apply_patch_pc(pts, inv, lv.boundary, v)
+    Bd = np.stack([prec(e) for e in np.eye(N)], axis=1)
+    lam = np.max(np.linalg.eigvals(Bd @ A.toarray()).real)
+    assert solvers.pcg_lanczos_lmax(A, prec, steps=80) == pytest.approx(lam, rel=1e-9)
+    dinv = 1.0 / A.diagonal()
+    lam_j = np.max(np.linalg.eigvals(dinv[:, None] * A.toarray()).real)
+    assert solvers.pcg_lanczos_lmax(A, lambda v: dinv * v, steps=80) == pytest.approx(lam_j, rel=1e-9)
+    # a few steps underestimate, never overestimate (Ritz values lie inside the spectrum)
+    assert solvers.pcg_lanczos_lmax(A, prec, steps=10) <= lam * (1 + 1e-12)
+
+
+def test_patch_smoothed_vcycle_contracts():
+    # two-level cycle with the patch-preconditioned Chebyshev smoother: the error propagation
+    # I - B_mg A has A-norm below 1 (a convergent multigrid iteration)
+    from oracle import solvers
+    levels = om.hierarchy(2, 1, 2, fem_inputs.jitter_offsets(2, 0.1))
+    mg = solvers.MGHierarchy(levels, None, smoother="patch")
+    A = mg.levels[-1].A.toarray()
+    N = A.shape[0]
+    E = np.eye(N) - np.stack([mg.vcycle(A[:, j]) for j in range(N)], axis=1)
+    Ls = np.linalg.cholesky(A)
+    rho = np.linalg.norm(Ls.T @ E @ np.linalg.inv(Ls.T), 2)
+    assert rho < 0.5
