@@ -167,6 +167,7 @@ void fem_csr_destroy(fem_csr* a);
 enum { FEM_PREC_FP64 = 0, FEM_PREC_MIXED = 1 };
 enum { FEM_COARSE_AUTO = 0, FEM_COARSE_DENSE = 1, FEM_COARSE_NESTED = 2 };
 enum { FEM_PC_MG = 0, FEM_PC_JACOBI = 1 };
+enum { FEM_SMOOTHER_JACOBI = 0, FEM_SMOOTHER_PATCH = 1 };
 
 typedef struct {
     double rtol;                 /* stop when ||b - A x|| / ||b|| <= rtol                       */
@@ -188,6 +189,11 @@ typedef struct {
     int32_t level_timing;        /* 1: record HIP events around every level of every V-cycle and
                                     report fem_solve_stats.level_ms (costs a few microseconds per
                                     level transition); 0 (default): level_ms stay zero            */
+    int32_t smoother;            /* preconditioner of the Chebyshev smoother on the smoothed levels:
+                                    FEM_SMOOTHER_JACOBI (default, diag(A)^-1) or FEM_SMOOTHER_PATCH
+                                    (Listing 2: additive vertex-star patches, degree 2 only, as
+                                    fem_apply_patch; lambda_max of B_patch A from CG-Lanczos).  A
+                                    nested coarse solver smooths with Jacobi.                     */
 } fem_solve_opts;
 
 typedef struct {

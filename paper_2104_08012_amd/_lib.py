@@ -33,6 +33,8 @@ FEM_COARSE_DENSE = 1
 FEM_COARSE_NESTED = 2
 FEM_PC_MG = 0
 FEM_PC_JACOBI = 1
+FEM_SMOOTHER_JACOBI = 0
+FEM_SMOOTHER_PATCH = 1
 
 
 class MeshDesc(C.Structure):
@@ -53,7 +55,8 @@ class SolveOpts(C.Structure):
                 ("coarse_method", C.c_int32), ("lambda_max_override", C.POINTER(C.c_double)),
                 ("coarse_rtol", C.c_double), ("replace_every", C.c_int32), ("flexible", C.c_int32),
                 ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int32),
-                ("preconditioner", C.c_int32), ("level_timing", C.c_int32)]
+                ("preconditioner", C.c_int32), ("level_timing", C.c_int32),
+                ("smoother", C.c_int32)]
 
 
 class SolveStats(C.Structure):

@@ -42,6 +42,7 @@ constexpr int64_t kInnerDense = 8000;  // nested solve: its dense level, the fin
 
 struct LevelWs {
     size_t x = 0, b = 0, r = 0, d = 0, dinv = 0, k64 = 0, k32 = 0, b64 = 0, x64 = 0;
+    size_t patch = 0, pz = 0, patch_bytes = 0;   // star-patch smoother: buffer, B r
     size_t fb = 0, fx = 0;   // full multigrid: FP64 right-hand side and solution (below the top)
 };
 
@@ -83,6 +84,7 @@ fem_solve_opts inner_opts(const fem_mesh& m, const fem_solve_opts& o, int top) {
     in.history = nullptr;
     in.history_cap = 0;
     in.preconditioner = FEM_PC_MG;
+    in.smoother = FEM_SMOOTHER_JACOBI;
     return in;
 }
 
@@ -114,6 +116,11 @@ fem_status make_layout(const fem_mesh& m, const fem_solve_opts& o, int top, Layo
         w.r = take(N * ts);
         w.d = take(N * ts);
         w.dinv = take(N * ts);
+        if (l > L.lo && o.smoother == FEM_SMOOTHER_PATCH) {
+            w.patch_bytes = patch_bytes(m.lev[l], ts);
+            w.patch = take(w.patch_bytes);
+            w.pz = take(N * ts);
+        }
         if (l == L.lo && L.mixed) {
             w.b64 = take(N * 8);
             w.x64 = take(N * 8);
@@ -298,6 +305,8 @@ struct fem_solver {
     fem_status coarse_solve(const double* b64, double* x64);
     fem_status setup(const double* k_top);
     fem_status lanczos(int l, double& lm);
+    fem_status lanczos_patch(int l, double& lm);
+    fem_status patch64(int l, const double* x, double* y);
     fem_status precondition(const double* r, double* z);
     fem_status cg(const double* b, double* x, int& iters, double& rel_true, bool& converged);
     fem_status fmg(const double* b, double* x, double& rel_true);
@@ -409,13 +418,24 @@ fem_status fem_solver::vcycle(int l, const T* b, T* x) {
     const double a = o.cheb_lo * lm, bb = o.cheb_hi * lm;
     const double theta = 0.5 * (bb + a), delta = 0.5 * (bb - a), sigma = theta / delta;
     if (timing) ignore(hipEventRecord(e[0], s));
+    // one Chebyshev step d = c1 d + c2 B src, x (+)= d, with B = D^-1 or the star patches
+    auto cheb = [&](double c1, double c2, const T* src, bool first, bool init) -> fem_status {
+        if (o.smoother == FEM_SMOOTHER_PATCH) {
+            T* pz = p<T>(w.pz);
+            FEM_TRY(patch_apply<T>(*m, l, p<char>(w.patch), src, pz, s));
+            cheb_launch<T>(n, c1, c2, static_cast<const T*>(nullptr), pz, d, x, first, init, s);
+        } else {
+            cheb_launch<T>(n, c1, c2, dinv, src, d, x, first, init, s);
+        }
+        return FEM_OK;
+    };
     // pre-smoothing from x = 0; r tracks b - A x
     double rho = 1.0 / sigma;
-    cheb_launch<T>(n, 0.0, 1.0 / theta, dinv, b, d, x, true, true, s);
+    FEM_TRY(cheb(0.0, 1.0 / theta, b, true, true));
     FEM_TRY(applyT<T>(l, d, -1.0, b, 1.0, r));
     for (int k = 1; k < deg; ++k) {
         const double rn = 1.0 / (2.0 * sigma - rho);
-        cheb_launch<T>(n, rn * rho, 2.0 * rn / delta, dinv, r, d, x, false, false, s);
+        FEM_TRY(cheb(rn * rho, 2.0 * rn / delta, r, false, false));
         rho = rn;
         FEM_TRY(applyT<T>(l, d, -1.0, r, 1.0, r));
     }
@@ -436,11 +456,11 @@ fem_status fem_solver::vcycle(int l, const T* b, T* x) {
     // post-smoothing from x
     FEM_TRY(applyT<T>(l, x, -1.0, b, 1.0, r));
     rho = 1.0 / sigma;
-    cheb_launch<T>(n, 0.0, 1.0 / theta, dinv, r, d, x, true, false, s);
+    FEM_TRY(cheb(0.0, 1.0 / theta, r, true, false));
     for (int k = 1; k < deg; ++k) {
         FEM_TRY(applyT<T>(l, d, -1.0, r, 1.0, r));
         const double rn = 1.0 / (2.0 * sigma - rho);
-        cheb_launch<T>(n, rn * rho, 2.0 * rn / delta, dinv, r, d, x, false, false, s);
+        FEM_TRY(cheb(rn * rho, 2.0 * rn / delta, r, false, false));
         rho = rn;
     }
     if (timing) ignore(hipEventRecord(e[3], s));
@@ -502,6 +522,71 @@ fem_status fem_solver::lanczos(int l, double& lm) {
     return FEM_OK;
 }
 
+// y = B_patch x on level l in FP64 (the FP32-stored patches of a mixed solver through the
+// level's FP32 vectors).
+fem_status fem_solver::patch64(int l, const double* x, double* y) {
+    const LevelWs& w = L.lev[l];
+    if (!L.mixed) return patch_apply<double>(*m, l, p<char>(w.patch), x, y, s);
+    const int64_t n = m->lev[l].N;
+    cast_launch<double, float>(n, x, p<float>(w.r), s);
+    FEM_TRY(patch_apply<float>(*m, l, p<char>(w.patch), p<float>(w.r), p<float>(w.pz), s));
+    cast_launch<float, double>(n, p<float>(w.pz), y, s);
+    return FEM_OK;
+}
+
+// Largest eigenvalue estimate of B_patch A from o.eig_iters steps of preconditioned CG on A e = v
+// (v the seeded random start): the CG coefficients alpha_j, beta_j give the Lanczos tridiagonal
+// of B A with diagonal 1/alpha_j + beta_{j-1}/alpha_{j-1} and off-diagonal sqrt(beta_j)/alpha_j
+// (the CG-Lanczos relation; Saad, Iterative Methods for Sparse Linear Systems, 6.7.3).
+fem_status fem_solver::lanczos_patch(int l, double& lm) {
+    const int64_t n = m->lev[l].N;
+    double* r = p<double>(L.cg_r);
+    double* z = p<double>(L.cg_z);
+    double* pv = p<double>(L.cg_p);
+    double* q = p<double>(L.cg_q);
+    random_launch(n, m->lev[l].L, 0x5eed0005ull + (uint64_t)l, r, s);
+    FEM_TRY(patch64(l, r, z));
+    cast_launch<double, double>(n, z, pv, s);
+    double rz = 0.0;
+    FEM_TRY(dot(n, r, z, rz));
+    if (!(rz > 0)) {
+        set_error("CG-Lanczos start vector has zero preconditioned norm");
+        return FEM_ERR_BREAKDOWN;
+    }
+    std::vector<double> al, be;
+    const int steps = std::max(2, o.eig_iters);
+    for (int it = 0; it < steps; ++it) {
+        FEM_TRY(apply64(l, pv, 1.0, nullptr, 0.0, q));               // q = A p
+        double pq = 0.0;
+        FEM_TRY(dot(n, pv, q, pq));
+        if (!(pq > 0)) break;
+        al.push_back(rz / pq);
+        if (it == steps - 1) break;
+        axpby_launch<double>(n, -al.back(), q, 1.0, r, s);           // r -= alpha q
+        FEM_TRY(patch64(l, r, z));                                   // z = B r
+        double rz2 = 0.0;
+        FEM_TRY(dot(n, r, z, rz2));
+        if (!(rz2 > 0)) break;
+        be.push_back(rz2 / rz);
+        rz = rz2;
+        axpby_launch<double>(n, 1.0, z, be.back(), pv, s);           // p = z + beta p
+    }
+    const size_t k = al.size();
+    if (k == 0) {
+        set_error("CG-Lanczos estimate of lambda_max failed");
+        return FEM_ERR_BREAKDOWN;
+    }
+    std::vector<double> dg(k), off(k - 1);
+    for (size_t j = 0; j < k; ++j) dg[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+    for (size_t j = 0; j + 1 < k; ++j) off[j] = std::sqrt(be[j]) / al[j];
+    lm = tridiag_max_eig(dg, off);
+    if (!std::isfinite(lm) || lm <= 0) {
+        set_error("CG-Lanczos estimate of lambda_max failed");
+        return FEM_ERR_BREAKDOWN;
+    }
+    return FEM_OK;
+}
+
 // k_top: the coefficient on the vertex lattice of this solver's finest level (NULL for k = 1).
 fem_status fem_solver::setup(const double* k_top) {
     kvar = k_top != nullptr;
@@ -538,9 +623,17 @@ fem_status fem_solver::setup(const double* k_top) {
                 recip_launch<double>(n, dg, p<double>(L.lev[l].dinv), s);
             }
         }
+        // star-patch smoother: the inverses of the vertex stars per smoothed level
+        if (o.smoother == FEM_SMOOTHER_PATCH)
+            for (int l = L.lo + 1; l <= L.hi; ++l) {
+                const double* kl = kvar ? p<double>(L.lev[l].k64) : nullptr;
+                if (L.mixed) FEM_TRY(patch_setup<float>(*m, l, kl, p<char>(L.lev[l].patch), s));
+                else FEM_TRY(patch_setup<double>(*m, l, kl, p<char>(L.lev[l].patch), s));
+            }
         // lambda_max per smoothed level
         for (int l = L.lo + 1; l <= L.hi; ++l) {
             if (o.lambda_max_override && o.lambda_max_override[l] > 0) lmax[l] = o.lambda_max_override[l];
+            else if (o.smoother == FEM_SMOOTHER_PATCH) FEM_TRY(lanczos_patch(l, lmax[l]));
             else FEM_TRY(lanczos(l, lmax[l]));
         }
         if (inner) {
@@ -821,6 +914,7 @@ void fem_solve_opts_default(fem_solve_opts* o) {
     o->history_cap = 0;
     o->preconditioner = FEM_PC_MG;
     o->level_timing = 0;
+    o->smoother = FEM_SMOOTHER_JACOBI;
 }
 
 static fem_status check_opts(const fem_mesh* m, const fem_solve_opts* o) {
@@ -832,9 +926,14 @@ static fem_status check_opts(const fem_mesh* m, const fem_solve_opts* o) {
         !(o->cheb_lo > 0) || (o->precision != FEM_PREC_FP64 && o->precision != FEM_PREC_MIXED) ||
         o->n_levels_used < 0 || o->eig_iters < 0 || o->eig_iters > 64 || !(o->coarse_rtol > 0) ||
         o->coarse_method < FEM_COARSE_AUTO || o->coarse_method > FEM_COARSE_NESTED ||
-        (o->preconditioner != FEM_PC_MG && o->preconditioner != FEM_PC_JACOBI)) {
+        (o->preconditioner != FEM_PC_MG && o->preconditioner != FEM_PC_JACOBI) ||
+        (o->smoother != FEM_SMOOTHER_JACOBI && o->smoother != FEM_SMOOTHER_PATCH)) {
         set_error("solver: invalid options");
         return FEM_ERR_INVALID_ARG;
+    }
+    if (o->smoother == FEM_SMOOTHER_PATCH && m->p != 2) {
+        set_error("solver: the star-patch smoother is built for degree 2 only");
+        return FEM_ERR_UNSUPPORTED;
     }
     return FEM_OK;
 }

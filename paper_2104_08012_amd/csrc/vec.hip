@@ -108,13 +108,14 @@ __global__ void k_cg_direction_dev(int64_t n, const double* __restrict__ sc, con
     if (i < n) p[i] = z[i] + sc[CG_BETA] * p[i];
 }
 
-// Chebyshev step: d = c1 d + c2 dinv r ; x = (init ? d : x + d)
+// Chebyshev step: d = c1 d + c2 dinv r ; x = (init ? d : x + d)   (dinv NULL: r is already
+// preconditioned)
 template <typename T>
 __global__ void k_cheb(int64_t n, T c1, T c2, const T* __restrict__ dinv, const T* __restrict__ r,
                        T* __restrict__ d, T* __restrict__ x, int init) {
     const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
     if (i < n) {
-        const T dn = c1 * d[i] + c2 * dinv[i] * r[i];
+        const T dn = c1 * d[i] + (dinv ? c2 * dinv[i] * r[i] : c2 * r[i]);
         d[i] = dn;
         x[i] = init ? dn : x[i] + dn;
     }
@@ -126,7 +127,7 @@ __global__ void k_cheb0(int64_t n, T c2, const T* __restrict__ dinv, const T* __
                         T* __restrict__ d, T* __restrict__ x, int init) {
     const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
     if (i < n) {
-        const T dn = c2 * dinv[i] * r[i];
+        const T dn = dinv ? c2 * dinv[i] * r[i] : c2 * r[i];
         d[i] = dn;
         x[i] = init ? dn : x[i] + dn;
     }

@@ -268,6 +268,7 @@ class SolveOptions:
     history_cap: int = 1000
     preconditioner: str = "mg"     # "mg" or "jacobi"
     level_timing: bool = False     # per-level V-cycle times in SolveResult.level_ms (adds events)
+    smoother: str = "jacobi"       # "jacobi" or "patch" (vertex-star patches, P2)
 
     def to_c(self):
         o = L.SolveOpts()
@@ -292,6 +293,7 @@ class SolveOptions:
         o.history = C.cast(hist, C.POINTER(C.c_double))
         o.history_cap = self.history_cap
         o.preconditioner = L.FEM_PC_JACOBI if self.preconditioner == "jacobi" else L.FEM_PC_MG
+        o.smoother = {"jacobi": L.FEM_SMOOTHER_JACOBI, "patch": L.FEM_SMOOTHER_PATCH}[self.smoother]
         o.level_timing = 1 if self.level_timing else 0
         keep.append(hist)
         return o, keep, hist

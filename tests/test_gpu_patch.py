@@ -106,3 +106,74 @@ def test_patch_argument_errors():
         pc.apply(r, out=r)
     with pytest.raises(ValueError):
         pc.apply(r.float())
+
+
+def _rhs(lev):
+    from oracle import assemble
+    b = assemble.mass(lev) @ fem_inputs.sin3_f(lev.dof_xyz())
+    b[lev.boundary] = 0
+    return b
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n0,r,jit,kvar", [(2, 2, 0.1, True), (3, 1, 0.0, True), (2, 1, 0.0, False)])
+def test_patch_smoothed_vcycle_matches_oracle(n0, r, jit, kvar):
+    # one FP64 V-cycle with the patch-preconditioned Chebyshev smoother against the oracle's, same
+    # lambda_max per level: 1e-11 (the 15x15 star inverses carry ~2e-12 relative errors)
+    banner(f"patch vcycle n0={n0} r={r} kvar={kvar}")
+    from oracle import solvers
+    from paper_2104_08012_amd import fem
+    from tests.gpu_util import rel
+    mesh, levels = make_pair(n0, r, 2, jit)
+    k = fem_inputs.k_exp_fourier(levels[-1].vert_xyz) if kvar else None
+    omg = solvers.MGHierarchy(levels, k, smoother="patch")
+    lm = [0.0] + [L.lmax for L in omg.levels[1:]]
+    S = fem.Solver(mesh, fem.SolveOptions(lambda_max=lm, smoother="patch")).setup(_t(k) if kvar else None)
+    x = fem_inputs.uniform_vector(levels[-1].n_dofs, 0)
+    x[levels[-1].boundary] = 0
+    z = S.vcycle(_t(x))
+    torch.cuda.synchronize()
+    assert rel(z.cpu().numpy(), omg.vcycle(x)) <= 1e-11
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_patch_smoothed_solution_parity(prec):
+    banner(f"patch-smoothed solve {prec}")
+    from oracle import assemble, solvers
+    from paper_2104_08012_amd import fem
+    from tests.gpu_util import rel
+    mesh, levels = make_pair(2, 2, 2, 0.1)
+    lev = levels[-1]
+    k = fem_inputs.k_exp_fourier(lev.vert_xyz)
+    A = assemble.apply_bc(assemble.stiffness(lev, k), lev.boundary)
+    b = _rhs(lev)
+    u_ref = solvers.direct_solve(A, b, rtol=1e-14)
+    S = fem.Solver(mesh, fem.SolveOptions(rtol=1e-10, precision=prec, smoother="patch")).setup(_t(k))
+    u, res = S.solve(_t(b))
+    Sj = fem.Solver(mesh, fem.SolveOptions(rtol=1e-10, precision=prec)).setup(_t(k))
+    _, resj = Sj.solve(_t(b))
+    torch.cuda.synchronize()
+    print(f"iterations patch {res.iterations} jacobi {resj.iterations}", flush=True)
+    assert res.rel_residual_true <= 1e-10
+    assert rel(u.cpu().numpy(), u_ref) <= 1e-8
+    assert res.iterations <= resj.iterations
+    # the CG-Lanczos estimate on the finest level lies inside the spectrum of B A and close to its top
+    if prec == "fp64":
+        from oracle import patch as op
+        pts = op.star_patches(lev)
+        inv = op.patch_inverses(A, pts)
+        Bd = np.stack([op.apply_patch_pc(pts, inv, lev.boundary, e) for e in np.eye(lev.n_dofs)], axis=1)
+        lam = np.max(np.linalg.eigvals(Bd @ A.toarray()).real)
+        est = res.lambda_max[len(levels) - 1]
+        assert 0.9 * lam <= est <= lam * (1 + 1e-9)
+
+
+@pytest.mark.gpu
+def test_patch_smoother_needs_degree_2():
+    banner("patch smoother degree check")
+    from paper_2104_08012_amd import fem
+    from paper_2104_08012_amd._lib import FemError
+    mesh = fem.Mesh(2, 1, 1, device="cuda:0")
+    with pytest.raises(FemError):
+        fem.Solver(mesh, fem.SolveOptions(smoother="patch"))
