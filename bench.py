@@ -18,6 +18,9 @@ One step = one pass of the hot path:
      mixed.
 Setup (mesh upload, Jacobi diagonals, Lanczos estimates, coarse inverse) is outside the timed
 region and reported separately.
+After the timed steps (P2 workloads, reported under "patch_smoother"): the additive vertex-star
+patch preconditioner of Listing 2's smoother applied on the finest level in FP64 and FP32 (cold,
+HIP events), and the MG-CG solves with the patch-preconditioned Chebyshev smoother.
 
 value = operator-action GDoF/s of step 1: n_dofs / (mean duration of the action, from HIP events
 recorded on the stream the action's kernels run on, over the timed steps).  The action is two
@@ -333,6 +336,58 @@ def run_solve(args, name, w):
     s64.set_level_timing(False)
     smx.set_level_timing(False)
 
+    # star-patch smoother (Listing 2's patch preconditioner inside the Chebyshev smoother, P2):
+    # the patch application on the finest level (cold cache, HIP events on the stream it runs on)
+    # and the patch-smoothed MG-CG solves, measured after the timed steps
+    patch_pc = None
+    if p == 2:
+        prec_rec = {}
+        pc64 = fem.PatchPreconditioner(mesh, -1, k64, dtype=torch.float64)
+        pc32 = fem.PatchPreconditioner(mesh, -1, k64, dtype=torch.float32)
+        for it in range(6):
+            r_ = prec_rec if it > 0 else None
+            flush.sum()
+            e = tm.start()
+            pc64.apply(x64, out=y64)
+            tm.stop(e, "patch64", r_)
+            flush.sum()
+            e = tm.start()
+            pc32.apply(x32, out=y32)
+            tm.stop(e, "patch32", r_)
+            tm.collect()
+        del pc64, pc32
+        op64 = fem.SolveOptions(rtol=w["rtol"], precision="fp64", n_levels_used=used, coarse_method=cm,
+                                smoother="patch")
+        opmx = fem.SolveOptions(rtol=w["rtol"], precision="mixed", n_levels_used=used, coarse_method=cm,
+                                smoother="patch")
+        sp64 = fem.Solver(mesh, op64).setup(k64)
+        spmx = fem.Solver(mesh, opmx).setup(k64)
+        tp64, tpmx = [], []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            up64, rp64 = sp64.solve(b)
+            t1 = time.perf_counter()
+            upmx, rpmx = spmx.solve(b)
+            t2 = time.perf_counter()
+            tp64.append(t1 - t0)
+            tpmx.append(t2 - t1)
+        a64, a32 = mean(prec_rec["patch64"]), mean(prec_rec["patch32"])
+        alg64, alg32 = 120 * NV * 8 + 2 * N * 8, 120 * NV * 4 + 2 * N * 4
+        patch_pc = {
+            "apply_us_fp64_cold": round(a64 * 1e6, 2), "apply_us_fp32_cold": round(a32 * 1e6, 2),
+            "alg_bytes_fp64": alg64, "alg_bytes_fp32": alg32,
+            "hbm_frac_fp64": round(alg64 / a64 / 8.0e12, 3), "hbm_frac_fp32": round(alg32 / a32 / 8.0e12, 3),
+            "bytes_note": "packed 15x15 star inverses (120 entries per vertex) + r in + z out; the 15 partial "
+                          "results per vertex (written and read back) are not counted",
+            "mgcg_fp64_ms": round(mean(tp64) * 1e3, 3), "mgcg_mixed_ms": round(mean(tpmx) * 1e3, 3),
+            "mgcg_fp64_iterations": rp64.iterations, "mgcg_mixed_iterations": rpmx.iterations,
+            "mgcg_fp64_rel_residual": rp64.rel_residual_true, "mgcg_mixed_rel_residual": rpmx.rel_residual_true,
+            "vs_jacobi_solution_rel_diff": (torch.linalg.norm(up64 - last["u64"]) / torch.linalg.norm(last["u64"])).item(),
+            "lambda_max": [round(v, 6) for v in rp64.lambda_max[:mesh.n_levels]],
+        }
+        del sp64, spmx
+
     ta64, ta32 = mean(rec["apply64"]), mean(rec["apply32"])
     key = f"P{p}{'k' if kvar else ''}_n{info['n']}"
     out = header(args, name, {
@@ -379,6 +434,8 @@ def run_solve(args, name, w):
         nu = torch.linalg.norm(u_exact)
         out["discretisation_rel_l2_nodal"] = (torch.linalg.norm(u64 - u_exact) / nu).item()
         out["fmg_discretisation_rel_l2_nodal"] = (torch.linalg.norm(last["uf64"] - u_exact) / nu).item()
+    if patch_pc is not None:
+        out["patch_smoother"] = patch_pc
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(info["n"], p, kvar)
     return out
@@ -551,7 +608,7 @@ def summarize_trace(d):
         agg[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     total = sum(sum(v) for v in agg.values())
     print(f"{'calls':>6} {'mean_us':>9} {'median_us':>9} {'min_us':>8} {'share':>6}  kernel [grid threads, workgroup]")
-    for (nm, g, w), v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:30]:
+    for (nm, g, w), v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:50]:
         v.sort()
         print(f"{len(v):6d} {sum(v) / len(v):9.2f} {v[len(v) // 2]:9.2f} {v[0]:8.2f} {100 * sum(v) / total:5.1f}%  "
               f"{nm} [{g}, {w}]")
@@ -583,7 +640,8 @@ def summarize_counters(fdir, wdir, workload, write_traffic):
     print(f"{'fetch_MB':>9} {'write_MB':>9}  kernel [grid threads]")
     acts = {}
     for (nm, full, g), c in sorted(res.items(), key=lambda kv: -kv[1].get("FETCH_SIZE", 0.0)):
-        if not any(k in nm for k in ("k_cube_apply", "k_fixup", "k_brick", "copyBuffer", "k_prolong", "k_sym")):
+        if not any(k in nm for k in ("k_cube_apply", "k_fixup", "k_brick", "copyBuffer", "k_prolong", "k_sym",
+                                     "k_patch")):
             continue
         f, w = c.get("FETCH_SIZE", 0.0), c.get("WRITE_SIZE", 0.0)
         print(f"{f / 1e6:9.2f} {w / 1e6:9.2f}  {nm} [{g}]")
