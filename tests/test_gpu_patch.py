@@ -177,3 +177,28 @@ def test_patch_smoother_needs_degree_2():
     mesh = fem.Mesh(2, 1, 1, device="cuda:0")
     with pytest.raises(FemError):
         fem.Solver(mesh, fem.SolveOptions(smoother="patch"))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_patch_smoother_with_nested_coarse_solve(prec):
+    # outer cycle on the two finest levels with patch smoothing; its coarse level is solved by the
+    # nested FP64 MG-PCG (Jacobi-smoothed) over the levels below
+    banner(f"patch smoother + nested coarse {prec}")
+    from oracle import assemble, solvers
+    from paper_2104_08012_amd import fem
+    from tests.gpu_util import rel
+    mesh, levels = make_pair(2, 2, 2, 0.1)
+    lev = levels[-1]
+    k = fem_inputs.k_exp_fourier(lev.vert_xyz)
+    A = assemble.apply_bc(assemble.stiffness(lev, k), lev.boundary)
+    b = _rhs(lev)
+    u_ref = solvers.direct_solve(A, b, rtol=1e-14)
+    opts = fem.SolveOptions(rtol=1e-10, precision=prec, smoother="patch", n_levels_used=2,
+                            coarse_method="nested")
+    S = fem.Solver(mesh, opts).setup(_t(k))
+    u, res = S.solve(_t(b))
+    torch.cuda.synchronize()
+    assert res.rel_residual_true <= 1e-10
+    assert rel(u.cpu().numpy(), u_ref) <= 1e-8
+    assert res.coarse_iterations > 0

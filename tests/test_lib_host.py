@@ -143,3 +143,29 @@ def test_patch_buffer_bytes_and_degree_check():
         mp = fem.Mesh(2, 0, p, upload=False)
         assert lib().fem_patch_bytes(mp.handle, 0, 0, C.byref(nb)) == FEM_ERR_UNSUPPORTED
     assert lib().fem_patch_bytes(m.handle, 2, 0, C.byref(nb)) != FEM_OK
+
+
+def test_solver_workspace_with_patch_smoother():
+    """The star-patch smoother adds, per smoothed level, the patch buffer (120 + 15 entries per
+    vertex) and one level vector; degrees other than 2 are refused."""
+    import ctypes as C
+    from paper_2104_08012_amd import fem
+    from paper_2104_08012_amd import _lib as L
+
+    def ws(m, **kw):
+        o, keep, _ = fem.SolveOptions(**kw).to_c()
+        nb = C.c_size_t()
+        st = L.lib().fem_solve_workspace_bytes(m.handle, C.byref(o), C.byref(nb))
+        return st, nb.value
+
+    m = fem.Mesh(4, 2, 2, upload=False)
+    for prec, s in (("fp64", 8), ("mixed", 4)):
+        st_j, b_j = ws(m, precision=prec)
+        st_p, b_p = ws(m, precision=prec, smoother="patch")
+        assert st_j == 0 and st_p == 0
+        extra = sum(135 * m.levels[l]["n_vertices"] * s + m.levels[l]["n_dofs"] * s for l in (1, 2))
+        assert extra <= b_p - b_j <= extra + 6 * 256
+    for p in (1, 3):
+        mp = fem.Mesh(2, 1, p, upload=False)
+        st, _ = ws(mp, smoother="patch")
+        assert st == L.FEM_ERR_UNSUPPORTED
