@@ -3,7 +3,7 @@
 Follows Section 2, Listing 1 of the paper: UnitCubeMesh(N, N, N) and
 MeshHierarchy(mesh, 2), i.e. a tetrahedral unit cube refined uniformly.
 
-Readings (listed in DESIGN.md):
+Readings of the paper taken here:
 * Each of the n^3 cubes is split into the 6 tetrahedra that share its main
   diagonal (Kuhn / Freudenthal split).  For the axis permutation s the cell's
   vertices follow the monotone lattice path

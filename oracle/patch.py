@@ -15,7 +15,7 @@ patch preconditioner with star patches built around mesh vertices
 * With R_v the restriction to the patch and A_v = R_v A R_v^T,
       z = sum_v R_v^T A_v^{-1} R_v r      on interior dofs.
 
-Reading (listed in the design doc): the system matrix carries identity rows for the
+Reading of the paper taken here: the system matrix carries identity rows for the
 boundary dofs; the preconditioner passes those entries through, z_B = r_B
 (each boundary dof acts as a patch of its own with matrix 1).
 

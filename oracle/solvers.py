@@ -4,7 +4,7 @@ Follows Section 4 of the paper (geometric multigrid: smooth, restrict the
 residual, solve the coarsest problem directly, prolong the correction, smooth
 again; Listing 2: 2 Chebyshev iterations per level, direct coarse solve).
 
-Readings (listed in DESIGN.md):
+Readings of the paper taken here:
 * The multigrid cycle is a V(2,2) cycle used as the preconditioner of CG
   (the configuration this library targets); Listing 2's full-multigrid cycle
   with a preonly outer solver is MGHierarchy.fmg (one F-cycle: restricted
