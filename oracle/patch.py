@@ -72,3 +72,42 @@ def apply_patch_pc(patches: list[np.ndarray], inverses: list[np.ndarray], bounda
         if idx.size:
             z[idx] += inv @ r[idx]
     return z
+
+
+def patch_pc_at(level: Level, k_vertex, r: np.ndarray, dofs) -> np.ndarray:
+    """z = B_patch r at the given dofs only, for meshes too large for the global construction:
+    every star containing a dof is assembled from the element matrices of the cells around its
+    vertex (the cells coupling two dofs of a star all contain its vertex, so this is the
+    principal submatrix of the global operator on the star) and solved densely."""
+    from . import assemble
+    mi = np.array(refelem.node_multi_indices(level.p), dtype=np.int64)
+    r = np.asarray(r, dtype=np.float64)
+    out = np.empty(len(dofs))
+    for j, g in enumerate(dofs):
+        g = int(g)
+        if level.boundary[g]:
+            out[j] = r[g]
+            continue
+        c, a = (int(t[0]) for t in np.nonzero(level.cell_dofs == g))
+        total = 0.0
+        for v in level.cell_vert[c, mi[a] > 0]:
+            cells = np.nonzero((level.cell_vert == v).any(axis=1))[0]
+            Ae = assemble.element_matrices(level, k_vertex, cells)
+            iv = np.argmax(level.cell_vert[cells] == v, axis=1)
+            rows, cols, vals = [], [], []
+            for q, cc in enumerate(cells):
+                loc = np.nonzero(mi[:, iv[q]] > 0)[0]
+                d = level.cell_dofs[cc, loc]
+                rows.append(np.repeat(d, loc.size))
+                cols.append(np.tile(d, loc.size))
+                vals.append(Ae[q][np.ix_(loc, loc)].ravel())
+            rows, cols, vals = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+            keep = ~level.boundary[rows] & ~level.boundary[cols]
+            star = np.unique(rows[keep])
+            pos = {int(d): i for i, d in enumerate(star)}
+            Av = np.zeros((star.size, star.size))
+            np.add.at(Av, (np.array([pos[int(d)] for d in rows[keep]]),
+                           np.array([pos[int(d)] for d in cols[keep]])), vals[keep])
+            total += np.linalg.solve(Av, r[star])[pos[g]]
+        out[j] = total
+    return out

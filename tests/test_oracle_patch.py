@@ -161,3 +161,16 @@ def test_patch_smoothed_vcycle_contracts():
     Ls = np.linalg.cholesky(A)
     rho = np.linalg.norm(Ls.T @ E @ np.linalg.inv(Ls.T), 2)
     assert rho < 0.5
+
+
+@pytest.mark.parametrize("n,p,jit", [(3, 2, 0.15), (2, 3, 0.1)])
+def test_pointwise_patch_values_match_global_definition(n, p, jit):
+    # the one-dof-at-a-time evaluation used at large sizes equals the global construction
+    lv = _level(n, p, jitter=jit)
+    k = fem_inputs.k_exp_fourier(lv.vert_xyz, seed=1)
+    A = _abc(lv, k)
+    pts = patch.star_patches(lv)
+    r = fem_inputs.uniform_vector(lv.n_dofs, seed=0)
+    z = patch.apply_patch_pc(pts, patch.patch_inverses(A, pts), lv.boundary, r)
+    sample = np.arange(lv.n_dofs)
+    np.testing.assert_allclose(patch.patch_pc_at(lv, k, r, sample), z, rtol=1e-12, atol=1e-14 * np.abs(z).max())
