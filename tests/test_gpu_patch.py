@@ -20,6 +20,7 @@ import pytest
 
 import fem_inputs
 from oracle import patch
+from oracle import patch as op
 from tests.gpu_util import banner, make_pair, oracle_A
 
 torch = pytest.importorskip("torch")
@@ -202,3 +203,33 @@ def test_patch_smoother_with_nested_coarse_solve(prec):
     assert res.rel_residual_true <= 1e-10
     assert rel(u.cpu().numpy(), u_ref) <= 1e-8
     assert res.coarse_iterations > 0
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("kvar", [False, True])
+def test_patch_sampled_parity_at_workload_size(kvar):
+    # the 64^3 P2 finest level in the launch configuration the benchmark times, against the
+    # oracle's one-dof-at-a-time evaluation on sampled dofs: random interior dofs, dofs next to
+    # the boundary and at the corners, and boundary dofs
+    banner(f"patch sampled parity 64^3 kvar={kvar}")
+    from oracle import mesh as om
+    from paper_2104_08012_amd import fem
+    mesh = fem.Mesh(16, 2, 2, device="cuda:0")
+    lev = om.hierarchy(16, 2, 2)[-1]
+    L = 129
+    k = fem_inputs.k_exp_fourier(lev.vert_xyz) if kvar else None
+    r = fem_inputs.uniform_vector(lev.n_dofs, seed=0)
+    rng = np.random.default_rng(11)
+    pts = [(1, 1, 1), (127, 127, 127), (1, 2, 2), (2, 1, 127), (64, 64, 64), (63, 65, 64), (1, 64, 127),
+           (0, 5, 7), (128, 64, 3)]
+    sample = [i + L * (j + L * kk) for i, j, kk in pts]
+    sample += rng.integers(0, lev.n_dofs, 40).tolist()
+    face = rng.integers(1, 128, (20, 3))
+    face[:, 0] = rng.choice([1, 2, 126, 127], 20)
+    sample += [int(i + L * (j + L * kk)) for i, j, kk in face]
+    sample = np.array(sample)
+    zr = op.patch_pc_at(lev, k, r, sample)
+    for dtype, tol in ((torch.float64, 1e-11), (torch.float32, 2e-5)):
+        pc = fem.PatchPreconditioner(mesh, -1, _t(k) if kvar else None, dtype=dtype)
+        z = pc.apply(_t(r, dtype)).double().cpu().numpy()[sample]
+        assert np.abs(z - zr).max() <= tol * np.abs(zr).max()
