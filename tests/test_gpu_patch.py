@@ -233,3 +233,25 @@ def test_patch_sampled_parity_at_workload_size(kvar):
         pc = fem.PatchPreconditioner(mesh, -1, _t(k) if kvar else None, dtype=dtype)
         z = pc.apply(_t(r, dtype)).double().cpu().numpy()[sample]
         assert np.abs(z - zr).max() <= tol * np.abs(zr).max()
+
+
+@pytest.mark.gpu
+def test_patch_smoothed_fmg_matches_oracle():
+    # one full-multigrid cycle (Listing 2's solver configuration) with the patch-preconditioned
+    # smoother against the oracle's, same lambda_max: FP64 1e-10, mixed within FP32 rounding
+    banner("patch-smoothed fmg")
+    from oracle import solvers
+    from paper_2104_08012_amd import fem
+    from tests.gpu_util import rel
+    mesh, levels = make_pair(2, 2, 2, 0.1)
+    lev = levels[-1]
+    k = fem_inputs.k_exp_fourier(lev.vert_xyz)
+    omg = solvers.MGHierarchy(levels, k, smoother="patch")
+    lm = [0.0] + [L.lmax for L in omg.levels[1:]]
+    b = _rhs(lev)
+    x_ref = omg.fmg(b)
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-5)):
+        S = fem.Solver(mesh, fem.SolveOptions(lambda_max=lm, precision=prec, smoother="patch")).setup(_t(k))
+        x, _ = S.fmg(_t(b))
+        torch.cuda.synchronize()
+        assert rel(x.cpu().numpy(), x_ref) <= tol
