@@ -14,7 +14,9 @@ with G = |det J| J^-1 J^-T.  Dirichlet conditions on all six faces
 
 Parity: the assembled operator is pinned by closed forms (P1 on the uniform
 split is h times the 7-point finite-difference Laplacian), exact
-reproduction of linear/quadratic/cubic fields and A.1 = 0, in
+reproduction of linear/quadratic/cubic fields and A.1 = 0, and, for the P1
+coefficient, exact reproduction of -div(ell grad q) with ell linear (which
+fails if the vertex weights of T^{v,ab} are permuted), in
 tests/test_oracle_assembly.py.
 """
 from __future__ import annotations

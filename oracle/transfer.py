@@ -11,7 +11,7 @@ are read off the sorted fractions, and the coarse basis functions of that
 cell are evaluated there.
 
 Parity: reproduction of coarse polynomials of degree <= p and the Galerkin
-identity P^T A_f P = A_c are pinned in tests/test_oracle_mg.py.
+identity P^T A_f P = A_c are pinned in tests/test_oracle_solvers.py.
 """
 from __future__ import annotations
 

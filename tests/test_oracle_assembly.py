@@ -6,6 +6,10 @@
 * Exact reproduction: for ell linear, (A ell)_i = 0 on interior rows; for q
   quadratic (p >= 2), (A q)_i = -lap(q) int phi_i; for c cubic (p = 3),
   (A c)_i = (M (-lap c))_i, since -lap(c) is linear and in the space.
+* Exact reproduction with a coefficient: for k = ell linear (its P1
+  interpolant is exact) and q of degree p, the interior rows of A(k) q equal
+  (M f)_i with f = -grad(ell).grad(q) - ell lap(q) of degree p - 1.  This pins
+  the P1-coefficient tensor T^{v,ab}: permuting its vertex weights fails it.
 * Structure: nnz counts from the sparsity pattern.
 """
 import numpy as np
@@ -150,3 +154,57 @@ def test_kvar_constant_equals_scaled():
     A1 = assemble.stiffness(lev, k)
     A0 = assemble.stiffness(lev)
     assert abs(A1 - 2.5 * A0).max() < 1e-14
+
+
+def _var_k_exactness_residual(p, jit, T_override=None, monkeypatch=None):
+    """Interior rows of A(k) q - M f for k = ell (linear, so its P1 interpolant is exact), q a
+    polynomial of degree p and f = -div(ell grad q) = -grad(ell).grad(q) - ell lap(q), which has
+    degree p - 1 and so lies in the space: a(q, phi_i) = int f phi_i = (M f)_i exactly for every
+    interior test function (weak form of Section 2 eq. (4) with a coefficient)."""
+    from oracle import refelem
+    if T_override is not None:
+        monkeypatch.setattr(refelem, "T", T_override)
+    n = 3
+    lev = om.single_level(n, p, fem_inputs.jitter_offsets(n, 0.15) if jit else None)
+    gl = np.array([0.8, -0.6, 1.3])                      # grad(ell)
+    vx = lev.vert_xyz
+    k = 2.0 + vx @ gl                                    # ell > 0 on the unit cube
+    x, y, z = lev.dof_xyz().T
+    if p == 1:
+        q = 0.4 + 1.5 * x - 0.9 * y + 0.7 * z
+        gq = np.stack([np.full_like(x, 1.5), np.full_like(x, -0.9), np.full_like(x, 0.7)])
+        lap_q = np.zeros_like(x)
+    elif p == 2:
+        q = 1.0 + x * x - 2.0 * y * y + 3.0 * z * z + 0.5 * x * y - z * x + 0.25 * y * z + x
+        gq = np.stack([2 * x + 0.5 * y - z + 1.0, -4 * y + 0.5 * x + 0.25 * z, 6 * z - x + 0.25 * y])
+        lap_q = np.full_like(x, 2.0 - 4.0 + 6.0)
+    else:
+        q = x ** 3 + 2 * y ** 2 * z - x * y * z + 0.5 * z ** 3 + y + x * z
+        gq = np.stack([3 * x ** 2 - y * z + z, 4 * y * z - x * z + 1.0, 2 * y ** 2 - x * y + 1.5 * z ** 2 + x])
+        lap_q = 6 * x + 4 * z + 3 * z
+    ell = 2.0 + np.stack([x, y, z]).T @ gl
+    f = -(gl @ gq) - ell * lap_q
+    A = assemble.stiffness(lev, k)
+    M = assemble.mass(lev)
+    I = _interior_rows(lev)
+    return np.max(np.abs((A @ q)[I] - (M @ f)[I])), np.max(np.abs(M @ f))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("jit", [False, True])
+def test_variable_coefficient_exactness(p, jit):
+    err, scale = _var_k_exactness_residual(p, jit)
+    assert err < 1e-13 * max(1.0, scale)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_variable_coefficient_exactness_catches_vertex_permutation(p, monkeypatch):
+    """The exactness pin above fails when the barycentric weights l_v of the P1-coefficient
+    tensor T^{v,ab} are permuted among the vertices (a mistake that A.1 = 0, symmetry, the
+    adjoint identity and finite differences all accept)."""
+    from oracle import refelem
+    T0 = refelem.T(p)
+    for perm in ((1, 0, 2, 3), (3, 1, 2, 0), (0, 2, 3, 1)):
+        err, scale = _var_k_exactness_residual(p, True, T_override=lambda _p, P=perm: T0[list(P)],
+                                               monkeypatch=monkeypatch)
+        assert err > 1e-4 * scale, perm
