@@ -165,7 +165,13 @@ void fem_csr_destroy(fem_csr* a);
 
 /* Solver */
 enum { FEM_PREC_FP64 = 0, FEM_PREC_MIXED = 1 };
-enum { FEM_COARSE_AUTO = 0, FEM_COARSE_DENSE = 1, FEM_COARSE_NESTED = 2 };
+/* Coarse solve (Section 4, Listing 2: a direct solve on the coarsest level, mg_coarse_pc_type lu).
+ * AUTO: the dense FP64 inverse up to 40,000 interior coarse dofs, else nested FP64 MG-PCG to
+ * coarse_rtol over the levels below.  DENSE / NESTED force one of the two.  DENSE_F32 (mixed
+ * precision only; FEM_ERR_INVALID_ARG otherwise): the dense inverse computed in FP64 but stored in
+ * FP32 (products accumulated in FP64): a relaxation of the exact FP64 coarse solve that halves
+ * its bytes, available only when asked for. */
+enum { FEM_COARSE_AUTO = 0, FEM_COARSE_DENSE = 1, FEM_COARSE_NESTED = 2, FEM_COARSE_DENSE_F32 = 3 };
 enum { FEM_PC_MG = 0, FEM_PC_JACOBI = 1 };
 enum { FEM_SMOOTHER_JACOBI = 0, FEM_SMOOTHER_PATCH = 1 };
 
@@ -219,9 +225,13 @@ fem_status fem_solver_create(const fem_mesh* mesh, const fem_solve_opts* opts,
  * coarse operator and its dense inverse (or nested solver).  k_vertex: NULL (k = 1) or FP64
  * device array on the finest level's vertices.  Host-synchronous. */
 fem_status fem_solver_setup(fem_solver* s, const double* k_vertex, void* stream);
-/* Solve A_bc(k) x = b (b, x FP64 device, finest level; x in: initial guess, out: solution).
- * Returns FEM_WARN_NOT_CONVERGED when max_it is reached, FEM_ERR_BREAKDOWN on p^T A p <= 0 or
- * non-finite scalars. */
+/* Solve A_bc(k) x = b, the discrete Poisson problem of Section 2 (eq. 4 with Listing 1's
+ * Dirichlet conditions), by CG preconditioned with the multigrid cycle of Section 4, Listing 2
+ * (Chebyshev smoothing, direct coarse solve) until ||b - A x|| / ||b|| <= rtol.  b, x: FP64
+ * device, finest level, n_dofs each, caller-owned; x in: initial guess, out: solution.
+ * Host-synchronous.  Returns FEM_WARN_NOT_CONVERGED when max_it is reached (x holds the last
+ * iterate), FEM_ERR_BREAKDOWN on p^T A p <= 0 or non-finite scalars, FEM_ERR_STATE before
+ * fem_solver_setup. */
 fem_status fem_solver_solve(fem_solver* s, const double* b, double* x, fem_solve_stats* stats, void* stream);
 /* z = B r: one application of the multigrid preconditioner (FP64 in/out, finest level). */
 fem_status fem_solver_vcycle(fem_solver* s, const double* r, double* z, void* stream);
@@ -239,15 +249,24 @@ fem_status fem_solver_fmg(fem_solver* s, const double* b, double* x, fem_solve_s
 fem_status fem_solver_set_level_timing(fem_solver* s, int32_t on);
 void fem_solver_destroy(fem_solver* s);
 
-/* One-shot: create, set up, solve, destroy. */
+/* One-shot solve of A_bc(k) x = b (Section 2 eq. 4 with Listing 1's boundary conditions; the
+ * multigrid-preconditioned CG of Section 4, Listing 2): create a solver on the caller's
+ * workspace (ws_bytes >= fem_solve_workspace_bytes), set it up for k_vertex (NULL => k = 1, else
+ * FP64 device values on the finest level's vertices), solve and destroy it.  b, x as in
+ * fem_solver_solve; stats (host, may be NULL) receives iterations, residual and times.  Errors
+ * and warnings as fem_solver_create, fem_solver_setup and fem_solver_solve. */
 fem_status fem_mg_cg_solve(const fem_mesh* mesh, const double* k_vertex, const double* b, double* x,
                            const fem_solve_opts* opts, void* workspace, size_t ws_bytes,
                            fem_solve_stats* stats, void* stream);
 
-/* grad_v = - sum_K int_K psi_v grad(u) . grad(lambda) dx over the cells K containing vertex v
- * (psi_v the P1 hat function): the derivative of lambda^T A(k) u with respect to the vertex
- * value k_v, negated.  u, lambda: FP64 n_dofs of `level`; grad: FP64 n_vertices, overwritten.
- * k_vertex is accepted for symmetry with the solve and not read (A is linear in k). */
+/* Adjoint gradient of a functional of the solution with respect to the vertex values of k (the
+ * sensitivities of Section 1, for the operator of Section 2 eq. 4 with a P1 coefficient):
+ *     grad_v = - sum_K int_K psi_v grad(u) . grad(lambda) dx   over the cells K containing v,
+ * psi_v the P1 hat function, i.e. -d(lambda^T A(k) u)/dk_v; with lambda the adjoint solution
+ * (A_bc lambda = dJ/du) this is dJ/dk_v.  u, lambda: FP64 device, n_dofs of `level`; grad: FP64
+ * device, n_vertices, overwritten; all caller-owned.  k_vertex is accepted for symmetry with the
+ * solve and not read (A is linear in k).  Stream-ordered.  Errors: FEM_ERR_INVALID_ARG (NULL
+ * pointers, level out of range), FEM_ERR_STATE (mesh not uploaded), FEM_ERR_HIP. */
 fem_status fem_adjoint_grad_k(const fem_mesh* mesh, int32_t level, const double* k_vertex,
                               const double* u, const double* lambda, double* grad, void* stream);
 

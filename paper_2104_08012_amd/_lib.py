@@ -31,6 +31,7 @@ FEM_PREC_MIXED = 1
 FEM_COARSE_AUTO = 0
 FEM_COARSE_DENSE = 1
 FEM_COARSE_NESTED = 2
+FEM_COARSE_DENSE_F32 = 3
 FEM_PC_MG = 0
 FEM_PC_JACOBI = 1
 FEM_SMOOTHER_JACOBI = 0

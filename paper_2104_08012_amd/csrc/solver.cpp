@@ -21,7 +21,8 @@
 //     inner products and the coarse solve in FP64 and runs the smoother, the level residuals and
 //     the transfers in FP32, casting at the entry and exit of the cycle and at the coarse level;
 //     the Polak-Ribiere beta and periodic true-residual replacement make CG tolerant of the
-//     slightly varying FP32 preconditioner.
+//     slightly varying FP32 preconditioner.  Only the explicit FEM_COARSE_DENSE_F32 option stores
+//     the dense coarse inverse in FP32 (its products still accumulate in FP64).
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -53,6 +54,7 @@ struct Layout {
     size_t inner = 0, inner_bytes = 0;
     size_t total = 0;
     int top = 0, lo = 0, hi = 0, mixed = 0, nested = 0;
+    int coarse32 = 0;   // dense inverse stored in FP32 (FEM_COARSE_DENSE_F32, mixed precision only)
     int64_t dense_n = 0;
 };
 
@@ -145,6 +147,10 @@ fem_status make_layout(const fem_mesh& m, const fem_solve_opts& o, int top, Layo
     const int64_t nI = interior_dofs(m, L.lo);
     const int method = o.coarse_method;
     const bool want_nested = method == FEM_COARSE_NESTED || (method == FEM_COARSE_AUTO && nI > kDenseMax);
+    if (method == FEM_COARSE_DENSE_F32 && !L.mixed) {
+        set_error("FP32 storage of the coarse inverse (FEM_COARSE_DENSE_F32) needs mixed precision");
+        return FEM_ERR_INVALID_ARG;
+    }
     if (want_nested && L.lo == 0) {
         if (method == FEM_COARSE_NESTED) {
             set_error("nested coarse solve needs a mesh level below the coarsest level used");
@@ -170,9 +176,12 @@ fem_status make_layout(const fem_mesh& m, const fem_solve_opts& o, int top, Layo
         L.dense_n = nI;
         L.dense = take((size_t)nI * nI * 8);
         L.dense_xc = take(std::max<int64_t>(nI, 1) * 8);
-        // the packed inverse: FP64, or FP32 in mixed precision (the coarse correction is part of
-        // the FP32 preconditioner; products are still accumulated in FP64)
-        L.dense_packed = take(sym_packed_doubles(nI) * ts);
+        // the packed inverse: FP64 (an exact coarse solve in both precisions), or FP32 storage when
+        // asked for explicitly (FEM_COARSE_DENSE_F32: half the bytes of the HBM-bound coarse
+        // product, products still accumulated in FP64, the coarse correction then rounded like
+        // the rest of the FP32 preconditioner)
+        L.coarse32 = method == FEM_COARSE_DENSE_F32 ? 1 : 0;
+        L.dense_packed = take(sym_packed_doubles(nI) * (L.coarse32 ? 4 : 8));
         L.dense_part = take(sym_partial_doubles(nI) * 8);
     }
     L.total = off;
@@ -382,7 +391,7 @@ fem_status fem_solver::coarse_solve(const double* b64, double* x64) {
         return FEM_OK;
     }
     const HostLevel& C = m->lev[L.lo];
-    if (L.mixed)
+    if (L.coarse32)
         sym_solve_launch(C.L, p<float>(L.dense_packed), b64, p<double>(L.dense_xc), p<double>(L.dense_part), x64, s);
     else
         sym_solve_launch(C.L, p<double>(L.dense_packed), b64, p<double>(L.dense_xc), p<double>(L.dense_part), x64, s);
@@ -657,7 +666,7 @@ fem_status fem_solver::setup(const double* k_top) {
                         probe_extract_launch(C.L, P, S, c0, c1, c2, y, A, s);
                     }
             FEM_TRY(dense_invert(nd, A, nullptr, s));
-            if (L.mixed) sym_pack_launch(nd, A, p<float>(L.dense_packed), s);
+            if (L.coarse32) sym_pack_launch(nd, A, p<float>(L.dense_packed), s);
             else sym_pack_launch(nd, A, p<double>(L.dense_packed), s);
         }
     }
@@ -925,7 +934,7 @@ static fem_status check_opts(const fem_mesh* m, const fem_solve_opts* o) {
     if (!(o->rtol > 0) || o->max_it < 1 || o->cheb_degree < 1 || o->cheb_degree > 16 || !(o->cheb_hi > o->cheb_lo) ||
         !(o->cheb_lo > 0) || (o->precision != FEM_PREC_FP64 && o->precision != FEM_PREC_MIXED) ||
         o->n_levels_used < 0 || o->eig_iters < 0 || o->eig_iters > 64 || !(o->coarse_rtol > 0) ||
-        o->coarse_method < FEM_COARSE_AUTO || o->coarse_method > FEM_COARSE_NESTED ||
+        o->coarse_method < FEM_COARSE_AUTO || o->coarse_method > FEM_COARSE_DENSE_F32 ||
         (o->preconditioner != FEM_PC_MG && o->preconditioner != FEM_PC_JACOBI) ||
         (o->smoother != FEM_SMOOTHER_JACOBI && o->smoother != FEM_SMOOTHER_PATCH)) {
         set_error("solver: invalid options");

@@ -260,7 +260,7 @@ class SolveOptions:
     cheb_lo: float = 0.1
     cheb_hi: float = 1.1
     eig_iters: int = 10
-    coarse_method: str = "auto"    # "auto", "dense", "nested"
+    coarse_method: str = "auto"    # "auto", "dense", "nested", "dense_f32" (mixed only: FP32-stored inverse)
     lambda_max: list | None = None
     coarse_rtol: float = 1e-10
     replace_every: int = 25
@@ -279,7 +279,7 @@ class SolveOptions:
         o.cheb_degree, o.cheb_lo, o.cheb_hi = self.cheb_degree, self.cheb_lo, self.cheb_hi
         o.eig_iters = self.eig_iters
         o.coarse_method = {"auto": L.FEM_COARSE_AUTO, "dense": L.FEM_COARSE_DENSE,
-                           "nested": L.FEM_COARSE_NESTED}[self.coarse_method]
+                           "nested": L.FEM_COARSE_NESTED, "dense_f32": L.FEM_COARSE_DENSE_F32}[self.coarse_method]
         keep = []
         if self.lambda_max is not None:
             arr = (C.c_double * len(self.lambda_max))(*self.lambda_max)

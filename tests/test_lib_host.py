@@ -104,6 +104,14 @@ def test_solver_workspace_coarse_choices():
     assert st == L.FEM_ERR_UNSUPPORTED
     st_m, b_m = ws(n_levels_used=2, precision="mixed")          # 16^3 coarse: dense, 31^3 dofs
     assert st_m == 0 and b_m > 31 ** 6 * 8
+    # the mixed solver keeps the FP64 coarse inverse: its packed half-matrix tiles take at least
+    # 31^6 / 2 * 8 bytes beside the 31^6 * 8 of the dense block; the FP32-stored inverse is an
+    # explicit option that halves them, and is refused in FP64
+    assert b_m > 31 ** 6 * 8 + 31 ** 6 * 4
+    st_f, b_f = ws(n_levels_used=2, precision="mixed", coarse_method="dense_f32")
+    assert st_f == 0 and b_m - b_f > 31 ** 6 * 2 * 0.9
+    st, _ = ws(n_levels_used=2, coarse_method="dense_f32")
+    assert st == L.FEM_ERR_INVALID_ARG
 
 
 @pytest.mark.parametrize("n,p", [(3, 1), (2, 2), (2, 3), (4, 2)])
