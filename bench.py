@@ -1,32 +1,37 @@
 """Benchmark of the hot path on one MI355X.
 
-Default workload ("p2-64"): P2 Lagrange Poisson on the unit cube, 16^3 x 6 tetrahedra refined
-twice to 64^3 x 6 (1,572,864 cells, 2,146,689 dofs), manufactured solution
+Default workload ("p2-128"): P2 Lagrange Poisson on the unit cube, 4^3 x 6 tetrahedra refined
+five times to 128^3 x 6 (12,582,912 cells, 16,974,593 dofs), manufactured solution
 sin(pi x) sin(pi y) sin(pi z) (right-hand side M f with f = 3 pi^2 u, boundary rows zero),
-homogeneous Dirichlet conditions, 3-level geometric multigrid (Chebyshev degree 2 / Jacobi)
-preconditioning CG to relative residual 1e-8.  Synthetic, seeded inputs; nothing is read from
-disk.
+homogeneous Dirichlet conditions, 3-level geometric multigrid (levels 32^3, 64^3, 128^3;
+Chebyshev degree 2 / Jacobi) preconditioning CG to relative residual 1e-8; the 32^3 coarse level
+(250,047 interior dofs) is solved exactly (FP64, nested MG-PCG to 1e-10) in both precisions.
+Synthetic, seeded inputs; nothing is read from disk.
 
 One step = one pass of the hot path:
   1. y = A x, the matrix-free stiffness action in FP64 (Infinity Cache flushed first by reading
-     2 GiB: "cold"),
-  2. the same action in FP32 (cold),
+     2 GiB: "cold"), then twice more back to back ("hot"),
+  2. the same action in FP32 (cold, then hot),
   3. the MG-CG solve to 1e-8 in FP64 (x0 = 0),
-  4. the MG-CG solve to 1e-8 with FP32 smoothing / transfers and FP64 outer CG (x0 = 0),
+  4. the MG-CG solve to 1e-8 with FP32 smoothing / transfers / level residuals and FP64 outer CG
+     and coarse solve (x0 = 0),
   5. the adjoint gradient kernel dJ/dk (u and lambda from steps 3 and 4),
   6. one full-multigrid cycle as the solver (the paper's Listing 2 configuration), FP64 and
      mixed.
 Setup (mesh upload, Jacobi diagonals, Lanczos estimates, coarse inverse) is outside the timed
 region and reported separately.
-After the timed steps (P2 workloads, reported under "patch_smoother"): the additive vertex-star
-patch preconditioner of Listing 2's smoother applied on the finest level in FP64 and FP32 (cold,
-HIP events), and the MG-CG solves with the patch-preconditioned Chebyshev smoother.
+After the timed steps ("sections", all by default): per-level times ("levels"), the additive
+vertex-star patch preconditioner of Listing 2's smoother and the patch-smoothed solves
+("patch", P2), the action sweep P1/P2/P3 x FP64/FP32 on 128^3 x 6 tetrahedra ("sweep"), the
+64^3 P2 workload of the same method (3 levels from 16^3, dense FP64 coarse inverse; "p2-64"),
+and the oracle timed on the host ("cpu", also --no-cpu-baseline).
 
-value = operator-action GDoF/s of step 1: n_dofs / (mean duration of the action, from HIP events
-recorded on the stream the action's kernels run on, over the timed steps).  The action is two
-launches (the cube kernel and the interface fix-up).  Algorithmic bytes of one action:
-  P1/P2 on 4-cube bricks (geometry from vertex coordinates, per-cube dof map):
-      B = 2 N s + 4 (p+1)^3 C/6 + 24 N_v (+ N_v s for a P1 coefficient)
+value = operator-action GDoF/s of step 1: n_dofs / (mean cold duration of the action, from HIP
+events recorded on the stream the action's kernels run on, over the timed steps).  The action is
+two launches (the cube kernel and the interface fix-up), bracketed together.  Algorithmic bytes
+of one action:
+  P1/P2 on 4-cube bricks (geometry from vertex coordinates, dofs addressed by lattice point):
+      B = 2 N s + 24 N_v (+ N_v s for a P1 coefficient)
   otherwise (stored per-cell factors): B = 2 N s + 4 C nloc + 6 C s (+ N_v s)
 (x read and y written once, int32 dof indices, FP64 vertex coordinates or per-cell factors).
 Algorithmic flops: (12 nq nloc + 20 nq) per cell, the tabulated-gradient contraction.  roofline
@@ -39,15 +44,14 @@ WRITE_DIR prints FETCH_SIZE / WRITE_SIZE per kernel and grid, scaled by the coun
 512 MiB calibration copy (--copy-calibration), and --write-traffic stores the action's bytes in
 profiles/apply_traffic.json for the current kernel sources.
 
-Other workloads (--workload): "p3-48-vark" (P3, k = exp(g), 6^3 refined 3x to 48^3, 4-level
-MG-CG, mixed precision as the solver of record), "p2-128" (P2 from 4^3 refined 5x to 128^3; the
-outer cycle uses the 3 finest levels and its 32^3 coarse level is solved by nested FP64 MG-PCG),
-"adjoint-p2-32" (P2 state on 32^3, P1 k: forward solve, misfit, adjoint solve and gradient),
-"p1-8-jacobi" (P1 8^3, Jacobi-CG to 1e-10), "sweep-128" (the action alone, P1/P2/P3 x
-FP64/FP32 on 128^3 x 6 tetrahedra), and for the hierarchy-depth study "p2-64-4lev" (the default
-problem from 8^3, 4 levels, dense 8^3 coarse) and "p2-64-nested" (3 levels with the 16^3 coarse
-level solved by nested MG-PCG); "csr" times the assembled operator (GPU assembly, SpMV) next to
-the matrix-free action.
+Other workloads (--workload): "p2-64" (P2, 16^3 refined twice to 64^3, dense FP64 coarse
+inverse), "p3-48-vark" (P3, k = exp(g), 6^3 refined 3x to 48^3, 4-level MG-CG), "adjoint-p2-32"
+(P2 state on 32^3, P1 k: forward solve, misfit, adjoint solve and gradient), "p1-8-jacobi"
+(P1 8^3, Jacobi-CG to 1e-10), "sweep-128" (the action alone, P1/P2/P3 x FP64/FP32 on 128^3 x 6
+tetrahedra), and for the hierarchy-depth study "p2-64-4lev" (the 64^3 problem from 8^3, 4
+levels, dense 8^3 coarse) and "p2-64-nested" (3 levels with the 16^3 coarse level solved by
+nested MG-PCG); "csr" times the assembled operator (GPU assembly, SpMV) next to the
+matrix-free action.
 """
 from __future__ import annotations
 
@@ -68,9 +72,10 @@ METRIC = ("operator-action GDoF/s (% HBM roofline); MG-CG time to rel residual 1
           "mixed vs FP64")
 
 WORKLOADS = {
+    "p2-128": dict(kind="solve", n0=4, refine=5, p=2, kvar=False, used=3, rhs="sin", rtol=1e-8,
+                   sweep=128, extra="p2-64"),
     "p2-64": dict(kind="solve", n0=16, refine=2, p=2, kvar=False, used=0, rhs="sin", rtol=1e-8),
     "p3-48-vark": dict(kind="solve", n0=6, refine=3, p=3, kvar=True, used=0, rhs="one", rtol=1e-8),
-    "p2-128": dict(kind="solve", n0=4, refine=5, p=2, kvar=False, used=3, rhs="sin", rtol=1e-8),
     # hierarchy-depth study on the default problem: one more level (dense 8^3 coarse), and the
     # 3-level cycle with its 16^3 coarse level solved by nested MG-PCG instead of the dense inverse
     "p2-64-4lev": dict(kind="solve", n0=8, refine=3, p=2, kvar=False, used=0, rhs="sin", rtol=1e-8),
@@ -160,26 +165,41 @@ def roofline(p, kvar, C, N, NV, s, t, key):
     cube = p <= 2 and n % 4 == 0
     out["kernels"] = ("k_cube_apply + k_fixup" if cube else "k_brick + k_fixup") + " (one action)"
     out["duration_us"] = round(t * 1e6, 2)
-    # the same time against the bytes of the per-cell-factor layout (cell-to-dof map and six
-    # geometric factors per cell read, x and y once): the reference design's byte count
-    Bc = balg_bytes(C, N, nloc_of(p), s, NV if kvar else 0)
-    out["percell_layout_bytes"] = Bc
-    out["percell_layout_hbm_frac"] = round(Bc / t / 1e9 / HBM_PEAK_GBS, 4)
     return out
 
 
+def host_cpu():
+    """Model name and logical core count of the host the benchmark runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return model, cores
+
+
 def cpu_baseline(n, p, kvar, max_seconds=30.0):
-    """The oracle's matrix-free FP64 action (numpy, one thread: BLAS pools limited to one thread).
-    Levels above 2^21 cells are sampled by a 64^3 mesh of the same degree (the oracle's cost is
-    linear in the cells)."""
+    """The oracle timed on the host, one thread (BLAS pools limited to one thread): its numpy
+    matrix-free FP64 action (levels above 2^21 cells are sampled by a 64^3 mesh of the same
+    degree; the oracle's cost is linear in the cells), and two of its solves (P1 8^3 Jacobi-CG to
+    1e-10; the 3-level P2 MG-CG to 1e-8 on 8^3 refined twice to 32^3)."""
     from threadpoolctl import threadpool_limits
     with threadpool_limits(limits=1):
         return _cpu_baseline(n, p, kvar, max_seconds)
 
 
 def _cpu_baseline(n, p, kvar, max_seconds):
+    import numpy as np
     import fem_inputs
-    from oracle import assemble
+    from oracle import assemble, solvers
     from oracle import mesh as om
     n_s = n if 6 * n ** 3 <= (1 << 21) else 64
     t0 = time.perf_counter()
@@ -195,10 +215,40 @@ def _cpu_baseline(n, p, kvar, max_seconds):
         reps += 1
     per = t_apply / reps
     what = "the same" if n_s == n else f"a {n_s}^3 x 6 sample of the"
-    return {"value": round(lev.n_dofs / per / 1e9, 6), "unit": "GDoF/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{reps} FP64 applications of the oracle's numpy matrix-free action on {what} "
-                       f"P{p} mesh ({lev.n_dofs} dofs, {per:.2f} s each, mesh build {t_build:.1f} s, "
-                       "single thread)")}
+    model, cores = host_cpu()
+    out = {"value": round(lev.n_dofs / per / 1e9, 6), "unit": "GDoF/s", "cores": 1, "kind": "oracle",
+           "sample": (f"{reps} FP64 applications of the oracle's numpy matrix-free action on {what} "
+                      f"P{p} mesh ({lev.n_dofs} dofs, {per:.2f} s each, mesh build {t_build:.1f} s, "
+                      "single thread)"),
+           "host_cpu": model, "host_logical_cores": cores, "threads_used": 1}
+    del lev, x
+    # oracle solves: P1 8^3 Jacobi-CG to 1e-10, and the P2 3-level MG-CG on 32^3 to 1e-8
+    lev = om.single_level(8, 1)
+    A = assemble.apply_bc(assemble.stiffness(lev), lev.boundary)
+    b = assemble.mass(lev) @ fem_inputs.sin3_f(lev.dof_xyz())
+    b[lev.boundary] = 0
+    dinv = 1.0 / A.diagonal()
+    t1 = time.perf_counter()
+    _, its1, _ = solvers.cg(A, b, rtol=1e-10, M=lambda r: dinv * r)
+    t_cg = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    levels = om.hierarchy(8, 2, 2)
+    lev = levels[-1]
+    b = assemble.mass(lev) @ fem_inputs.sin3_f(lev.dof_xyz())
+    b[lev.boundary] = 0
+    mg = solvers.MGHierarchy(levels)
+    t_setup = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    _, its2, _ = mg.solve(b, rtol=1e-8)
+    t_mg = time.perf_counter() - t1
+    out["solves"] = {
+        "p1-8-jacobi-cg": {"dofs": 729, "rtol": 1e-10, "iterations": its1, "ms": round(t_cg * 1e3, 3)},
+        "p2-32-mgcg": {"dofs": int(lev.n_dofs), "levels": 3, "rtol": 1e-8, "iterations": its2,
+                       "solve_ms": round(t_mg * 1e3, 1), "setup_s": round(t_setup, 2),
+                       "note": "oracle CG + V(2,2) Chebyshev/Jacobi cycle, CSR operators, coarse 8^3 "
+                               "solved by the oracle's direct solve; single thread"},
+    }
+    return out
 
 
 class Timer:
@@ -231,6 +281,22 @@ def mean(v):
     return sum(v) / len(v)
 
 
+def median(v):
+    v = sorted(v)
+    m = len(v) // 2
+    return v[m] if len(v) % 2 else 0.5 * (v[m - 1] + v[m])
+
+
+def stats_us(v):
+    return {"mean": round(mean(v) * 1e6, 2), "median": round(median(v) * 1e6, 2),
+            "min": round(min(v) * 1e6, 2), "n": len(v)}
+
+
+def stats_ms(v):
+    return {"mean": round(mean(v) * 1e3, 3), "median": round(median(v) * 1e3, 3),
+            "min": round(min(v) * 1e3, 3), "n": len(v)}
+
+
 def header(args, name, config, steps_wall):
     return {"metric": METRIC, "value": None, "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": round(steps_wall / args.steps * 1e3, 3),
@@ -251,6 +317,19 @@ def rhs_for(mesh, kind, torch, dev, np, fem_inputs):
     return mesh.mass(f, bc="zero_rows"), u_exact
 
 
+def time_actions(torch, tm, flush, mesh, x64, x32, k64, k32, y64, y32, rec, hot=2):
+    """One cold and `hot` back-to-back applications per precision, recorded in rec."""
+    for tag, x, k, y in (("64", x64, k64, y64), ("32", x32, k32, y32)):
+        flush.sum()
+        e = tm.start()
+        mesh.apply(x, k, out=y)
+        tm.stop(e, "apply" + tag, rec)
+        for _ in range(hot):
+            e = tm.start()
+            mesh.apply(x, k, out=y)
+            tm.stop(e, "apply" + tag + "_hot", rec)
+
+
 def run_solve(args, name, w):
     import numpy as np
     import torch
@@ -259,6 +338,8 @@ def run_solve(args, name, w):
 
     dev = torch.device("cuda:0")
     p, kvar = w["p"], w["kvar"]
+    sections = set(args.sections.split(",")) if args.sections != "all" else {
+        "levels", "patch", "sweep", "extra", "cpu"}
     t_setup0 = time.perf_counter()
     mesh = fem.Mesh(w["n0"], w["refine"], p, device=dev)
     info = mesh.levels[-1]
@@ -289,14 +370,7 @@ def run_solve(args, name, w):
 
     def step(record):
         r = rec if record else None
-        flush.sum()
-        e = tm.start()
-        mesh.apply(x64, k64, out=y64)
-        tm.stop(e, "apply64", r)
-        flush.sum()
-        e = tm.start()
-        mesh.apply(x32, k32, out=y32)
-        tm.stop(e, "apply32", r)
+        time_actions(torch, tm, flush, mesh, x64, x32, k64, k32, y64, y32, r)
         t0 = time.perf_counter()
         u64, r64 = s64.solve(b)
         t1 = time.perf_counter()
@@ -326,107 +400,47 @@ def run_solve(args, name, w):
         step(True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-
-    # per-level times from one more solve per precision with the level events on (kept out of
-    # the timed solves: the events add a few microseconds at every level transition)
-    s64.set_level_timing(True)
-    smx.set_level_timing(True)
-    _, lt64 = s64.solve(b)
-    _, ltmx = smx.solve(b)
-    s64.set_level_timing(False)
-    smx.set_level_timing(False)
-
-    # star-patch smoother (Listing 2's patch preconditioner inside the Chebyshev smoother, P2):
-    # the patch application on the finest level (cold cache, HIP events on the stream it runs on)
-    # and the patch-smoothed MG-CG solves, measured after the timed steps
-    patch_pc = None
-    if p == 2:
-        prec_rec = {}
-        pc64 = fem.PatchPreconditioner(mesh, -1, k64, dtype=torch.float64)
-        pc32 = fem.PatchPreconditioner(mesh, -1, k64, dtype=torch.float32)
-        for it in range(6):
-            r_ = prec_rec if it > 0 else None
-            flush.sum()
-            e = tm.start()
-            pc64.apply(x64, out=y64)
-            tm.stop(e, "patch64", r_)
-            flush.sum()
-            e = tm.start()
-            pc32.apply(x32, out=y32)
-            tm.stop(e, "patch32", r_)
-            tm.collect()
-        del pc64, pc32
-        op64 = fem.SolveOptions(rtol=w["rtol"], precision="fp64", n_levels_used=used, coarse_method=cm,
-                                smoother="patch")
-        opmx = fem.SolveOptions(rtol=w["rtol"], precision="mixed", n_levels_used=used, coarse_method=cm,
-                                smoother="patch")
-        sp64 = fem.Solver(mesh, op64).setup(k64)
-        spmx = fem.Solver(mesh, opmx).setup(k64)
-        tp64, tpmx = [], []
-        for _ in range(3):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            up64, rp64 = sp64.solve(b)
-            t1 = time.perf_counter()
-            upmx, rpmx = spmx.solve(b)
-            t2 = time.perf_counter()
-            tp64.append(t1 - t0)
-            tpmx.append(t2 - t1)
-        a64, a32 = mean(prec_rec["patch64"]), mean(prec_rec["patch32"])
-        alg64, alg32 = 120 * NV * 8 + 2 * N * 8, 120 * NV * 4 + 2 * N * 4
-        patch_pc = {
-            "apply_us_fp64_cold": round(a64 * 1e6, 2), "apply_us_fp32_cold": round(a32 * 1e6, 2),
-            "alg_bytes_fp64": alg64, "alg_bytes_fp32": alg32,
-            "hbm_frac_fp64": round(alg64 / a64 / 8.0e12, 3), "hbm_frac_fp32": round(alg32 / a32 / 8.0e12, 3),
-            "bytes_note": "packed 15x15 star inverses (120 entries per vertex) + r in + z out; the 15 partial "
-                          "results per vertex (written and read back) are not counted",
-            "mgcg_fp64_ms": round(mean(tp64) * 1e3, 3), "mgcg_mixed_ms": round(mean(tpmx) * 1e3, 3),
-            "mgcg_fp64_iterations": rp64.iterations, "mgcg_mixed_iterations": rpmx.iterations,
-            "mgcg_fp64_rel_residual": rp64.rel_residual_true, "mgcg_mixed_rel_residual": rpmx.rel_residual_true,
-            "vs_jacobi_solution_rel_diff": (torch.linalg.norm(up64 - last["u64"]) / torch.linalg.norm(last["u64"])).item(),
-            "lambda_max": [round(v, 6) for v in rp64.lambda_max[:mesh.n_levels]],
-        }
-        del sp64, spmx
+    print(f"[bench] {args.steps} timed steps done in {wall:.2f} s", file=sys.stderr, flush=True)
 
     ta64, ta32 = mean(rec["apply64"]), mean(rec["apply32"])
     key = f"P{p}{'k' if kvar else ''}_n{info['n']}"
+    nl = mesh.n_levels
     out = header(args, name, {
         "description": (f"P{p} Poisson -div(k grad u)=f, unit cube {w['n0']}^3x6 tets refined {w['refine']}x "
                         f"to {info['n']}^3x6 ({C} cells, {N} dofs), "
                         + ("k = exp(g), g a 16-mode Fourier P1 field, f = 1" if kvar else "k = 1, sin MMS")
                         + f"; {mesh.n_levels if not used else used}-level MG-CG (Chebyshev-2/Jacobi) to "
-                        f"{w['rtol']:g}" + (", nested FP64 MG-PCG coarse solve" if used else "")),
+                        f"{w['rtol']:g}" + (", coarse level solved exactly by nested FP64 MG-PCG (1e-10)"
+                                            if used else ", dense FP64 coarse inverse")),
         "cells": C, "dofs": N, "degree": p, "levels": mesh.n_levels, "levels_in_outer_cycle": used or mesh.n_levels,
         "coefficient": "P1 exp(g)" if kvar else "1"}, wall)
     out["value"] = round(N / ta64 / 1e9, 3)
     out["roofline"] = roofline(p, kvar, C, N, NV, 8, ta64, key + "_f64")
     m64, mmx = mean(rec["solve64"]), mean(rec["solvemx"])
     u64, umx, r64, rmx = last["u64"], last["umx"], last["r64"], last["rmx"]
-    nl = mesh.n_levels
     out.update({
-        "apply_ms_fp64_cold": round(ta64 * 1e3, 4),
-        "apply_ms_fp32_cold": round(ta32 * 1e3, 4),
+        "apply_us_fp64_cold": stats_us(rec["apply64"]), "apply_us_fp64_hot": stats_us(rec["apply64_hot"]),
+        "apply_us_fp32_cold": stats_us(rec["apply32"]), "apply_us_fp32_hot": stats_us(rec["apply32_hot"]),
         "apply_fp32_gdofs": round(N / ta32 / 1e9, 3),
         "apply_fp32_roofline": roofline(p, kvar, C, N, NV, 4, ta32, key + "_f32"),
-        "mgcg_fp64_ms": round(m64 * 1e3, 3), "mgcg_mixed_ms": round(mmx * 1e3, 3),
+        "timing_note": ("action: HIP events on the library's stream; cold = Infinity Cache flushed by a 2 GiB "
+                        "read first, hot = back-to-back repeats; solves: host wall clock, first enqueue to "
+                        "return, x0 = 0, setup excluded"),
+        "mgcg_fp64_ms": stats_ms(rec["solve64"]), "mgcg_mixed_ms": stats_ms(rec["solvemx"]),
         "mixed_speedup": round(m64 / mmx, 3),
         "mgcg_fp64_iterations": r64.iterations, "mgcg_mixed_iterations": rmx.iterations,
         "mgcg_fp64_rel_residual": r64.rel_residual_true, "mgcg_mixed_rel_residual": rmx.rel_residual_true,
         "mgcg_fp64_coarse_iterations": r64.coarse_iterations,
         "mgcg_mixed_coarse_iterations": rmx.coarse_iterations,
         "mixed_vs_fp64_solution_rel_diff": (torch.linalg.norm(u64 - umx) / torch.linalg.norm(u64)).item(),
-        "mgcg_fp64_coarse_ms": round(lt64.coarse_ms, 3),
-        "mgcg_mixed_coarse_ms": round(ltmx.coarse_ms, 3),
-        "mgcg_fp64_level_ms": [round(v, 3) for v in lt64.level_ms[:nl]],
-        "mgcg_mixed_level_ms": [round(v, 3) for v in ltmx.level_ms[:nl]],
-        "level_times_note": "coarse/level ms from one extra solve with per-level events on",
+        "precision_split": ("mixed: FP32 smoother applications, level residuals, transfers and D^-1; FP64 outer "
+                            "CG vectors, outer operator, inner products, true residual and the exact coarse "
+                            "solve (FP64 storage and arithmetic)"),
         "lambda_max": [round(v, 6) for v in r64.lambda_max[:nl]],
         "setup_s": round(setup_s, 3),
         "solver_setup_s": {"fp64": round(setup64, 3), "mixed": round(setupmx, 3)},
         "adjoint_grad_kernel_ms": round(mean(rec["grad"]) * 1e3, 4),
-    })
-    out.update({
-        "fmg_fp64_ms": round(mean(rec["fmg64"]) * 1e3, 3), "fmg_mixed_ms": round(mean(rec["fmgmx"]) * 1e3, 3),
+        "fmg_fp64_ms": stats_ms(rec["fmg64"]), "fmg_mixed_ms": stats_ms(rec["fmgmx"]),
         "fmg_fp64_rel_residual": last["rf64"].rel_residual_true, "fmg_mixed_rel_residual": last["rfmx"].rel_residual_true,
         "fmg_vs_mgcg_solution_rel_diff": (torch.linalg.norm(last["uf64"] - u64) / torch.linalg.norm(u64)).item(),
     })
@@ -434,10 +448,184 @@ def run_solve(args, name, w):
         nu = torch.linalg.norm(u_exact)
         out["discretisation_rel_l2_nodal"] = (torch.linalg.norm(u64 - u_exact) / nu).item()
         out["fmg_discretisation_rel_l2_nodal"] = (torch.linalg.norm(last["uf64"] - u_exact) / nu).item()
-    if patch_pc is not None:
-        out["patch_smoother"] = patch_pc
-    if not args.no_cpu_baseline:
+    del last
+
+    if "levels" in sections:
+        # per-level times from one more solve per precision with the level events on (kept out of
+        # the timed solves: the events add a few microseconds at every level transition)
+        s64.set_level_timing(True)
+        smx.set_level_timing(True)
+        _, lt64 = s64.solve(b)
+        _, ltmx = smx.solve(b)
+        s64.set_level_timing(False)
+        smx.set_level_timing(False)
+        out.update({
+            "mgcg_fp64_coarse_ms": round(lt64.coarse_ms, 3), "mgcg_mixed_coarse_ms": round(ltmx.coarse_ms, 3),
+            "mgcg_fp64_level_ms": [round(v, 3) for v in lt64.level_ms[:nl]],
+            "mgcg_mixed_level_ms": [round(v, 3) for v in ltmx.level_ms[:nl]],
+            "level_times_note": "coarse/level ms from one extra solve with per-level events on",
+        })
+        print("[bench] level times done", file=sys.stderr, flush=True)
+    del s64, smx
+    torch.cuda.empty_cache()
+
+    if "patch" in sections and p == 2:
+        out["patch_smoother"] = patch_section(torch, fem, tm, flush, mesh, k64, x64, x32, y64, y32, b, w, used, cm,
+                                              N, NV)
+        print("[bench] patch smoother done", file=sys.stderr, flush=True)
+    del mesh, x64, x32, y64, y32, b
+    torch.cuda.empty_cache()
+
+    if "sweep" in sections and w.get("sweep"):
+        out["sweep"] = sweep_rows(torch, fem, fem_inputs, flush, w["sweep"], reps=max(5, args.steps))
+        print("[bench] sweep done", file=sys.stderr, flush=True)
+    if "extra" in sections and w.get("extra"):
+        out["extra"] = {w["extra"]: solve_extra(torch, fem, fem_inputs, np, flush, WORKLOADS[w["extra"]])}
+        print("[bench] extra workload done", file=sys.stderr, flush=True)
+    del flush
+    torch.cuda.empty_cache()
+    if "cpu" in sections and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(info["n"], p, kvar)
+    return out
+
+
+def patch_section(torch, fem, tm, flush, mesh, k64, x64, x32, y64, y32, b, w, used, cm, N, NV):
+    """Listing 2's patch preconditioner inside the Chebyshev smoother (P2): the patch application
+    on the finest level (cold cache, HIP events on the stream it runs on) and the patch-smoothed
+    MG-CG solves."""
+    prec_rec = {}
+    pc64 = fem.PatchPreconditioner(mesh, -1, k64, dtype=torch.float64)
+    pc32 = fem.PatchPreconditioner(mesh, -1, k64, dtype=torch.float32)
+    for it in range(6):
+        r_ = prec_rec if it > 0 else None
+        flush.sum()
+        e = tm.start()
+        pc64.apply(x64, out=y64)
+        tm.stop(e, "patch64", r_)
+        flush.sum()
+        e = tm.start()
+        pc32.apply(x32, out=y32)
+        tm.stop(e, "patch32", r_)
+        tm.collect()
+    del pc64, pc32
+    op64 = fem.SolveOptions(rtol=w["rtol"], precision="fp64", n_levels_used=used, coarse_method=cm, smoother="patch")
+    opmx = fem.SolveOptions(rtol=w["rtol"], precision="mixed", n_levels_used=used, coarse_method=cm, smoother="patch")
+    sp64 = fem.Solver(mesh, op64).setup(k64)
+    spmx = fem.Solver(mesh, opmx).setup(k64)
+    tp64, tpmx = [], []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        up64, rp64 = sp64.solve(b)
+        t1 = time.perf_counter()
+        upmx, rpmx = spmx.solve(b)
+        t2 = time.perf_counter()
+        tp64.append(t1 - t0)
+        tpmx.append(t2 - t1)
+    a64, a32 = mean(prec_rec["patch64"]), mean(prec_rec["patch32"])
+    alg64, alg32 = 120 * NV * 8 + 2 * N * 8, 120 * NV * 4 + 2 * N * 4
+    return {
+        "apply_us_fp64_cold": stats_us(prec_rec["patch64"]), "apply_us_fp32_cold": stats_us(prec_rec["patch32"]),
+        "alg_bytes_fp64": alg64, "alg_bytes_fp32": alg32,
+        "hbm_frac_fp64": round(alg64 / a64 / 8.0e12, 3), "hbm_frac_fp32": round(alg32 / a32 / 8.0e12, 3),
+        "bytes_note": "packed 15x15 star inverses (120 entries per vertex) + r in + z out; the 15 partial "
+                      "results per vertex (written and read back) are not counted",
+        "mgcg_fp64_ms": stats_ms(tp64), "mgcg_mixed_ms": stats_ms(tpmx),
+        "mgcg_fp64_iterations": rp64.iterations, "mgcg_mixed_iterations": rpmx.iterations,
+        "mgcg_fp64_rel_residual": rp64.rel_residual_true, "mgcg_mixed_rel_residual": rpmx.rel_residual_true,
+        "mixed_vs_fp64_solution_rel_diff": (torch.linalg.norm(upmx - up64) / torch.linalg.norm(up64)).item(),
+        "lambda_max": [round(v, 6) for v in rp64.lambda_max[:mesh.n_levels]],
+    }
+
+
+def sweep_rows(torch, fem, fem_inputs, flush, n, reps):
+    """The action alone, k = 1, on n^3 x 6 tetrahedra: P1/P2/P3 x FP64/FP32, cold (Infinity Cache
+    flushed before each) and hot (back to back)."""
+    rows = []
+    for p in (1, 2, 3):
+        mesh = fem.Mesh(n, 0, p, device="cuda:0")
+        info = mesh.levels[-1]
+        N, C, NV = info["n_dofs"], info["n_cells"], info["n_vertices"]
+        for dt, s in ((torch.float64, 8), (torch.float32, 4)):
+            x = torch.as_tensor(fem_inputs.uniform_vector(N, 0), device="cuda:0").to(dt)
+            y = torch.empty_like(x)
+            tm = Timer(torch)
+            rec = {}
+            for i in range(reps + 1):
+                r = rec if i > 0 else None
+                flush.sum()
+                e = tm.start()
+                mesh.apply(x, out=y)
+                tm.stop(e, "cold", r)
+                for _ in range(2):
+                    e = tm.start()
+                    mesh.apply(x, out=y)
+                    tm.stop(e, "hot", r)
+                tm.collect()
+            t = mean(rec["cold"])
+            tag = "f64" if s == 8 else "f32"
+            rows.append({"degree": p, "dtype": tag, "dofs": N, "cells": C,
+                         "us_cold": stats_us(rec["cold"]), "us_hot": stats_us(rec["hot"]),
+                         "gdofs_cold": round(N / t / 1e9, 3), "gdofs_hot": round(N / mean(rec["hot"]) / 1e9, 3),
+                         "roofline": roofline(p, False, C, N, NV, s, t, f"P{p}_n{n}_{tag}")})
+            del x, y
+        del mesh
+        torch.cuda.empty_cache()
+    return rows
+
+
+def solve_extra(torch, fem, fem_inputs, np, flush, w):
+    """Another workload of the same method, after the timed steps: the action (cold and hot) and
+    MG-CG to the workload's tolerance in FP64, mixed precision (FP64 coarse solve) and, reported
+    under its own name, mixed precision with the FP32-stored dense coarse inverse."""
+    dev = torch.device("cuda:0")
+    p = w["p"]
+    mesh = fem.Mesh(w["n0"], w["refine"], p, device=dev)
+    info = mesh.levels[-1]
+    N, C, NV = info["n_dofs"], info["n_cells"], info["n_vertices"]
+    x64 = torch.as_tensor(fem_inputs.uniform_vector(N, 0), device=dev)
+    x32 = x64.float()
+    y64, y32 = torch.empty_like(x64), torch.empty_like(x32)
+    b, _ = rhs_for(mesh, w["rhs"], torch, dev, np, fem_inputs)
+    tm = Timer(torch)
+    rec = {}
+    for i in range(11):
+        time_actions(torch, tm, flush, mesh, x64, x32, None, None, y64, y32, rec if i > 0 else None)
+        tm.collect()
+    out = {"description": (f"P{p} on {w['n0']}^3x6 refined {w['refine']}x to {info['n']}^3x6 ({N} dofs), "
+                           f"{mesh.n_levels}-level MG-CG to {w['rtol']:g}, dense coarse inverse"),
+           "apply_gdofs_fp64_cold": round(N / mean(rec["apply64"]) / 1e9, 3),
+           "apply_us_fp64_cold": stats_us(rec["apply64"]), "apply_us_fp64_hot": stats_us(rec["apply64_hot"]),
+           "apply_us_fp32_cold": stats_us(rec["apply32"]), "apply_us_fp32_hot": stats_us(rec["apply32_hot"]),
+           "roofline_fp64": roofline(p, False, C, N, NV, 8, mean(rec["apply64"]), f"P{p}_n{info['n']}_f64"),
+           "roofline_fp32": roofline(p, False, C, N, NV, 4, mean(rec["apply32"]), f"P{p}_n{info['n']}_f32")}
+    del x64, x32, y64, y32
+    sols = {}
+    for tag, prec, cm in (("fp64", "fp64", "auto"), ("mixed", "mixed", "auto"),
+                          ("mixed_fp32_coarse_inverse", "mixed", "dense_f32")):
+        S = fem.Solver(mesh, fem.SolveOptions(rtol=w["rtol"], precision=prec, coarse_method=cm)).setup()
+        ts = []
+        for i in range(6):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, r = S.solve(b)
+            if i > 0:
+                ts.append(time.perf_counter() - t0)
+        S.set_level_timing(True)
+        _, lt = S.solve(b)
+        out[f"mgcg_{tag}_ms"] = stats_ms(ts)
+        out[f"mgcg_{tag}_iterations"] = r.iterations
+        out[f"mgcg_{tag}_rel_residual"] = r.rel_residual_true
+        out[f"mgcg_{tag}_coarse_ms"] = round(lt.coarse_ms, 3)
+        sols[tag] = u
+        del S
+    out["mixed_speedup"] = round(out["mgcg_fp64_ms"]["mean"] / out["mgcg_mixed_ms"]["mean"], 3)
+    out["mixed_fp32_coarse_inverse_speedup"] = round(
+        out["mgcg_fp64_ms"]["mean"] / out["mgcg_mixed_fp32_coarse_inverse_ms"]["mean"], 3)
+    out["mixed_vs_fp64_solution_rel_diff"] = (torch.linalg.norm(sols["mixed"] - sols["fp64"])
+                                              / torch.linalg.norm(sols["fp64"])).item()
+    del mesh, sols, b
+    torch.cuda.empty_cache()
     return out
 
 
@@ -550,40 +738,16 @@ def run_sweep(args, name, w):
     import fem_inputs
     from paper_2104_08012_amd import fem
 
-    dev = torch.device("cuda:0")
     n = w["n"]
-    flush = torch.ones(1 << 29, dtype=torch.float32, device=dev)
-    rows = []
-    wall = 0.0
-    for p in (1, 2, 3):
-        mesh = fem.Mesh(n, 0, p, device=dev)
-        info = mesh.levels[-1]
-        N, C, NV = info["n_dofs"], info["n_cells"], info["n_vertices"]
-        for dt, s in ((torch.float64, 8), (torch.float32, 4)):
-            x = torch.as_tensor(fem_inputs.uniform_vector(N, 0), device=dev).to(dt)
-            y = torch.empty_like(x)
-            tm = Timer(torch)
-            rec = {}
-            t0 = time.perf_counter()
-            for i in range(args.warmup + args.steps):
-                flush.sum()
-                e = tm.start()
-                mesh.apply(x, out=y)
-                tm.stop(e, "t", rec if i >= args.warmup else None)
-                tm.collect()
-            wall += time.perf_counter() - t0
-            t = mean(rec["t"])
-            rows.append({"degree": p, "dtype": "f64" if s == 8 else "f32", "dofs": N, "cells": C,
-                         "ms_cold": round(t * 1e3, 4), "gdofs": round(N / t / 1e9, 3),
-                         "roofline": roofline(p, False, C, N, NV, s, t, f"P{p}_n{n}_{'f64' if s == 8 else 'f32'}")})
-            del x, y
-        del mesh
-        torch.cuda.empty_cache()
-    out = header(args, name, {"description": f"matrix-free action alone, k = 1, {n}^3x6 tets (12,582,912 cells), "
-                                             "P1/P2/P3 x FP64/FP32, Infinity Cache flushed before each",
+    flush = torch.ones(1 << 29, dtype=torch.float32, device="cuda:0")
+    t0 = time.perf_counter()
+    rows = sweep_rows(torch, fem, fem_inputs, flush, n, reps=args.steps)
+    wall = time.perf_counter() - t0
+    out = header(args, name, {"description": f"matrix-free action alone, k = 1, {n}^3x6 tets ({6 * n ** 3} cells), "
+                                             "P1/P2/P3 x FP64/FP32, Infinity Cache flushed before each cold run",
                               "cells": 6 * n ** 3}, wall)
     p2 = [r for r in rows if r["degree"] == 2 and r["dtype"] == "f64"][0]
-    out.update({"value": p2["gdofs"], "roofline": p2["roofline"], "sweep": rows})
+    out.update({"value": p2["gdofs_cold"], "roofline": p2["roofline"], "sweep": rows})
     return out
 
 
@@ -648,19 +812,31 @@ def summarize_counters(fdir, wdir, workload, write_traffic):
         acts.setdefault("f64" if "double" in full else "f32", []).append((g, nm, f + w))
     w = WORKLOADS[workload]
     pw = w.get("p", 2)
-    action_kernels = (f"k_cube_apply<{pw},", f"k_brick<0, {pw},", f"k_fixup<{pw},")
-    acts = {prec: [(g, nm, b) for g, nm, b in lst if nm.startswith(action_kernels)] for prec, lst in acts.items()}
     n = w.get("n0", 0) * 2 ** w.get("refine", 0)
+    # the action's kernels: on 4-cube bricks (P1/P2, n divisible by 4) the cube kernel and its
+    # fix-up, whose third template argument is the number of bricks merged along x (4 for P2, 1
+    # for P1); otherwise the brick kernel of the stiffness operator and the unmerged fix-up.  For
+    # P2 this tells the action's fix-up from the mass/gradient fix-up (k_fixup<2, 4, 1, ...>);
+    # for P1 both are the same instance with the same slot layout.
+    cube = pw <= 2 and n % 4 == 0
+    R = 4 if pw == 2 else 1
+    main_prefix = f"k_cube_apply<{pw}," if cube else f"k_brick<0, {pw},"
+    fix_prefix = f"k_fixup<{pw}, 4, {R}," if cube else f"k_fixup<{pw}, 4, 1,"
+    acts = {prec: [(g, nm, b) for g, nm, b in lst if nm.startswith((main_prefix, fix_prefix))]
+            for prec, lst in acts.items()}
     key0 = f"P{w.get('p', 2)}{'k' if w.get('kvar') else ''}_n{n}"
     out = {}
     for prec, lst in acts.items():
         # the finest level's launches: the largest grid of the main kernel and of the fix-up
         best = {}
-        for fam in ("main", "fix"):
-            cand = [(g, nm, b) for g, nm, b in lst if nm.startswith("k_fixup") == (fam == "fix")]
-            if cand:
-                g, nm, b = max(cand)
-                best[nm] = (g, b)
+        mains = [(g, nm, b) for g, nm, b in lst if nm.startswith(main_prefix)]
+        fixes = [(g, nm, b) for g, nm, b in lst if nm.startswith(fix_prefix)]
+        if mains:
+            g, nm, b = max(mains)
+            best[nm] = (g, b)
+        if fixes:
+            g, nm, b = max(fixes)
+            best[nm] = (g, b)
         total = sum(b for g, b in best.values())
         out[f"{key0}_{prec}"] = {"kernel_sources_sha": kernel_sources_sha(), "traffic_bytes": int(total),
                                  "kernels": {nm: {"grid": g, "bytes": int(b)} for nm, (g, b) in best.items()}}
@@ -743,7 +919,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="p2-64", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="p2-128", choices=sorted(WORKLOADS))
+    ap.add_argument("--sections", default="all",
+                    help="comma-separated sections run after the timed steps of a solve workload: levels, "
+                         "patch, sweep, extra, cpu (default all; e.g. 'none' for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 512 MiB device-to-device copy first: a dispatch of known size that "

@@ -117,6 +117,66 @@ def matfree_action(level: Level, x: np.ndarray, k_vertex: np.ndarray | None = No
     return y
 
 
+def action_at(n: int, p: int, vert_xyz: np.ndarray, x: np.ndarray, sample: np.ndarray,
+              k_vertex: np.ndarray | None = None, bc: bool = True) -> np.ndarray:
+    """(A_bc x)_i (bc=True) or (A x)_i for the sampled dofs i only, on the P_p space of the
+    n^3 x 6 mesh with vertex positions vert_xyz (((n+1)^3, 3)).
+
+    The same definition as matfree_action, summed over the cells around each sampled dof
+    instead of all cells: row i of A x is the sum over the cells whose closure holds dof i of
+    their local products, and those cells lie in the cubes whose p-lattice box contains the
+    dof's lattice point.  Those cubes' six tetrahedra are formed (a superset; the other cells'
+    rows do not include dof i), their element matrices built from the same reference tensors,
+    and the local products summed into the sampled rows.  Used for checks at sizes where the
+    full action is too slow to compute.
+    """
+    from .mesh import cube_cells, vertex_id
+    sample = np.asarray(sample, dtype=np.int64)
+    L = p * n + 1
+    ijk = np.stack([sample % L, (sample // L) % L, sample // (L * L)], axis=1)
+    cand = []
+    for d in range(3):
+        lo = np.clip((ijk[:, d] - 1) // p, 0, n - 1)
+        hi = np.clip(ijk[:, d] // p, 0, n - 1)
+        cand.append((lo, hi))
+    corners = []
+    for bits in range(8):
+        c = np.stack([cand[d][(bits >> d) & 1] for d in range(3)], axis=1)
+        corners.append(c)
+    corners = np.unique(np.concatenate(corners), axis=0)
+    cells_ijk = cube_cells(corners)
+    cell_vert = vertex_id(n, cells_ijk)
+    mi = np.array(refelem.node_multi_indices(p), dtype=np.int64)
+    lat = np.einsum("li,cid->cld", mi, cells_ijk)
+    cell_dofs = lat[..., 0] + L * (lat[..., 1] + L * lat[..., 2])
+    xyz = vert_xyz[cell_vert]
+    J = np.stack([xyz[:, 1] - xyz[:, 0], xyz[:, 2] - xyz[:, 0], xyz[:, 3] - xyz[:, 0]], axis=2)
+    det = np.linalg.det(J)
+    Jinv = np.linalg.inv(J)
+    G = np.abs(det)[:, None, None] * np.einsum("cai,cbi->cab", Jinv, Jinv)
+    if k_vertex is None:
+        Ae = np.einsum("cab,abij->cij", G, refelem.S(p))
+    else:
+        kc = np.asarray(k_vertex, dtype=np.float64)[cell_vert]
+        Ae = np.einsum("cv,cab,vabij->cij", kc, G, refelem.T(p))
+    xl = np.asarray(x, dtype=np.float64)[cell_dofs]
+    if bc:
+        on_bnd = np.any((lat == 0) | (lat == p * n), axis=2)
+        xl = np.where(on_bnd, 0.0, xl)
+    yk = np.einsum("cij,cj->ci", Ae, xl)
+    uniq, inv = np.unique(sample, return_inverse=True)
+    flat = cell_dofs.ravel()
+    pos = np.searchsorted(uniq, flat)
+    hit = (pos < uniq.size) & (uniq[np.minimum(pos, uniq.size - 1)] == flat)
+    acc = np.zeros(uniq.size)
+    np.add.at(acc, pos[hit], yk.ravel()[hit])
+    y = acc[inv]
+    if bc:
+        s_bnd = np.any((ijk == 0) | (ijk == p * n), axis=1)
+        y[s_bnd] = np.asarray(x, dtype=np.float64)[sample[s_bnd]]
+    return y
+
+
 def diagonal(A: sp.csr_matrix) -> np.ndarray:
     return A.diagonal().copy()
 

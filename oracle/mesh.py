@@ -44,6 +44,12 @@ def kuhn_cells(n: int) -> np.ndarray:
     r = np.arange(n)
     kk, jj, ii = np.meshgrid(r, r, r, indexing="ij")
     corners = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1)  # (n^3, 3)
+    return cube_cells(corners)
+
+
+def cube_cells(corners: np.ndarray) -> np.ndarray:
+    """The 6 tetrahedra of each cube with the given lower corners: (6 m, 4, 3), cube-major."""
+    corners = np.asarray(corners, dtype=np.int64).reshape(-1, 3)
     cells = np.zeros((corners.shape[0], 6, 4, 3), dtype=np.int64)
     for t, s in enumerate(PERMS):
         v = corners.copy()

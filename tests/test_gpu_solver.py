@@ -1,7 +1,8 @@
 """GPU parity of the multigrid-CG solver against the oracle, through the C ABI.
 
 * One FP64 V-cycle against the oracle's V-cycle with the same lambda_max (1e-12): exercises the
-  Chebyshev smoother, transfers, rediscretised coefficient and exact coarse solve together.
+  Chebyshev smoother, transfers, rediscretised coefficient and exact coarse solve together; two-,
+  three- and four-level cycles.
 * Solutions to rtol 1e-10 against the oracle's reference solution (1e-8), FP64 and mixed.
 * Jacobi-CG on the P1 8^3 workload (iteration bound 60 for 1e-10).
 * Nested coarse solve (FP64 MG-PCG over the levels below the coarsest level used): one V-cycle
@@ -9,6 +10,7 @@
   solutions against the oracle's reference solution (1e-8), FP64 and mixed.
 * Failure handling: max_it reached, NaN right-hand side, negative coefficient, bad arguments.
 * Determinism and warm start.
+* Mixed precision keeps the coarse solve in FP64 (the FP32-stored inverse only on request).
 """
 import numpy as np
 import pytest
@@ -32,7 +34,9 @@ def _rhs(lev):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("n0,r,p,jit,kvar", [(2, 2, 2, 0.1, True), (2, 2, 1, 0.0, False), (2, 1, 3, 0.1, True),
-                                             (3, 1, 2, 0.0, True)])
+                                             (3, 1, 2, 0.0, True),
+                                             # four-level cycles, as the P3 k = exp(g) workload runs
+                                             (1, 3, 2, 0.1, True), (1, 3, 3, 0.0, True)])
 def test_vcycle_matches_oracle(n0, r, p, jit, kvar):
     banner(f"vcycle n0={n0} r={r} p={p} kvar={kvar}")
     from paper_2104_08012_amd import fem
@@ -243,3 +247,30 @@ def test_smallest_meshes_and_zero_rhs(p):
     z, rz = S.solve(torch.zeros(lev.n_dofs, dtype=torch.float64, device="cuda:0"))
     torch.cuda.synchronize()
     assert rz.iterations == 0 and float(z.abs().max()) == 0.0
+
+
+@pytest.mark.gpu
+def test_mixed_precision_coarse_solve_is_fp64():
+    """In mixed precision the coarse solve stays FP64 (Section 4's direct coarse solve; the FP32
+    part of the method is the smoother and the transfers): full multigrid on one level is the
+    coarse solve alone, so the mixed solver's result equals the oracle's direct solve to FP64
+    accuracy.  The FP32-stored inverse (coarse_method "dense_f32") is an explicit option and
+    agrees only to FP32 accuracy."""
+    banner("mixed coarse solve FP64 / dense_f32")
+    from paper_2104_08012_amd import fem
+    mesh, levels = make_pair(4, 1, 2, 0.1)
+    lev = levels[-1]
+    k = fem_inputs.k_exp_fourier(lev.vert_xyz)
+    A = assemble.apply_bc(assemble.stiffness(lev, k), lev.boundary)
+    b = _rhs(lev)
+    u_ref = solvers.direct_solve(A, b, rtol=1e-14)
+    for cm, tol in (("auto", 1e-11), ("dense", 1e-11), ("dense_f32", 1e-5)):
+        S = fem.Solver(mesh, fem.SolveOptions(precision="mixed", n_levels_used=1, coarse_method=cm)).setup(_t(k))
+        u, _ = S.fmg(_t(b))
+        torch.cuda.synchronize()
+        assert rel(u.cpu().numpy(), u_ref) <= tol, cm
+    # and the outer solve with the FP32-stored inverse still reaches the FP64 residual
+    S = fem.Solver(mesh, fem.SolveOptions(rtol=1e-10, precision="mixed", coarse_method="dense_f32")).setup(_t(k))
+    u, res = S.solve(_t(b))
+    torch.cuda.synchronize()
+    assert res.rel_residual_true <= 1e-10 and rel(u.cpu().numpy(), u_ref) <= 1e-8

@@ -208,3 +208,22 @@ def test_variable_coefficient_exactness_catches_vertex_permutation(p, monkeypatc
         err, scale = _var_k_exactness_residual(p, True, T_override=lambda _p, P=perm: T0[list(P)],
                                                monkeypatch=monkeypatch)
         assert err > 1e-4 * scale, perm
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("kvar", [False, True])
+@pytest.mark.parametrize("bc", [True, False])
+def test_action_at_sampled_rows_equals_full_action(p, kvar, bc):
+    """The sampled-row evaluation (cells around each sampled dof only) equals the full action on
+    every dof of small jittered meshes, boundary rows included, with repeated sample entries."""
+    n = 3
+    lev = om.single_level(n, p, fem_inputs.jitter_offsets(n, 0.15))
+    k = fem_inputs.k_exp_fourier(lev.vert_xyz) if kvar else None
+    x = fem_inputs.uniform_vector(lev.n_dofs, 0)
+    y = assemble.matfree_action(lev, x, k, bc=bc)
+    every = np.arange(lev.n_dofs)
+    ys = assemble.action_at(n, p, lev.vert_xyz, x, every, k, bc=bc)
+    assert np.max(np.abs(ys - y)) <= 1e-14 * np.max(np.abs(y))
+    sub = np.array([5, 0, lev.n_dofs - 1, 5, 17])
+    ysub = assemble.action_at(n, p, lev.vert_xyz, x, sub, k, bc=bc)
+    assert np.max(np.abs(ysub - y[sub])) <= 1e-14 * np.max(np.abs(y))
