@@ -123,6 +123,24 @@ fem_status fem_apply_laplacian_axpby(const fem_mesh* mesh, int32_t level, fem_dt
                                      const void* z, double beta, void* y,
                                      uint32_t flags, void* stream);
 
+/* For callers that cannot allocate device memory or have it allocated for them (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): y = A(k) x exactly as
+ * fem_apply_laplacian computes it (the same kernels; the same result bit for bit), except that the
+ * kernels keep the interface partial sums of the brick decomposition in a library-owned
+ * file-scope device array of 64 MiB per GPU instead of the level's slot area in the mesh buffer.
+ * Allocates nothing: the array's device address is looked up once per GPU on the first call made
+ * with that GPU current.  Arguments as fem_apply_laplacian; the current device must be the one
+ * the mesh was uploaded to.  The array needs 8 * (interface points) * sizeof(dtype) bytes for the
+ * level (P2 up to 64^3 cubes in FP64, P3 up to 48^3); larger levels return FEM_ERR_WORKSPACE
+ * before anything is enqueued.  Every call on a GPU shares that GPU's array and leaves its partial
+ * sums there (no call reads a value it has not written first, so nothing needs clearing); calls
+ * that overlap in time on one GPU (other streams, concurrent graph replays) race on the array.
+ * Stream-ordered.  Errors: FEM_ERR_INVALID_ARG (as fem_apply_laplacian, or another device
+ * current), FEM_ERR_STATE, FEM_ERR_WORKSPACE, FEM_ERR_HIP. */
+fem_status fem_apply_laplacian_noalloc(const fem_mesh* mesh, int32_t level, fem_dtype dtype,
+                                       const void* k_vertex, const void* x, void* y,
+                                       uint32_t flags, void* stream);
+
 /* y = M x, the consistent mass matrix int phi_i phi_j (used for J and the adjoint right-hand
  * side).  flags as above (FEM_BC_NONE gives the raw matrix). */
 fem_status fem_apply_mass(const fem_mesh* mesh, int32_t level, fem_dtype dtype,

@@ -85,6 +85,7 @@ SIGNATURES = {
     "fem_apply_laplacian": (_st, [_vp, _i32, _i32, _vp, _vp, _vp, C.c_uint32, _vp]),
     "fem_apply_laplacian_axpby": (_st, [_vp, _i32, _i32, _vp, _vp, C.c_double, _vp, C.c_double, _vp,
                                         C.c_uint32, _vp]),
+    "fem_apply_laplacian_noalloc": (_st, [_vp, _i32, _i32, _vp, _vp, _vp, C.c_uint32, _vp]),
     "fem_apply_mass": (_st, [_vp, _i32, _i32, _vp, _vp, C.c_uint32, _vp]),
     "fem_assemble_diagonal": (_st, [_vp, _i32, _i32, _vp, _vp, _vp]),
     "fem_prolong": (_st, [_vp, _i32, _i32, _vp, _vp, _vp]),

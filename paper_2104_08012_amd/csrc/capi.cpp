@@ -214,6 +214,47 @@ fem_status fem_apply_laplacian(const fem_mesh* m, int32_t level, fem_dtype dtype
     return fem_apply_laplacian_axpby(m, level, dtype, k, x, 1.0, nullptr, 0.0, y, flags, stream);
 }
 
+fem_status fem_apply_laplacian_noalloc(const fem_mesh* m, int32_t level, fem_dtype dtype, const void* k,
+                                      const void* x, void* y, uint32_t flags, void* stream) {
+    fem_status st = check_common(m, level, dtype, "fem_apply_laplacian_noalloc");
+    if (st) return st;
+    FEM_REQUIRE(x && y, FEM_ERR_INVALID_ARG, "fem_apply_laplacian_noalloc: NULL vector");
+    FEM_REQUIRE(x != y, FEM_ERR_INVALID_ARG, "fem_apply_laplacian_noalloc: x and y must differ");
+    FEM_REQUIRE(flags <= FEM_BC_ZERO_ROWS, FEM_ERR_INVALID_ARG, "fem_apply_laplacian_noalloc: bad flags");
+    int dev = -1;
+    FEM_REQUIRE(hipGetDevice(&dev) == hipSuccess && dev == m->device, FEM_ERR_INVALID_ARG,
+                "fem_apply_laplacian_noalloc: the current device is not the mesh's device");
+    void* scr = nullptr;
+    size_t scr_bytes = 0;
+    st = noalloc_scratch(&scr, &scr_bytes);
+    if (st) return st;
+    const int rm = row_mode_of(flags);
+    const bool mask = flags != FEM_BC_NONE && flags != FEM_BC_ZERO_ROWS;
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == FEM_F64) {
+        ScatterIO<double> io;
+        io.x = (const double*)x;
+        io.k = (const double*)k;
+        io.y = (double*)y;
+        io.row_mode = rm;
+        io.xid = (const double*)x;
+        io.mask_cols = mask;
+        io.slots = scr;
+        io.slots_bytes = scr_bytes;
+        return run_scatter<double>(*m, level, K_APPLY, k != nullptr, io, s);
+    }
+    ScatterIO<float> io;
+    io.x = (const float*)x;
+    io.k = (const float*)k;
+    io.y = (float*)y;
+    io.row_mode = rm;
+    io.xid = (const float*)x;
+    io.mask_cols = mask;
+    io.slots = scr;
+    io.slots_bytes = scr_bytes;
+    return run_scatter<float>(*m, level, K_APPLY, k != nullptr, io, s);
+}
+
 fem_status fem_apply_mass(const fem_mesh* m, int32_t level, fem_dtype dtype, const void* x, void* y, uint32_t flags,
                           void* stream) {
     fem_status st = check_common(m, level, dtype, "fem_apply_mass");

@@ -1,11 +1,44 @@
 // Launchers for the cell-wise kernels (stiffness action, diagonal, mass, transfers, adjoint
 // gradient): fill the kernel arguments from the mesh's device tables and dispatch the template
 // instance for the degree, brick size, coefficient kind and precision.
+#include <mutex>
+
 #include "ops.hpp"
 #include "cube.hpp"
 #include "scatter.hpp"
 
 namespace fem {
+
+// Interface partial sums of fem_apply_laplacian_noalloc: a file-scope device array, one copy per
+// GPU the library runs on, held until the process ends.  In host code its name is a host-side
+// stand-in: kernels receive the device address looked up by noalloc_scratch.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kNoallocScratchBytes];
+
+fem_status noalloc_scratch(void** ptr, size_t* bytes) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        set_error("fem_apply_laplacian_noalloc: no current HIP device");
+        return FEM_ERR_HIP;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error(std::string("fem_apply_laplacian_noalloc: scratch address lookup failed: ") +
+                      hipGetErrorString(e));
+            return FEM_ERR_HIP;
+        }
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = kNoallocScratchBytes;
+    return FEM_OK;
+}
 
 namespace {
 
@@ -107,7 +140,7 @@ fem_status run_kind(const fem_mesh& m, int level, bool kvar, const ScatterIO<T>&
     a.aux = (KIND == K_MASS) ? dptr<T>(m, mref_off<T>(m)) : (KIND == K_RESTRICT) ? dptr<T>(m, ploc_off<T>(m)) : nullptr;
     a.fine_mi = dptr<int32_t>(m, m.d_fine_mi);
     a.owner = (KIND == K_RESTRICT) ? dptr<uint32_t>(m, L.d_owner) : nullptr;
-    a.slots = const_cast<T*>(dptr<T>(m, L.d_slots));
+    a.slots = io.slots ? static_cast<T*>(io.slots) : const_cast<T*>(dptr<T>(m, L.d_slots));
     a.mask_cols = io.mask_cols;
     a.Lin = (KIND == K_RESTRICT) ? m.lev[level + 1].L : 0;
     a.x = io.x;
@@ -130,6 +163,12 @@ fem_status run_kind(const fem_mesh& m, int level, bool kvar, const ScatterIO<T>&
     a.if_c0 = ic.c0;
     a.if_c01 = ic.c01;
     a.if_tot = ic.total;
+    if (io.slots && (size_t)8 * ic.total * sizeof(T) > io.slots_bytes) {
+        // slot code * total + t for the 8 side codes: more than the array holds
+        set_error("interface partial sums need " + std::to_string((size_t)8 * ic.total * sizeof(T)) +
+                  " bytes, more than the " + std::to_string(io.slots_bytes) + " of the scratch array");
+        return FEM_ERR_WORKSPACE;
+    }
     launch_p<KIND, T>(m.p, L.B, kvar, a, L.nbricks, s);
     FixGeom fg;
     fg.cnt0 = ic.c0;

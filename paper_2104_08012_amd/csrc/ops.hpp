@@ -22,6 +22,10 @@ struct ScatterIO {
     int row_mode = ROW_IDENTITY;
     const T* xid = nullptr;
     int mask_cols = 1;
+    // interface partial sums: the level's slot area of the mesh buffer (NULL), or this array of
+    // slots_bytes (the allocation-free action's file-scope scratch)
+    void* slots = nullptr;
+    size_t slots_bytes = 0;
 };
 
 // kind: K_APPLY, K_DIAG, K_MASS, K_RESTRICT (level = coarse level), K_GRAD (T = double).
@@ -32,6 +36,10 @@ template <typename T>
 fem_status run_prolong(const fem_mesh& m, int fine_level, const T* xc, T* xf, hipStream_t s);
 
 fem_status check_launch(const char* what);
+
+// Device address of the file-scope scratch array of the allocation-free action on the current
+// device (looked up once per device), and its size in bytes.
+fem_status noalloc_scratch(void** ptr, size_t* bytes);
 
 // Additive vertex-star patch preconditioner, degree 2 (patch.hip).
 size_t patch_bytes(const HostLevel& H, size_t ts);
