@@ -854,6 +854,64 @@ def summarize_counters(fdir, wdir, workload, write_traffic):
         print(f"wrote {path}")
 
 
+VALU_PASSES = (
+    "SQ_INSTS_VALU_FLOPS_FP64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 "
+    "SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_VALU_MFMA_MOPS_F64 GRBM_GUI_ACTIVE",
+    "SQ_INSTS_VALU_FLOPS_FP32 SQ_INSTS_VALU_FMA_F32 SQ_INSTS_VALU_ADD_F32 SQ_INSTS_VALU_MUL_F32 "
+    "SQ_INSTS_VALU_TRANS_F32 SQ_INSTS_LDS SQ_WAVES SQ_BUSY_CU_CYCLES GRBM_GUI_ACTIVE",
+)
+
+
+def summarize_valu(dirs, trace_dir, kernels):
+    """Issued VALU work per dispatch from rocprofv3 --pmc runs (the counter sets of VALU_PASSES,
+    one run each), averaged per kernel and grid, with the kernel's median duration from a
+    --kernel-trace run:
+      flops: 64 lanes x (add + mul + transcendental + 2 fma) wave instructions, FP64 for kernels
+             instantiated in double, FP32 otherwise (SQ_INSTS_VALU_FLOPS_* counts one lane);
+      rate:  flops / duration, and its fraction of the vector peak;
+      issue: VALU wave instructions x 4 cycles / (1024 SIMDs x 2.4 GHz x duration), the share of
+             the VALU issue slots the kernel fills (full-rate FP32/FP64 instructions take 4
+             cycles per wave on a 16-lane SIMD);
+      busy:  100 SQ_ACTIVE_INST_VALU / (256 CUs x GRBM_GUI_ACTIVE / 8), rocprofv3's VALUBusy
+             with GRBM_GUI_ACTIVE, which the per-dispatch record sums over the 8 XCDs, taken
+             per XCD (grbm_MHz, GRBM_GUI_ACTIVE per microsecond, shows the sum)."""
+    import collections
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for d in dirs:
+        for r in _csv(os.path.join(d, "run_counter_collection.csv")):
+            key = (_short(r["Kernel_Name"]), int(r["Grid_Size"]))
+            vals[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    dur = collections.defaultdict(list)
+    if trace_dir:
+        for r in _csv(os.path.join(trace_dir, "run_kernel_trace.csv")):
+            dur[(_short(r["Kernel_Name"]), int(r["Grid_Size_X"]))].append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+    print(f"{'GFLOP':>8} {'valu_Minst':>10} {'t_us':>8} {'TF/s':>6} {'frac':>5} {'issue':>5} {'busy%':>6} "
+          f"{'grbm_MHz':>8} {'lds_Minst':>9}  kernel [grid threads]")
+    rows = []
+    for (nm, g), c in vals.items():
+        if kernels and not any(nm.startswith(k) for k in kernels):
+            continue
+        m = {k: sum(v) / len(v) for k, v in c.items()}
+        dbl = "double" in nm
+        sfx = "F64" if dbl else "F32"
+        fl = 64 * (m.get(f"SQ_INSTS_VALU_ADD_{sfx}", 0) + m.get(f"SQ_INSTS_VALU_MUL_{sfx}", 0)
+                   + m.get(f"SQ_INSTS_VALU_TRANS_{sfx}", 0) + 2 * m.get(f"SQ_INSTS_VALU_FMA_{sfx}", 0))
+        t = sorted(dur.get((nm, g), []))
+        tm = t[len(t) // 2] if t else 0.0
+        rate = fl / tm / 1e12 if tm else 0.0
+        peak = FP64_PEAK_TFLOPS if dbl else FP32_PEAK_TFLOPS
+        vi = m.get("SQ_INSTS_VALU", 0.0)
+        issue = vi * 4 / (1024 * 2.4e9 * tm) if tm else 0.0
+        gg = m.get("GRBM_GUI_ACTIVE", 0.0)
+        busy = 100.0 * m.get("SQ_ACTIVE_INST_VALU", 0.0) / 256 / (gg / 8) if gg else 0.0
+        rows.append((fl, f"{fl / 1e9:8.3f} {vi / 1e6:10.2f} {tm * 1e6:8.2f} {rate:6.2f} {rate / peak:5.2f} "
+                         f"{issue:5.2f} {busy:6.1f} {gg / (tm * 1e6) if tm else 0:8.0f} "
+                         f"{m.get('SQ_INSTS_LDS', 0) / 1e6:9.2f}  {nm} [{g}]"))
+    for _, line in sorted(rows, key=lambda r: -r[0]):
+        print(line)
+
+
 def run_csr(args, name, w):
     import torch
     import fem_inputs
@@ -930,9 +988,17 @@ def main():
     ap.add_argument("--summarize-trace", metavar="DIR")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--write-traffic", action="store_true")
+    ap.add_argument("--summarize-valu", nargs="+", metavar="PMC_DIR",
+                    help="rocprofv3 --pmc directories of the VALU_PASSES counter sets")
+    ap.add_argument("--valu-trace", metavar="TRACE_DIR", help="kernel-trace directory for durations")
+    ap.add_argument("--valu-kernels", default="k_cube_apply,k_brick<0,k_fixup",
+                    help="comma-separated kernel-name prefixes to list")
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(args.summarize_trace)
+        return
+    if args.summarize_valu:
+        summarize_valu(args.summarize_valu, args.valu_trace, [k for k in args.valu_kernels.split(",") if k])
         return
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, args.workload, args.write_traffic)
