@@ -215,7 +215,7 @@ typedef struct {
                                     level transition); 0 (default): level_ms stay zero            */
     int32_t smoother;            /* preconditioner of the Chebyshev smoother on the smoothed levels:
                                     FEM_SMOOTHER_JACOBI (default, diag(A)^-1) or FEM_SMOOTHER_PATCH
-                                    (Listing 2: additive vertex-star patches, degree 2 only, as
+                                    (Listing 2: additive vertex-star patches, degrees 2 and 3, as
                                     fem_apply_patch; lambda_max of B_patch A from CG-Lanczos).  A
                                     nested coarse solver smooths with Jacobi.                     */
 } fem_solve_opts;
@@ -292,11 +292,13 @@ fem_status fem_adjoint_grad_k(const fem_mesh* mesh, int32_t level, const double*
  * is the patch preconditioner with star patches around vertices, construct_dim 0):
  *     z = sum_v R_v^T A_v^{-1} R_v r on interior dofs,  z_B = r_B,
  * R_v restricting to the interior dofs whose carrying entity contains vertex v, A_v = R_v A R_v^T
- * with A the stiffness matrix of k.  Degree 2 only (15 dofs per interior star; other degrees
- * return FEM_ERR_UNSUPPORTED).
+ * with A the stiffness matrix of k.  Degrees 2 and 3: an interior star holds 15 dofs for P2 (the
+ * vertex and the 14 edge midpoints around it) and 65 for P3 (the vertex, two dofs on each of 14
+ * edges, one on each of 36 faces).  Degree 1 (every star one dof: point Jacobi) and levels whose
+ * packed index (entries per vertex x n_vertices) reaches 2^32 return FEM_ERR_UNSUPPORTED.
  * fem_patch_bytes: size of the caller-owned patch buffer of `level` for dtype (the packed
- * lower triangles of the 15x15 star inverses, 120 entries per vertex, plus 15 partial results per
- * vertex), 256-byte aligned parts.
+ * lower triangles of the star inverses, 120 (P2) or 2145 (P3) entries per vertex, plus 15 or 65
+ * partial results per vertex), 256-byte aligned parts.
  * fem_patch_setup: fills the buffer for k_vertex (FP64 device, n_vertices; NULL => k = 1); the
  * inverses are computed in FP64 and stored in dtype.  FEM_ERR_WORKSPACE for a NULL or short
  * buffer.  Stream-ordered.

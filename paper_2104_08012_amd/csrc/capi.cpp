@@ -354,7 +354,8 @@ fem_status fem_patch_bytes(const fem_mesh* m, int32_t level, fem_dtype dtype, si
     FEM_REQUIRE(m && bytes, FEM_ERR_INVALID_ARG, "fem_patch_bytes: NULL argument");
     FEM_REQUIRE(level >= 0 && level < m->nlev, FEM_ERR_INVALID_ARG, "fem_patch_bytes: level out of range");
     FEM_REQUIRE(dtype == FEM_F64 || dtype == FEM_F32, FEM_ERR_INVALID_ARG, "fem_patch_bytes: bad dtype");
-    FEM_REQUIRE(m->p == 2, FEM_ERR_UNSUPPORTED, "fem_patch_bytes: star patches are built for degree 2 only");
+    std::string why;
+    FEM_REQUIRE(patch_supported(m->lev[level], why), FEM_ERR_UNSUPPORTED, "fem_patch_bytes: " + why);
     *bytes = patch_bytes(m->lev[level], dtype == FEM_F64 ? 8 : 4);
     return FEM_OK;
 }
@@ -363,7 +364,8 @@ fem_status fem_patch_setup(const fem_mesh* m, int32_t level, fem_dtype dtype, co
                            size_t bytes, void* stream) {
     fem_status st = check_common(m, level, dtype, "fem_patch_setup");
     if (st) return st;
-    FEM_REQUIRE(m->p == 2, FEM_ERR_UNSUPPORTED, "fem_patch_setup: star patches are built for degree 2 only");
+    std::string why;
+    FEM_REQUIRE(patch_supported(m->lev[level], why), FEM_ERR_UNSUPPORTED, "fem_patch_setup: " + why);
     const size_t need = patch_bytes(m->lev[level], dtype == FEM_F64 ? 8 : 4);
     FEM_REQUIRE(patch && bytes >= need, FEM_ERR_WORKSPACE, "fem_patch_setup: patch buffer NULL or too small");
     return dtype == FEM_F64 ? patch_setup<double>(*m, level, k, patch, (hipStream_t)stream)
@@ -374,7 +376,8 @@ fem_status fem_apply_patch(const fem_mesh* m, int32_t level, fem_dtype dtype, vo
                            const void* r, void* z, void* stream) {
     fem_status st = check_common(m, level, dtype, "fem_apply_patch");
     if (st) return st;
-    FEM_REQUIRE(m->p == 2, FEM_ERR_UNSUPPORTED, "fem_apply_patch: star patches are built for degree 2 only");
+    std::string why;
+    FEM_REQUIRE(patch_supported(m->lev[level], why), FEM_ERR_UNSUPPORTED, "fem_apply_patch: " + why);
     const size_t need = patch_bytes(m->lev[level], dtype == FEM_F64 ? 8 : 4);
     FEM_REQUIRE(patch && bytes >= need, FEM_ERR_WORKSPACE, "fem_apply_patch: patch buffer NULL or too small");
     FEM_REQUIRE(r && z, FEM_ERR_INVALID_ARG, "fem_apply_patch: NULL vector");

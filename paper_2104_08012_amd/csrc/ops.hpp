@@ -41,7 +41,8 @@ fem_status check_launch(const char* what);
 // device (looked up once per device), and its size in bytes.
 fem_status noalloc_scratch(void** ptr, size_t* bytes);
 
-// Additive vertex-star patch preconditioner, degree 2 (patch.hip).
+// Additive vertex-star patch preconditioner, degrees 2 and 3 (patch.hip).
+bool patch_supported(const HostLevel& H, std::string& why);
 size_t patch_bytes(const HostLevel& H, size_t ts);
 template <typename T>
 fem_status patch_setup(const fem_mesh& m, int level, const double* k, void* buf, hipStream_t s);

@@ -940,9 +940,13 @@ static fem_status check_opts(const fem_mesh* m, const fem_solve_opts* o) {
         set_error("solver: invalid options");
         return FEM_ERR_INVALID_ARG;
     }
-    if (o->smoother == FEM_SMOOTHER_PATCH && m->p != 2) {
-        set_error("solver: the star-patch smoother is built for degree 2 only");
-        return FEM_ERR_UNSUPPORTED;
+    if (o->smoother == FEM_SMOOTHER_PATCH) {
+        std::string why;
+        for (int l = 0; l < m->nlev; ++l)
+            if (!patch_supported(m->lev[l], why)) {
+                set_error("solver: star-patch smoother: " + why);
+                return FEM_ERR_UNSUPPORTED;
+            }
     }
     return FEM_OK;
 }

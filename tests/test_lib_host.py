@@ -147,15 +147,24 @@ def test_patch_buffer_bytes_and_degree_check():
         for dt, s in ((0, 8), (1, 4)):
             assert lib().fem_patch_bytes(m.handle, level, dt, C.byref(nb)) == FEM_OK
             assert nb.value == a256(120 * NV * s) + a256(15 * NV * s)
-    for p in (1, 3):
-        mp = fem.Mesh(2, 0, p, upload=False)
-        assert lib().fem_patch_bytes(mp.handle, 0, 0, C.byref(nb)) == FEM_ERR_UNSUPPORTED
+    m3 = fem.Mesh(3, 1, 3, upload=False)           # P3 stars: 2145 packed entries + 65 results
+    for level, n in ((0, 3), (1, 6)):
+        NV = (n + 1) ** 3
+        for dt, s in ((0, 8), (1, 4)):
+            assert lib().fem_patch_bytes(m3.handle, level, dt, C.byref(nb)) == FEM_OK
+            assert nb.value == a256(2145 * NV * s) + a256(65 * NV * s)
+    mp = fem.Mesh(2, 0, 1, upload=False)           # P1: every star is one dof (Jacobi)
+    assert lib().fem_patch_bytes(mp.handle, 0, 0, C.byref(nb)) == FEM_ERR_UNSUPPORTED
+    # the packed star index is 32-bit: (2145 + 65) * n_vertices must stay below 2^32, which P3
+    # at 128^3 cubes (2,146,689 vertices) exceeds
+    big = fem.Mesh(128, 0, 3, upload=False)
+    assert lib().fem_patch_bytes(big.handle, 0, 0, C.byref(nb)) == FEM_ERR_UNSUPPORTED
     assert lib().fem_patch_bytes(m.handle, 2, 0, C.byref(nb)) != FEM_OK
 
 
 def test_solver_workspace_with_patch_smoother():
     """The star-patch smoother adds, per smoothed level, the patch buffer (120 + 15 entries per
-    vertex) and one level vector; degrees other than 2 are refused."""
+    vertex for P2, 2145 + 65 for P3) and one level vector; degree 1 is refused."""
     import ctypes as C
     from paper_2104_08012_amd import fem
     from paper_2104_08012_amd import _lib as L
@@ -173,7 +182,13 @@ def test_solver_workspace_with_patch_smoother():
         assert st_j == 0 and st_p == 0
         extra = sum(135 * m.levels[l]["n_vertices"] * s + m.levels[l]["n_dofs"] * s for l in (1, 2))
         assert extra <= b_p - b_j <= extra + 6 * 256
-    for p in (1, 3):
-        mp = fem.Mesh(2, 1, p, upload=False)
-        st, _ = ws(mp, smoother="patch")
-        assert st == L.FEM_ERR_UNSUPPORTED
+    m3 = fem.Mesh(2, 2, 3, upload=False)
+    for prec, s in (("fp64", 8), ("mixed", 4)):
+        st_j, b_j = ws(m3, precision=prec)
+        st_p, b_p = ws(m3, precision=prec, smoother="patch")
+        assert st_j == 0 and st_p == 0
+        extra = sum(2210 * m3.levels[l]["n_vertices"] * s + m3.levels[l]["n_dofs"] * s for l in (1, 2))
+        assert extra <= b_p - b_j <= extra + 6 * 256
+    mp = fem.Mesh(2, 1, 1, upload=False)
+    st, _ = ws(mp, smoother="patch")
+    assert st == L.FEM_ERR_UNSUPPORTED
