@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(64) k_patch_local3(PatchGeom g, const T* __res
             ra[j] = j < nr ? rs[a0 + j][lane] : T(0);
             row[j] = (uint32_t)((a0 + j) * (a0 + j + 1) / 2);
         }
-#pragma unroll 2
+#pragma unroll 4
         for (int b = 0; b < a0; ++b) {
             const T rb = rs[b][lane];
             T sym = T(0);

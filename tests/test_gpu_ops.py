@@ -78,6 +78,37 @@ def test_apply_axpby_and_determinism(n):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("n,p,dtype", [(32, 2, "f64"), (32, 2, "f32"), (24, 2, "f64"), (32, 1, "f64"),
+                                       (64, 2, "f64")])
+def test_apply_repeated_launches_bitwise(n, p, dtype):
+    """Back-to-back actions on alternating inputs share the level's interface slots: 40 launches
+    without synchronisation (and the in-place axpby form y = z - A x) must each equal the first
+    launch on the same input bit for bit, and that one the oracle."""
+    banner(f"repeated launches n={n} p={p} {dtype}")
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    mesh, levels = make_pair(n, 0, p, 0.1 if n <= 32 else 0.0)
+    lev = levels[0]
+    xs = [_t(fem_inputs.uniform_vector(lev.n_dofs, s), dt) for s in (0, 1)]
+    ref = [mesh.apply(x) for x in xs]
+    torch.cuda.synchronize()
+    if n <= 32:
+        y0 = oracle_A(lev) @ fem_inputs.uniform_vector(lev.n_dofs, 0)
+        assert rel(ref[0].double().cpu().numpy(), y0) <= (1e-12 if dtype == "f64" else 2e-6)
+    outs = [torch.empty_like(xs[0]) for _ in range(40)]
+    for i, y in enumerate(outs):
+        mesh.apply(xs[i % 2], out=y)
+    zs = [x.clone() for x in xs]
+    for i in range(10):                      # r = z - A x in place, alternating inputs
+        zs[i % 2].copy_(xs[(i + 1) % 2])
+        mesh.apply(xs[i % 2], out=zs[i % 2], alpha=-1.0, z=zs[i % 2], beta=1.0)
+        torch.cuda.synchronize()
+        assert torch.equal(zs[i % 2], xs[(i + 1) % 2] - ref[i % 2]), i
+    torch.cuda.synchronize()
+    for i, y in enumerate(outs):
+        assert torch.equal(y, ref[i % 2]), i
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("n,p,jit", [(8, 2, 0.15), (6, 3, 0.0), (5, 1, 0.0)])
 def test_mass_parity(n, p, jit):
     banner(f"mass n={n} p={p}")
