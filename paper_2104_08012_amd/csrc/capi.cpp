@@ -95,17 +95,21 @@ fem_status fem_mesh_upload(fem_mesh* m, void* dev, size_t bytes, void* stream) {
         if (e == hipSuccess) e = put(T.d64, T.t64.data(), T.t64.size() * 8);
         if (e == hipSuccess) e = put(T.d32, T.t32.data(), T.t32.size() * 4);
     }
-    if (e == hipSuccess) e = put(m->d_fine_mi, m->fine_mi.data(), m->fine_mi.size() * 4);
-    if (e == hipSuccess) e = put(m->d_ploc64, m->ploc64.data(), m->ploc64.size() * 8);
-    if (e == hipSuccess) e = put(m->d_ploc32, m->ploc32.data(), m->ploc32.size() * 4);
     if (e == hipSuccess) e = put(m->d_mref64, m->mref64.data(), m->mref64.size() * 8);
     if (e == hipSuccess) e = put(m->d_mref32, m->mref32.data(), m->mref32.size() * 4);
+    if (e == hipSuccess) e = put(m->d_pt_off, m->pt_off.data(), m->pt_off.size() * 4);
+    if (e == hipSuccess) e = put(m->d_pt_w64, m->pt_w64.data(), m->pt_w64.size() * 8);
+    if (e == hipSuccess) e = put(m->d_pt_w32, m->pt_w32.data(), m->pt_w32.size() * 4);
+    if (e == hipSuccess) e = put(m->d_rs_start, m->rs_start.data(), m->rs_start.size() * 4);
+    if (e == hipSuccess) e = put(m->d_rs_off, m->rs_off.data(), m->rs_off.size() * 4);
+    if (e == hipSuccess) e = put(m->d_rs_w64, m->rs_w64.data(), m->rs_w64.size() * 8);
+    if (e == hipSuccess) e = put(m->d_rs_w32, m->rs_w32.data(), m->rs_w32.size() * 4);
     for (const auto& L : m->lev) {
         if (e == hipSuccess) e = put(L.d_map, L.map.data(), L.map.size() * 4);
         if (e == hipSuccess) e = put(L.d_G64, L.G64.data(), L.G64.size() * 8);
         if (e == hipSuccess) e = put(L.d_G32, L.G32.data(), L.G32.size() * 4);
-        if (e == hipSuccess) e = put(L.d_owner, L.owner.data(), L.owner.size() * 4);
         if (e == hipSuccess) e = put(L.d_vsoa, L.vsoa.data(), L.vsoa.size() * 8);
+        if (e == hipSuccess) e = put(L.d_rs_lin, L.rs_lin.data(), L.rs_lin.size() * 4);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -320,18 +324,8 @@ fem_status fem_restrict(const fem_mesh* m, int32_t fine_level, fem_dtype dtype, 
     FEM_REQUIRE(fine_level >= 1, FEM_ERR_INVALID_ARG, "fem_restrict: fine_level must be >= 1");
     FEM_REQUIRE(rf && rc && rf != rc, FEM_ERR_INVALID_ARG, "fem_restrict: NULL or aliased vectors");
     hipStream_t s = (hipStream_t)stream;
-    if (dtype == FEM_F64) {
-        ScatterIO<double> io;
-        io.x = (const double*)rf;
-        io.y = (double*)rc;
-        io.row_mode = ROW_ZERO;
-        return run_scatter<double>(*m, fine_level - 1, K_RESTRICT, false, io, s);
-    }
-    ScatterIO<float> io;
-    io.x = (const float*)rf;
-    io.y = (float*)rc;
-    io.row_mode = ROW_ZERO;
-    return run_scatter<float>(*m, fine_level - 1, K_RESTRICT, false, io, s);
+    if (dtype == FEM_F64) return run_restrict<double>(*m, fine_level, (const double*)rf, (double*)rc, s);
+    return run_restrict<float>(*m, fine_level, (const float*)rf, (float*)rc, s);
 }
 
 fem_status fem_adjoint_grad_k(const fem_mesh* m, int32_t level, const double* k, const double* u,

@@ -13,10 +13,6 @@ namespace fem {
 // Local dofs of Lagrange P_p on a tetrahedron: (p+1)(p+2)(p+3)/6.
 FEM_HD constexpr int nloc_of(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 
-// Points of the barycentric lattice {m : |m| = 2p}: the fine-mesh nodes inside one coarse cell
-// after one uniform refinement.
-FEM_HD constexpr int nfine_pts(int p) { return (2 * p + 1) * (2 * p + 2) * (2 * p + 3) / 6; }
-
 // Quadrature points per cell.  Stiffness with k = 1 has integrand degree 2p-2, with a P1
 // coefficient (and the adjoint gradient, which carries one P1 factor) degree 2p-1.
 //   degree <= 1: 1 point (centroid)   degree 2: 4 points   degree 3: 5 points
@@ -42,7 +38,7 @@ constexpr uint32_t kBoundaryBit = 0x80000000u;
 enum { G00 = 0, G11 = 1, G22 = 2, G01 = 3, G02 = 4, G12 = 5 };
 
 // Cell-wise operations that scatter-add into shared dofs.
-enum Kind : int { K_APPLY = 0, K_DIAG = 1, K_MASS = 2, K_RESTRICT = 3, K_GRAD = 4 };
+enum Kind : int { K_APPLY = 0, K_DIAG = 1, K_MASS = 2, K_GRAD = 4 };
 
 // Row treatment of boundary dofs in scatter kernels.
 enum RowMode : int { ROW_NONE = 0, ROW_IDENTITY = 1, ROW_ZERO = 2, ROW_ONE = 3 };

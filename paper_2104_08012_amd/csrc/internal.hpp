@@ -23,7 +23,6 @@ void eval_basis_grad(int p, const double xi[3], double* phi, double* dphi);
 void mass_matrix(int p, std::vector<double>& M);
 const Rule& rule_for_degree(int degree);
 double rule_exactness_error(int degree);
-void fine_points(int p, std::vector<std::array<int, 4>>& pts);
 
 // ---------------- error reporting (capi.cpp) ----------------
 void set_error(const std::string& msg);
@@ -57,15 +56,15 @@ struct HostLevel {
     std::vector<int32_t> map;      // SoA nloc * C, sign bit = boundary dof
     std::vector<double> G64;       // SoA 6 * C
     std::vector<float> G32;
-    std::vector<uint32_t> owner;   // SoA nwords * C: fine points owned by this (coarse) cell
-    int nwords = 0;
     // Cube-kernel data (P1/P2 on 4-cube bricks, whose dofs are addressed by their lattice point):
     // the vertex coordinates SoA (x[NV], y[NV], z[NV]) in FP64.
     bool cube = false;
     std::vector<double> vsoa;
     int red = -1, red1 = -1;       // reduction tables for degree p and for degree 1 output
     int64_t slot_elems = 0;        // interface partial slots (max over the tables used)
-    size_t d_map = 0, d_G64 = 0, d_G32 = 0, d_slots = 0, d_owner = 0, d_vsoa = 0;
+    std::vector<int32_t> rs_lin;   // restriction onto this level: stencil offsets as linear offsets
+                                   // on the next finer level's lattice (entry order of rs_off)
+    size_t d_map = 0, d_G64 = 0, d_G32 = 0, d_slots = 0, d_vsoa = 0, d_rs_lin = 0;
 };
 
 }  // namespace fem
@@ -76,13 +75,16 @@ struct fem_mesh {
     std::vector<fem::HostLevel> lev;
     std::vector<fem::RedTable> red;
     fem::Tabulation tab[2];          // [kvar]
-    int npts = 0;                    // fine points per coarse cell
-    std::vector<int32_t> fine_mi;    // npts * 4
-    std::vector<double> ploc64;      // npts * nloc
-    std::vector<float> ploc32;
     std::vector<double> mref64;      // nloc * nloc
     std::vector<float> mref32;
-    size_t d_fine_mi = 0, d_ploc64 = 0, d_ploc32 = 0, d_mref64 = 0, d_mref32 = 0;
+    size_t d_mref64 = 0, d_mref32 = 0;
+    // lattice transfers (transfer.cpp): prolongation weights per local fine position (pt_ne
+    // entries each: packed node offset, weight) and restriction stencils per residue class
+    int pt_ne = 0;
+    std::vector<int32_t> pt_off, rs_start, rs_off;
+    std::vector<double> pt_w64, rs_w64;
+    std::vector<float> pt_w32, rs_w32;
+    size_t d_pt_off = 0, d_pt_w64 = 0, d_pt_w32 = 0, d_rs_start = 0, d_rs_off = 0, d_rs_w64 = 0, d_rs_w32 = 0;
     size_t bytes = 0;
     char* dev = nullptr;
     int device = -1;
@@ -90,4 +92,5 @@ struct fem_mesh {
 
 namespace fem {
 fem_status build_mesh(const fem_mesh_desc& d, fem_mesh& m);
+void build_transfer_tables(fem_mesh& m);
 }

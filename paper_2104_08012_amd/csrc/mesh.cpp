@@ -202,32 +202,6 @@ static void validate_level(const HostLevel& L, const RedTable& t) {
     }
 }
 
-// Fine points of one uniform refinement owned by each coarse cell: the first coarse cell (in
-// cell order) whose closure contains the point owns it.
-static void build_owner(HostLevel& Lc, const HostLevel& Lf, const std::vector<std::array<int, 4>>& pts) {
-    const int np = (int)pts.size();
-    Lc.nwords = (np + 31) / 32;
-    Lc.owner.assign((size_t)Lc.nwords * Lc.C, 0u);
-    std::vector<uint8_t> claimed((size_t)Lf.N, 0);
-    const int64_t Lfl = Lf.L;
-    for (int64_t c = 0; c < Lc.C; ++c) {
-        int V[4][3];
-        cell_vertices(Lc, c, V);
-        for (int m = 0; m < np; ++m) {
-            int X[3] = {0, 0, 0};
-            for (int v = 0; v < 4; ++v)
-                for (int k = 0; k < 3; ++k) X[k] += pts[m][v] * V[v][k];
-            const int64_t g = X[0] + Lfl * (X[1] + Lfl * X[2]);
-            if (!claimed[g]) {
-                claimed[g] = 1;
-                Lc.owner[(size_t)(m / 32) * Lc.C + c] |= 1u << (m % 32);
-            }
-        }
-    }
-    for (int64_t g = 0; g < Lf.N; ++g)
-        if (!claimed[g]) throw std::runtime_error("fine dof not covered by any coarse cell");
-}
-
 static void build_tab(Tabulation& T, int p, int kvar) {
     const Rule& r = rule_for_degree(kvar ? 2 * p - 1 : 2 * p - 2);
     const int nl = nloc_of(p);
@@ -302,23 +276,8 @@ fem_status build_mesh(const fem_mesh_desc& d, fem_mesh& m) {
         };
         L.slot_elems = 8 * std::max(iface(p), iface(1));
     }
-    std::vector<std::array<int, 4>> pts;
-    fine_points(p, pts);
-    m.npts = (int)pts.size();
-    for (int l = 0; l + 1 < m.nlev; ++l) build_owner(m.lev[l], m.lev[l + 1], pts);
     for (int kv = 0; kv < 2; ++kv) build_tab(m.tab[kv], p, kv);
-    // prolongation table: coarse basis at the fine points m / (2p)
-    const int nl = nloc_of(p);
-    m.fine_mi.resize((size_t)m.npts * 4);
-    m.ploc64.resize((size_t)m.npts * nl);
-    for (int q = 0; q < m.npts; ++q) {
-        for (int v = 0; v < 4; ++v) m.fine_mi[4 * q + v] = pts[q][v];
-        const double xi[3] = {pts[q][1] / (2.0 * p), pts[q][2] / (2.0 * p), pts[q][3] / (2.0 * p)};
-        eval_basis_grad(p, xi, &m.ploc64[(size_t)q * nl], nullptr);
-        for (int j = 0; j < nl; ++j)  // exact zeros / ones where the basis is at a node or a zero set
-            if (std::fabs(m.ploc64[(size_t)q * nl + j]) < 1e-15) m.ploc64[(size_t)q * nl + j] = 0.0;
-    }
-    m.ploc32.assign(m.ploc64.begin(), m.ploc64.end());
+    build_transfer_tables(m);
     mass_matrix(p, m.mref64);
     m.mref32.assign(m.mref64.begin(), m.mref64.end());
 
@@ -333,18 +292,22 @@ fem_status build_mesh(const fem_mesh_desc& d, fem_mesh& m) {
         T.d64 = take(T.t64.size() * 8);
         T.d32 = take(T.t32.size() * 4);
     }
-    m.d_fine_mi = take(m.fine_mi.size() * 4);
-    m.d_ploc64 = take(m.ploc64.size() * 8);
-    m.d_ploc32 = take(m.ploc32.size() * 4);
     m.d_mref64 = take(m.mref64.size() * 8);
     m.d_mref32 = take(m.mref32.size() * 4);
+    m.d_pt_off = take(m.pt_off.size() * 4);
+    m.d_pt_w64 = take(m.pt_w64.size() * 8);
+    m.d_pt_w32 = take(m.pt_w32.size() * 4);
+    m.d_rs_start = take(m.rs_start.size() * 4);
+    m.d_rs_off = take(m.rs_off.size() * 4);
+    m.d_rs_w64 = take(m.rs_w64.size() * 8);
+    m.d_rs_w32 = take(m.rs_w32.size() * 4);
     for (auto& L : m.lev) {
         L.d_map = take(L.map.size() * 4);
         L.d_G64 = take(L.G64.size() * 8);
         L.d_G32 = take(L.G32.size() * 4);
         L.d_slots = take((size_t)L.slot_elems * 8);
-        L.d_owner = take(L.owner.size() * 4);
         L.d_vsoa = take(L.vsoa.size() * 8);
+        L.d_rs_lin = take(L.rs_lin.size() * 4);
     }
     m.bytes = off;
     return FEM_OK;

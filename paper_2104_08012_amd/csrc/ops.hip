@@ -121,8 +121,6 @@ size_t G_off<float>(const HostLevel& L) { return L.d_G32; }
 
 template <typename T>
 size_t mref_off(const fem_mesh& m) { return sizeof(T) == 8 ? m.d_mref64 : m.d_mref32; }
-template <typename T>
-size_t ploc_off(const fem_mesh& m) { return sizeof(T) == 8 ? m.d_ploc64 : m.d_ploc32; }
 
 template <int KIND, typename T>
 fem_status run_kind(const fem_mesh& m, int level, bool kvar, const ScatterIO<T>& io, hipStream_t s) {
@@ -137,12 +135,9 @@ fem_status run_kind(const fem_mesh& m, int level, bool kvar, const ScatterIO<T>&
     a.map = dptr<int32_t>(m, L.d_map);
     a.G = dptr<T>(m, G_off<T>(L));
     a.tab = tab_ptr<T>(m, (KIND == K_GRAD) ? 1 : (kvar ? 1 : 0));
-    a.aux = (KIND == K_MASS) ? dptr<T>(m, mref_off<T>(m)) : (KIND == K_RESTRICT) ? dptr<T>(m, ploc_off<T>(m)) : nullptr;
-    a.fine_mi = dptr<int32_t>(m, m.d_fine_mi);
-    a.owner = (KIND == K_RESTRICT) ? dptr<uint32_t>(m, L.d_owner) : nullptr;
+    a.aux = (KIND == K_MASS) ? dptr<T>(m, mref_off<T>(m)) : nullptr;
     a.slots = io.slots ? static_cast<T*>(io.slots) : const_cast<T*>(dptr<T>(m, L.d_slots));
     a.mask_cols = io.mask_cols;
-    a.Lin = (KIND == K_RESTRICT) ? m.lev[level + 1].L : 0;
     a.x = io.x;
     a.x2 = io.x2;
     a.k = io.k;
@@ -192,7 +187,6 @@ fem_status run_scatter(const fem_mesh& m, int level, int kind, bool kvar, const 
         case K_APPLY: return run_kind<K_APPLY, T>(m, level, kvar, io, s);
         case K_DIAG: return run_kind<K_DIAG, T>(m, level, kvar, io, s);
         case K_MASS: return run_kind<K_MASS, T>(m, level, false, io, s);
-        case K_RESTRICT: return run_kind<K_RESTRICT, T>(m, level, false, io, s);
         case K_GRAD:
             if constexpr (sizeof(T) == 8) return run_kind<K_GRAD, T>(m, level, false, io, s);
             break;
@@ -204,39 +198,6 @@ fem_status run_scatter(const fem_mesh& m, int level, int kind, bool kvar, const 
 
 template fem_status run_scatter<double>(const fem_mesh&, int, int, bool, const ScatterIO<double>&, hipStream_t);
 template fem_status run_scatter<float>(const fem_mesh&, int, int, bool, const ScatterIO<float>&, hipStream_t);
-
-namespace {
-template <typename T, int P>
-void launch_prolong_b(int B, const PArgs<T>& a, hipStream_t s) {
-    const unsigned grid = (unsigned)((a.C + 255) / 256);
-    if (B == 4) hipLaunchKernelGGL((k_prolong<P, 4, T>), dim3(grid), dim3(256), 0, s, a);
-    else if (B == 2) hipLaunchKernelGGL((k_prolong<P, 2, T>), dim3(grid), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_prolong<P, 1, T>), dim3(grid), dim3(256), 0, s, a);
-}
-}  // namespace
-
-template <typename T>
-fem_status run_prolong(const fem_mesh& m, int fine_level, const T* xc, T* xf, hipStream_t s) {
-    const HostLevel& Lc = m.lev[fine_level - 1];
-    PArgs<T> a{};
-    a.n = Lc.n;
-    a.nb = Lc.nb;
-    a.Lf = m.lev[fine_level].L;
-    a.C = Lc.C;
-    a.map = dptr<int32_t>(m, Lc.d_map);
-    a.owner = dptr<uint32_t>(m, Lc.d_owner);
-    a.fine_mi = dptr<int32_t>(m, m.d_fine_mi);
-    a.ploc = dptr<T>(m, ploc_off<T>(m));
-    a.xc = xc;
-    a.xf = xf;
-    if (m.p == 1) launch_prolong_b<T, 1>(Lc.B, a, s);
-    else if (m.p == 2) launch_prolong_b<T, 2>(Lc.B, a, s);
-    else launch_prolong_b<T, 3>(Lc.B, a, s);
-    return check_launch("prolongation kernel");
-}
-
-template fem_status run_prolong<double>(const fem_mesh&, int, const double*, double*, hipStream_t);
-template fem_status run_prolong<float>(const fem_mesh&, int, const float*, float*, hipStream_t);
 
 fem_status check_launch(const char* what) {
     const hipError_t e = hipGetLastError();

@@ -28,12 +28,16 @@ struct ScatterIO {
     size_t slots_bytes = 0;
 };
 
-// kind: K_APPLY, K_DIAG, K_MASS, K_RESTRICT (level = coarse level), K_GRAD (T = double).
+// kind: K_APPLY, K_DIAG, K_MASS, K_GRAD (T = double).
 template <typename T>
 fem_status run_scatter(const fem_mesh& m, int level, int kind, bool kvar, const ScatterIO<T>& io, hipStream_t s);
 
+// Lattice transfers between fine_level - 1 and fine_level (transfer.hip): x_f += P x_c, and
+// r_c = P^T r_f with boundary rows zero.
 template <typename T>
 fem_status run_prolong(const fem_mesh& m, int fine_level, const T* xc, T* xf, hipStream_t s);
+template <typename T>
+fem_status run_restrict(const fem_mesh& m, int fine_level, const T* rf, T* rc, hipStream_t s);
 
 fem_status check_launch(const char* what);
 

@@ -1,6 +1,6 @@
-// Reference tetrahedron for Lagrange P1-P3: basis, gradients, quadrature rules, mass matrix and
-// the prolongation table of one uniform refinement.  Host code; the results are uploaded as
-// tables that the kernels read with uniform (scalar) loads.
+// Reference tetrahedron for Lagrange P1-P3: basis, gradients, quadrature rules and mass matrix.
+// Host code; the results are uploaded as tables that the kernels read with uniform (scalar)
+// loads.
 //
 // Element: continuous Lagrange elements of degree p on the reference tetrahedron with vertices
 // (0,0,0), (1,0,0), (0,1,0), (0,0,1) (paper Section 2, Listing 1: FunctionSpace "CG").  Nodes are
@@ -308,14 +308,6 @@ const Rule& rule_for_degree(int degree) {
 double rule_exactness_error(int degree) {
     const Rule& r = rule_for_degree(degree);
     return moment_error(r, degree, nullptr);
-}
-
-void fine_points(int p, std::vector<std::array<int, 4>>& pts) {
-    pts.clear();
-    const int q = 2 * p;
-    for (int m3 = 0; m3 <= q; ++m3)
-        for (int m2 = 0; m2 + m3 <= q; ++m2)
-            for (int m1 = 0; m1 + m2 + m3 <= q; ++m1) pts.push_back({q - m1 - m2 - m3, m1, m2, m3});
 }
 
 }  // namespace fem

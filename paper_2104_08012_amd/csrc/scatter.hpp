@@ -40,13 +40,10 @@ struct SArgs {
     const int32_t* map;              // SoA nloc * C (sign bit: boundary dof)
     const T* G;                      // SoA 6 * C
     const T* tab;                    // stiffness tabulation: per point w, lambda[4], D[3][nloc]
-    const T* aux;                    // mass: M_ref (nloc^2); restriction: P_loc (npts * nloc)
-    const int32_t* fine_mi;          // restriction: barycentric multi-index of each fine point
-    const uint32_t* owner;           // restriction: SoA owner masks of the coarse cells
+    const T* aux;                    // mass: M_ref (nloc^2)
     T* slots;                        // interface partials: 8 arrays (side code) x if_tot points
     uint32_t if_c0, if_c01, if_tot;  // interface points on x planes; + y planes; + z planes
     int mask_cols;                   // gather boundary dofs as zero
-    int Lin;                         // restriction: fine lattice size
     const T* x;                      // input field (u for the gradient)
     const T* x2;                     // second input (lambda for the gradient)
     const T* k;                      // P1 coefficient on the vertex lattice, or null
@@ -229,36 +226,6 @@ struct Producer<K_MASS, P, B, KVAR, T> {
 #pragma unroll
             for (int j = 0; j < NL; ++j) s += a.aux[i * NL + j] * xs[j];
             out[i] = det * s;
-        }
-    }
-};
-
-// Restriction, per coarse cell: r_K[j] = sum over the fine points m owned by K of
-// P_loc[m][j] r_f[fine dof of m].
-template <int P, int B, bool KVAR, typename T>
-struct Producer<K_RESTRICT, P, B, KVAR, T> {
-    static constexpr int NL = nloc_of(P), NP = nfine_pts(P), NW = (NP + 31) / 32;
-    __device__ __forceinline__ static void run(const SArgs<T>& a, int64_t c, int cl, int bx, int by, int bz,
-                                               T* out) {
-        int V[4][3];
-        cell_vertices<B>(bx, by, bz, cl, V);
-        uint32_t w[NW];
-#pragma unroll
-        for (int i = 0; i < NW; ++i) w[i] = soa(a.owner, i, a.C, c);
-#pragma unroll
-        for (int j = 0; j < NL; ++j) out[j] = T(0);
-        const int64_t Lf = a.Lin;
-#pragma unroll
-        for (int m = 0; m < NP; ++m) {
-            if ((w[m >> 5] >> (m & 31)) & 1u) {
-                const int* mi = a.fine_mi + 4 * m;
-                const int X = mi[0] * V[0][0] + mi[1] * V[1][0] + mi[2] * V[2][0] + mi[3] * V[3][0];
-                const int Y = mi[0] * V[0][1] + mi[1] * V[1][1] + mi[2] * V[2][1] + mi[3] * V[3][1];
-                const int Z = mi[0] * V[0][2] + mi[1] * V[1][2] + mi[2] * V[2][2] + mi[3] * V[3][2];
-                const T r = a.x[X + Lf * (Y + Lf * Z)];
-#pragma unroll
-                for (int j = 0; j < NL; ++j) out[j] += a.aux[m * NL + j] * r;
-            }
         }
     }
 };
@@ -457,51 +424,6 @@ __global__ void __launch_bounds__(256) k_fixup(SArgs<T> a, FixGeom fg) {
     T r = a.alpha * acc;
     if (a.beta != T(0)) r += a.beta * zv;
     stg(a.y, g, r);
-}
-
-// Prolongation, one thread per coarse cell: x_f[fine dof of m] += sum_j P_loc[m][j] x_c[map_j]
-// for the fine points m this coarse cell owns (each fine dof has exactly one owner).
-template <typename T>
-struct PArgs {
-    int n, nb, Lf;
-    int64_t C;
-    const int32_t* map;
-    const uint32_t* owner;
-    const int32_t* fine_mi;
-    const T* ploc;
-    const T* xc;
-    T* xf;
-};
-
-template <int P, int B, typename T>
-__global__ void __launch_bounds__(256) k_prolong(PArgs<T> a) {
-    constexpr int NL = nloc_of(P), NP = nfine_pts(P), NW = (NP + 31) / 32, NC = 6 * B * B * B;
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= a.C) return;
-    const int brick = (int)(c / NC), cl = (int)(c % NC);
-    const int nb = a.nb;
-    int V[4][3];
-    cell_vertices<B>(brick % nb, (brick / nb) % nb, brick / (nb * nb), cl, V);
-    T e[NL];
-#pragma unroll
-    for (int j = 0; j < NL; ++j) e[j] = gather(a.xc, soa(a.map, j, a.C, c), 0);
-    uint32_t w[NW];
-#pragma unroll
-    for (int i = 0; i < NW; ++i) w[i] = soa(a.owner, i, a.C, c);
-    const int64_t Lf = a.Lf;
-#pragma unroll
-    for (int m = 0; m < NP; ++m) {
-        if ((w[m >> 5] >> (m & 31)) & 1u) {
-            const int* mi = a.fine_mi + 4 * m;
-            const int X = mi[0] * V[0][0] + mi[1] * V[1][0] + mi[2] * V[2][0] + mi[3] * V[3][0];
-            const int Y = mi[0] * V[0][1] + mi[1] * V[1][1] + mi[2] * V[2][1] + mi[3] * V[3][1];
-            const int Z = mi[0] * V[0][2] + mi[1] * V[1][2] + mi[2] * V[2][2] + mi[3] * V[3][2];
-            T s = T(0);
-#pragma unroll
-            for (int j = 0; j < NL; ++j) s += a.ploc[m * NL + j] * e[j];
-            a.xf[X + Lf * (Y + Lf * Z)] += s;
-        }
-    }
 }
 
 }  // namespace fem

@@ -451,13 +451,7 @@ fem_status fem_solver::vcycle(int l, const T* b, T* x) {
     // coarse-grid correction
     T* bc = p<T>(L.lev[l - 1].b);
     T* xc = p<T>(L.lev[l - 1].x);
-    {
-        ScatterIO<T> io;
-        io.x = r;
-        io.y = bc;
-        io.row_mode = ROW_ZERO;
-        FEM_TRY(run_scatter<T>(*m, l - 1, K_RESTRICT, false, io, s));
-    }
+    FEM_TRY(run_restrict<T>(*m, l, r, bc, s));
     if (timing) ignore(hipEventRecord(e[1], s));
     FEM_TRY(vcycle<T>(l - 1, bc, xc));
     if (timing) ignore(hipEventRecord(e[2], s));
@@ -866,11 +860,7 @@ fem_status fem_solver::fmg(const double* b, double* x, double& rel_true) {
     auto fb = [&](int l) -> double* { return l == hi ? const_cast<double*>(b) : p<double>(L.lev[l].fb); };
     auto fx = [&](int l) -> double* { return l == hi ? x : p<double>(L.lev[l].fx); };
     for (int l = hi; l > lo; --l) {
-        ScatterIO<double> io;
-        io.x = fb(l);
-        io.y = fb(l - 1);
-        io.row_mode = ROW_ZERO;
-        FEM_TRY(run_scatter<double>(*m, l - 1, K_RESTRICT, false, io, s));
+        FEM_TRY(run_restrict<double>(*m, l, fb(l), fb(l - 1), s));
     }
     FEM_TRY(coarse_solve(fb(lo), fx(lo)));                    // FP64 in both precisions
     for (int l = lo + 1; l <= hi; ++l) {
