@@ -29,11 +29,14 @@ and the oracle timed on the host ("cpu", also --no-cpu-baseline).
 value = operator-action GDoF/s of step 1: n_dofs / (mean cold duration of the action, from HIP
 events recorded on the stream the action's kernels run on, over the timed steps).  The action is
 two launches (the cube kernel and the interface fix-up), bracketed together.  Algorithmic bytes
-of one action:
-  P1/P2 on 4-cube bricks (geometry from vertex coordinates, dofs addressed by lattice point):
-      B = 2 N s + 24 N_v (+ N_v s for a P1 coefficient)
-  otherwise (stored per-cell factors): B = 2 N s + 4 C nloc + 6 C s (+ N_v s)
-(x read and y written once, int32 dof indices, FP64 vertex coordinates or per-cell factors).
+of one action, by where the level takes its geometry (the mesh reports it per level):
+  table (P1/P2 on 4-cube bricks of a refined level, G from the coarsest level's table):
+      B = 2 N s + 1728 n0^3 (+ N_v s for a P1 coefficient)
+  vertex (P1/P2 on 4-cube bricks, G from the vertex coordinates):
+      B = 2 N s + 24 N_v (+ N_v s)
+  cell (stored per-cell factors and dof map): B = 2 N s + 4 C nloc + 6 C s (+ N_v s)
+(x read and y written once, dofs addressed by lattice point on 4-cube bricks, else int32 dof
+indices; the table holds 36 x 6 FP64 values per coarsest cube.)
 Algorithmic flops: (12 nq nloc + 20 nq) per cell, the tabulated-gradient contraction.  roofline
 reports the binding roof: the larger of bytes / 8 TB/s and flops / vector peak (FP64 78.6,
 FP32 157.3 TFLOP/s), as a fraction of the measured time.
@@ -58,6 +61,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -132,21 +136,24 @@ def traffic_from_profiles(key):
     return e.get("traffic_bytes")
 
 
-def action_bytes(p, n, C, N, NV, s, kvar):
-    """Algorithmic bytes of one action for the layout the library uses at this size: for the cube
-    kernel (P1/P2 on 4-cube bricks, dofs addressed by lattice point) x and y once, the FP64 vertex
-    coordinates and the vertex coefficient; otherwise also the cell-to-dof map and the geometric
-    factors of every cell."""
-    if p <= 2 and n % 4 == 0:
-        return 2 * N * s + 24 * NV + (NV * s if kvar else 0)
+def action_bytes(p, C, N, NV, s, kvar, geometry, n0):
+    """Algorithmic bytes of one action for the layout the library uses on the level: x and y once
+    and the vertex coefficient, plus the geometry the kernel reads (the coarsest level's table, the
+    FP64 vertex coordinates, or the cell-to-dof map and the per-cell factors)."""
+    kv = NV * s if kvar else 0
+    if geometry == "table":
+        return 2 * N * s + 36 * 6 * 8 * n0 ** 3 + kv
+    if geometry == "vertex":
+        return 2 * N * s + 24 * NV + kv
     return balg_bytes(C, N, nloc_of(p), s, NV if kvar else 0)
 
 
-def roofline(p, kvar, C, N, NV, s, t, key):
-    """Roofline entry of the action: the binding roof of bytes / 8 TB/s and flops / vector peak,
-    with the measured fraction of it."""
-    n = round((C / 6) ** (1 / 3))
-    B = action_bytes(p, n, C, N, NV, s, kvar)
+def roofline(p, kvar, mesh, s, t, key):
+    """Roofline entry of the action on the mesh's finest level: the binding roof of bytes / 8 TB/s
+    and flops / vector peak, with the measured fraction of it."""
+    info = mesh.levels[-1]
+    C, N, NV, geometry = info["n_cells"], info["n_dofs"], info["n_vertices"], info["geometry"]
+    B = action_bytes(p, C, N, NV, s, kvar, geometry, mesh.levels[0]["n"])
     gbs = B / t / 1e9
     out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(key),
@@ -162,8 +169,8 @@ def roofline(p, kvar, C, N, NV, s, t, key):
         out["alu_frac"] = round(tf / peak, 4)
     # what was timed: one action = the cell kernel and the fix-up, bracketed together by HIP
     # events on the library's stream (the kernel trace in profiles/ lists the two separately)
-    cube = p <= 2 and n % 4 == 0
-    out["kernels"] = ("k_cube_apply + k_fixup" if cube else "k_brick + k_fixup") + " (one action)"
+    out["kernels"] = ("k_brick + k_fixup" if geometry == "cell" else "k_cube_apply + k_fixup") + " (one action)"
+    out["geometry"] = geometry
     out["duration_us"] = round(t * 1e6, 2)
     return out
 
@@ -415,14 +422,14 @@ def run_solve(args, name, w):
         "cells": C, "dofs": N, "degree": p, "levels": mesh.n_levels, "levels_in_outer_cycle": used or mesh.n_levels,
         "coefficient": "P1 exp(g)" if kvar else "1"}, wall)
     out["value"] = round(N / ta64 / 1e9, 3)
-    out["roofline"] = roofline(p, kvar, C, N, NV, 8, ta64, key + "_f64")
+    out["roofline"] = roofline(p, kvar, mesh, 8, ta64, key + "_f64")
     m64, mmx = mean(rec["solve64"]), mean(rec["solvemx"])
     u64, umx, r64, rmx = last["u64"], last["umx"], last["r64"], last["rmx"]
     out.update({
         "apply_us_fp64_cold": stats_us(rec["apply64"]), "apply_us_fp64_hot": stats_us(rec["apply64_hot"]),
         "apply_us_fp32_cold": stats_us(rec["apply32"]), "apply_us_fp32_hot": stats_us(rec["apply32_hot"]),
         "apply_fp32_gdofs": round(N / ta32 / 1e9, 3),
-        "apply_fp32_roofline": roofline(p, kvar, C, N, NV, 4, ta32, key + "_f32"),
+        "apply_fp32_roofline": roofline(p, kvar, mesh, 4, ta32, key + "_f32"),
         "timing_note": ("action: HIP events on the library's stream; cold = Infinity Cache flushed by a 2 GiB "
                         "read first, hot = back-to-back repeats; solves: host wall clock, first enqueue to "
                         "return, x0 = 0, setup excluded"),
@@ -539,11 +546,17 @@ def patch_section(torch, fem, tm, flush, mesh, k64, x64, x32, y64, y32, b, w, us
 
 
 def sweep_rows(torch, fem, fem_inputs, flush, n, reps):
-    """The action alone, k = 1, on n^3 x 6 tetrahedra: P1/P2/P3 x FP64/FP32, cold (Infinity Cache
-    flushed before each) and hot (back to back)."""
+    """The action alone, k = 1, on n^3 x 6 tetrahedra: P1/P2/P3 x FP64/FP32 on the finest level of
+    the hierarchy refined from 4^3 (P1/P2: geometry from the coarsest level's table), and P2 on a
+    single-level n^3 mesh (geometry from the vertex coordinates); cold (Infinity Cache flushed
+    before each) and hot (back to back)."""
     rows = []
-    for p in (1, 2, 3):
-        mesh = fem.Mesh(n, 0, p, device="cuda:0")
+    r = max(0, round(math.log2(n / 4)))
+    hier = 4 * 2 ** r == n
+    for p, single in ((1, False), (2, False), (2, True), (3, False)):
+        if single and not hier:
+            continue
+        mesh = fem.Mesh(n, 0, p, device="cuda:0") if single or not hier else fem.Mesh(4, r, p, device="cuda:0")
         info = mesh.levels[-1]
         N, C, NV = info["n_dofs"], info["n_cells"], info["n_vertices"]
         for dt, s in ((torch.float64, 8), (torch.float32, 4)):
@@ -564,10 +577,11 @@ def sweep_rows(torch, fem, fem_inputs, flush, n, reps):
                 tm.collect()
             t = mean(rec["cold"])
             tag = "f64" if s == 8 else "f32"
-            rows.append({"degree": p, "dtype": tag, "dofs": N, "cells": C,
+            rows.append({"degree": p, "dtype": tag, "dofs": N, "cells": C, "geometry": info["geometry"],
+                         "mesh": f"{mesh.levels[0]['n']}^3 refined {mesh.n_levels - 1}x",
                          "us_cold": stats_us(rec["cold"]), "us_hot": stats_us(rec["hot"]),
                          "gdofs_cold": round(N / t / 1e9, 3), "gdofs_hot": round(N / mean(rec["hot"]) / 1e9, 3),
-                         "roofline": roofline(p, False, C, N, NV, s, t, f"P{p}_n{n}_{tag}")})
+                         "roofline": roofline(p, False, mesh, s, t, f"P{p}_n{n}_{tag}_{info['geometry']}")})
             del x, y
         del mesh
         torch.cuda.empty_cache()
@@ -597,8 +611,8 @@ def solve_extra(torch, fem, fem_inputs, np, flush, w):
            "apply_gdofs_fp64_cold": round(N / mean(rec["apply64"]) / 1e9, 3),
            "apply_us_fp64_cold": stats_us(rec["apply64"]), "apply_us_fp64_hot": stats_us(rec["apply64_hot"]),
            "apply_us_fp32_cold": stats_us(rec["apply32"]), "apply_us_fp32_hot": stats_us(rec["apply32_hot"]),
-           "roofline_fp64": roofline(p, False, C, N, NV, 8, mean(rec["apply64"]), f"P{p}_n{info['n']}_f64"),
-           "roofline_fp32": roofline(p, False, C, N, NV, 4, mean(rec["apply32"]), f"P{p}_n{info['n']}_f32")}
+           "roofline_fp64": roofline(p, False, mesh, 8, mean(rec["apply64"]), f"P{p}_n{info['n']}_f64"),
+           "roofline_fp32": roofline(p, False, mesh, 4, mean(rec["apply32"]), f"P{p}_n{info['n']}_f32")}
     del x64, x32, y64, y32
     sols = {}
     for tag, prec, cm in (("fp64", "fp64", "auto"), ("mixed", "mixed", "auto"),
@@ -692,7 +706,7 @@ def run_adjoint(args, name, w):
                         "seeded k_ref + 1% noise; forward + adjoint MG-CG (1e-10) + dJ/dk kernel, FP64"),
         "cells": C, "dofs": N, "degree": p, "levels": mesh.n_levels, "vertices": NV}, wall)
     out["value"] = round(N / ta / 1e9, 3)
-    out["roofline"] = roofline(p, True, C, N, NV, 8, ta, f"P{p}k_n{info['n']}_f64")
+    out["roofline"] = roofline(p, True, mesh, 8, ta, f"P{p}k_n{info['n']}_f64")
     tg = mean(rec["grad"])
     gbytes = C * nloc_of(p) * 4 + 2 * N * 8 + NV * 8 + C * 6 * 8
     out.update({"J_plus_gradJ_ms": round(mean(rec["jgrad"]) * 1e3, 3),

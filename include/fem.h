@@ -72,10 +72,20 @@ typedef struct {
                                read only when FEM_MESH_JITTER is set; boundary rows ignored */
 } fem_mesh_desc;
 
+/* Where the stiffness action of a level takes its geometry from (fem_level_info.geometry). */
+enum {
+    FEM_GEOM_CELL = 0,    /* per-cell factors G stored for every cell (P3, bricks below 4 cubes) */
+    FEM_GEOM_VERTEX = 1,  /* the vertex coordinates, G formed in the kernel (P1/P2, 4-cube bricks) */
+    FEM_GEOM_TABLE = 2    /* the coarsest level's table of G per (coarsest cell, tetrahedron type),
+                             scaled by 2^-level: P1/P2 levels whose 4-cube bricks each lie in one
+                             coarsest cube, coarsest mesh of at most 24^3 cubes.  Every level is a
+                             uniform refinement of the coarsest, affine on each coarsest cell. */
+};
+
 typedef struct {
     int64_t n_cells, n_dofs, n_interior, n_vertices;
     int32_t n, degree, brick;   /* cubes per direction, degree, cubes per brick edge */
-    int32_t pad;
+    int32_t geometry;           /* FEM_GEOM_* of the stiffness action on this level */
 } fem_level_info;
 
 typedef struct fem_mesh fem_mesh;

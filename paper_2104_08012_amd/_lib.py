@@ -46,7 +46,7 @@ class MeshDesc(C.Structure):
 class LevelInfo(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_dofs", C.c_int64), ("n_interior", C.c_int64),
                 ("n_vertices", C.c_int64), ("n", C.c_int32), ("degree", C.c_int32),
-                ("brick", C.c_int32), ("pad", C.c_int32)]
+                ("brick", C.c_int32), ("geometry", C.c_int32)]
 
 
 class SolveOpts(C.Structure):

@@ -97,6 +97,7 @@ fem_status fem_mesh_upload(fem_mesh* m, void* dev, size_t bytes, void* stream) {
     }
     if (e == hipSuccess) e = put(m->d_mref64, m->mref64.data(), m->mref64.size() * 8);
     if (e == hipSuccess) e = put(m->d_mref32, m->mref32.data(), m->mref32.size() * 4);
+    if (e == hipSuccess) e = put(m->d_geo, m->geo.data(), m->geo.size() * 8);
     if (e == hipSuccess) e = put(m->d_pt_off, m->pt_off.data(), m->pt_off.size() * 4);
     if (e == hipSuccess) e = put(m->d_pt_w64, m->pt_w64.data(), m->pt_w64.size() * 8);
     if (e == hipSuccess) e = put(m->d_pt_w32, m->pt_w32.data(), m->pt_w32.size() * 4);
@@ -134,7 +135,7 @@ fem_status fem_mesh_info(const fem_mesh* m, int32_t level, fem_level_info* info)
     info->n = L.n;
     info->degree = L.p;
     info->brick = L.B;
-    info->pad = 0;
+    info->geometry = action_geometry(*m, level);
     return FEM_OK;
 }
 

@@ -31,6 +31,9 @@ FEM_HD constexpr int perm_axis(int t, int k) {
          : (t == 4) ? (k == 0 ? 2 : k == 1 ? 0 : 1) : (k == 0 ? 2 : k == 1 ? 1 : 0);
 }
 
+// Coarsest levels up to this many cubes per direction carry the hierarchy's geometry table.
+constexpr int kGeoMaxN = 24;
+
 // The boundary flag of a dof lives in the sign bit of the cell-to-dof map entry.
 constexpr uint32_t kBoundaryBit = 0x80000000u;
 

@@ -21,6 +21,13 @@
 //    it, in a fixed order (bitwise reproducible);
 //  * the sums go to the LDS closure array and are written with consecutive lanes on consecutive
 //    points: interior points to y (contiguous runs), brick-face points to their slots;
+//  * on a refined level whose bricks each lie inside one cube of the coarsest level (GEO), the
+//    geometry comes from the hierarchy's table instead: uniform refinement of the Kuhn split
+//    nests every tetrahedron in one coarsest tetrahedron, on which the mesh is affine, so G of a
+//    type-t tetrahedron is 2^-l times a value that depends only on the coarsest cube, the
+//    coarsest tetrahedron's type t0 and t.  The wave stages its coarsest cube's 36 x 6 values in
+//    LDS (scaled, in the kernel's precision) in place of the 5^3 vertex coordinates; a lane finds
+//    t0 by ordering the coordinates of the tetrahedron's centroid inside the coarsest cube;
 //  * loads use 32-bit offsets from uniform bases (the host keeps such levels below 4 GiB per array).
 #pragma once
 #include "scatter.hpp"
@@ -108,6 +115,22 @@ __host__ __device__ constexpr int xo_of(int j) {
     return XL::idx(ja, jb, jc) - XL::idx(0, 0, 0);
 }
 
+// Centroid of path tetrahedron t of the unit cube, times 4: 3, 2, 1 along axes s0, s1, s2.
+__host__ __device__ constexpr int centroid4(int t, int d) {
+    return perm_axis(t, 0) == d ? 3 : perm_axis(t, 1) == d ? 2 : 1;
+}
+// The type of the path tetrahedron holding a point with pairwise distinct coordinates u, from
+// the bits [u0 > u1] + 2 [u0 > u2] + 4 [u1 > u2]: three bits per code, packed.
+__host__ __device__ constexpr int path_type_code() {
+    int code = 0;
+    for (int t = 0; t < 6; ++t) {
+        const int u0 = centroid4(t, 0), u1 = centroid4(t, 1), u2 = centroid4(t, 2);
+        code |= t << (3 * ((u0 > u1) + 2 * (u0 > u2) + 4 * (u1 > u2)));
+    }
+    return code;
+}
+constexpr int kPathTypeCode = path_type_code();
+
 constexpr int kQuadPrev = 0 | (0 << 2) | (1 << 4) | (2 << 6);   // quad_perm [0, 0, 1, 2]
 constexpr int kRowShr4 = 0x114;                                  // row_shr:4
 
@@ -118,7 +141,7 @@ constexpr int cube_min_waves() {
     return (P == 1 || (sizeof(T) == 4 && !KVAR)) ? 4 : (sizeof(T) == 4 || !KVAR) ? 3 : 2;
 }
 
-template <int P, int B, int R, bool KVAR, typename T>
+template <int P, int B, int R, bool KVAR, bool GEO, typename T>
 __global__ void __launch_bounds__(B * B * B * R, (cube_min_waves<P, KVAR, T>())) k_cube_apply(SArgs<T> a) {
     static_assert(B == 4, "one wave per brick of 4^3 cubes");
     static_assert(R == 1 || P == 2, "bricks are merged along x for P2 only");
@@ -128,14 +151,18 @@ __global__ void __launch_bounds__(B * B * B * R, (cube_min_waves<P, KVAR, T>()))
     constexpr StiffTab<P, KVAR> TB{};
     constexpr CubeNodes<P> CN{};
     using XL = ClosureLayout<P>;
+    constexpr int NG = 216;                                              // GEO table of a coarsest cube
+    constexpr double kScale = (P == 2 && !KVAR) ? 1.0 / 120.0 : 1.0;   // P1 mass factor, vertex form
     // per wave: closure values (x on input, the brick's sums on output), the coordinates of the
-    // brick's 5^3 vertices and the coefficient there
+    // brick's 5^3 vertices (or its coarsest cube's geometry table) and the coefficient there
     __shared__ T xcs[R][XL::SIZE];
-    __shared__ double vcs[R][3][NV3];
+    __shared__ double vcs[R][3][GEO ? 1 : NV3];
+    __shared__ T gts[R][GEO ? NG : 1];
     __shared__ T kls[R][KVAR ? NV3 : 1];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / NT), lane = threadIdx.x % NT;
     T* __restrict__ xc = xcs[wave];
-    double(*__restrict__ vc)[NV3] = vcs[wave];
+    double(*__restrict__ vc)[GEO ? 1 : NV3] = vcs[wave];
+    T* __restrict__ gt = gts[wave];
     T* __restrict__ kl = kls[wave];
     // workgroup = R bricks along x (wave w: brick R px + w)
     const int pid = brick_of_block(blockIdx.x, gridDim.x);
@@ -176,17 +203,30 @@ __global__ void __launch_bounds__(B * B * B * R, (cube_min_waves<P, KVAR, T>()))
         }
         const uint32_t n1 = (uint32_t)a.n + 1, NV = a.nv;
         const uint32_t vb = (uint32_t)(bx * B) + n1 * ((uint32_t)(by * B) + n1 * (uint32_t)(bz * B));
-        constexpr int NVIT = (NV3 + NT - 1) / NT;
-        double cx[NVIT], cy[NVIT], cz[NVIT];
+        constexpr int NVIT = (NV3 + NT - 1) / NT, NGIT = (NG + NT - 1) / NT;
+        double cx[NVIT], cy[NVIT], cz[NVIT], gv[NGIT];
         T kv[NVIT];
 #pragma unroll
         for (int it = 0; it < NVIT; ++it) {
             const int r = (lane + NT * it < NV3) ? lane + NT * it : NV3 - 1;
             const uint32_t w = vb + (uint32_t)(r % VS) + n1 * ((uint32_t)((r / VS) % VS) + n1 * (uint32_t)(r / (VS * VS)));
-            cx[it] = ldg(a.vxyz, w);
-            cy[it] = ldg(a.vxyz, NV + w);
-            cz[it] = ldg(a.vxyz, 2 * NV + w);
+            if constexpr (!GEO) {
+                cx[it] = ldg(a.vxyz, w);
+                cy[it] = ldg(a.vxyz, NV + w);
+                cz[it] = ldg(a.vxyz, 2 * NV + w);
+            }
             if constexpr (KVAR) kv[it] = ldg(a.k, w);
+        }
+        if constexpr (GEO) {
+            // the brick's coarsest cube (the brick lies inside it: 2^geo_shift >= B)
+            const int sh = a.geo_shift;
+            const uint32_t n0 = (uint32_t)a.n >> sh;
+            const uint32_t q0 = (uint32_t)((bx * B) >> sh) + n0 * ((uint32_t)((by * B) >> sh) + n0 * (uint32_t)((bz * B) >> sh));
+#pragma unroll
+            for (int it = 0; it < NGIT; ++it) {
+                const int r = (lane + NT * it < NG) ? lane + NT * it : NG - 1;
+                gv[it] = ldg(a.geo, q0 * (uint32_t)NG + (uint32_t)r);
+            }
         }
         if constexpr (P == 2) {
             const int iA = XL::idx(la, rA, 0), iB = XL::idx(la, lbB, lc0);
@@ -205,10 +245,20 @@ __global__ void __launch_bounds__(B * B * B * R, (cube_min_waves<P, KVAR, T>()))
         for (int it = 0; it < NVIT; ++it) {
             const int r = lane + NT * it;
             if (r < NV3) {
-                vc[0][r] = cx[it];
-                vc[1][r] = cy[it];
-                vc[2][r] = cz[it];
+                if constexpr (!GEO) {
+                    vc[0][r] = cx[it];
+                    vc[1][r] = cy[it];
+                    vc[2][r] = cz[it];
+                }
                 if constexpr (KVAR) kl[r] = kv[it];
+            }
+        }
+        if constexpr (GEO) {
+            const double gs = a.geo_scale * kScale;
+#pragma unroll
+            for (int it = 0; it < NGIT; ++it) {
+                const int r = lane + NT * it;
+                if (r < NG) gt[r] = T(gv[it] * gs);
             }
         }
         // masked columns: zero the closure faces that lie on the domain boundary
@@ -230,6 +280,9 @@ __global__ void __launch_bounds__(B * B * B * R, (cube_min_waves<P, KVAR, T>()))
     // ---- the six tetrahedra of the lane's cube ----
     const int xb = XL::idx(P * lx, P * ly, P * lz);       // LDS index of the cube's point 0
     const int vbl = lx + VS * (ly + VS * lz);              // vertex index of the cube's corner 0
+    // GEO: 4 x the cube's position inside its coarsest cube
+    const int gmask = GEO ? (1 << a.geo_shift) - 1 : 0;
+    const int ax4 = 4 * ((bx * B + lx) & gmask), ay4 = 4 * ((by * B + ly) & gmask), az4 = 4 * ((bz * B + lz) & gmask);
     T ys[NCP];
 #pragma unroll
     for (int j = 0; j < NCP; ++j) ys[j] = T(0);
@@ -241,29 +294,41 @@ __global__ void __launch_bounds__(B * B * B * R, (cube_min_waves<P, KVAR, T>()))
         // at offset (j & 1, j >> 1 & 1, j >> 2))
         const int s0 = perm_axis(t, 0), s1 = perm_axis(t, 1);
         const int j1 = 1 << s0, j2 = (1 << s0) | (1 << s1);
-        double e1[3], e2[3], e3[3];
+        T gm[6];                                 // G: 00, 11, 22, 01, 02, 12
+        double c1x = 0, c1y = 0, c1z = 0, c2x = 0, c2y = 0, c2z = 0, c3x = 0, c3y = 0, c3z = 0, inv = 0;
+        if constexpr (GEO) {
+            const int ux = ax4 + centroid4(t, 0), uy = ay4 + centroid4(t, 1), uz = az4 + centroid4(t, 2);
+            const int t0 = (kPathTypeCode >> (3 * ((ux > uy) + 2 * (ux > uz) + 4 * (uy > uz)))) & 7;
+            const int g0 = 6 * (6 * t0 + t);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const double p0 = vc[d][vbl];
-            e1[d] = vc[d][vbl + vo_of<VS>(j1)] - p0;
-            e2[d] = vc[d][vbl + vo_of<VS>(j2)] - p0;
-            e3[d] = vc[d][vbl + vo_of<VS>(7)] - p0;
+            for (int e = 0; e < 6; ++e) gm[e] = gt[g0 + e];
+        } else {
+            double e1[3], e2[3], e3[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double p0 = vc[d][vbl];
+                e1[d] = vc[d][vbl + vo_of<VS>(j1)] - p0;
+                e2[d] = vc[d][vbl + vo_of<VS>(j2)] - p0;
+                e3[d] = vc[d][vbl + vo_of<VS>(7)] - p0;
+            }
+            c1x = e2[1] * e3[2] - e2[2] * e3[1], c1y = e2[2] * e3[0] - e2[0] * e3[2], c1z = e2[0] * e3[1] - e2[1] * e3[0];
+            c2x = e3[1] * e1[2] - e3[2] * e1[1], c2y = e3[2] * e1[0] - e3[0] * e1[2], c2z = e3[0] * e1[1] - e3[1] * e1[0];
+            c3x = e1[1] * e2[2] - e1[2] * e2[1], c3y = e1[2] * e2[0] - e1[0] * e2[2], c3z = e1[0] * e2[1] - e1[1] * e2[0];
+            const double det = e1[0] * c1x + e1[1] * c1y + e1[2] * c1z;
+            inv = kScale * recip(fabs(det));
+            if constexpr (P == 2) {
+                gm[0] = T((c1x * c1x + c1y * c1y + c1z * c1z) * inv);
+                gm[1] = T((c2x * c2x + c2y * c2y + c2z * c2z) * inv);
+                gm[2] = T((c3x * c3x + c3y * c3y + c3z * c3z) * inv);
+                gm[3] = T((c1x * c2x + c1y * c2y + c1z * c2z) * inv);
+                gm[4] = T((c1x * c3x + c1y * c3y + c1z * c3z) * inv);
+                gm[5] = T((c2x * c3x + c2y * c3y + c2z * c3z) * inv);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 6; ++e) gm[e] = T(0);
+            }
         }
-        const double c1x = e2[1] * e3[2] - e2[2] * e3[1], c1y = e2[2] * e3[0] - e2[0] * e3[2],
-                     c1z = e2[0] * e3[1] - e2[1] * e3[0];
-        const double c2x = e3[1] * e1[2] - e3[2] * e1[1], c2y = e3[2] * e1[0] - e3[0] * e1[2],
-                     c2z = e3[0] * e1[1] - e3[1] * e1[0];
-        const double c3x = e1[1] * e2[2] - e1[2] * e2[1], c3y = e1[2] * e2[0] - e1[0] * e2[2],
-                     c3z = e1[0] * e2[1] - e1[1] * e2[0];
-        const double det = e1[0] * c1x + e1[1] * c1y + e1[2] * c1z;
-        constexpr double kScale = (P == 2 && !KVAR) ? 1.0 / 120.0 : 1.0;   // P1 mass factor, vertex form
-        const double inv = kScale * recip(fabs(det));
-        const T g00 = T((c1x * c1x + c1y * c1y + c1z * c1z) * inv);
-        const T g11 = T((c2x * c2x + c2y * c2y + c2z * c2z) * inv);
-        const T g22 = T((c3x * c3x + c3y * c3y + c3z * c3z) * inv);
-        const T g01 = T((c1x * c2x + c1y * c2y + c1z * c2z) * inv);
-        const T g02 = T((c1x * c3x + c1y * c3y + c1z * c3z) * inv);
-        const T g12 = T((c2x * c3x + c2y * c3y + c2z * c3z) * inv);
+        const T g00 = gm[0], g11 = gm[1], g22 = gm[2], g01 = gm[3], g02 = gm[4], g12 = gm[5];
         // the cell's nodal values, read once the geometry is done (fewer values live at once)
         __asm__ volatile("" ::: "memory");
         T xs[NL];
@@ -328,15 +393,22 @@ __global__ void __launch_bounds__(B * B * B * R, (cube_min_waves<P, KVAR, T>()))
             if constexpr (KVAR)
                 s *= T(TB.lam[q][0]) * kt[0] + T(TB.lam[q][1]) * kt[1] + T(TB.lam[q][2]) * kt[2] +
                      T(TB.lam[q][3]) * kt[3];
-            const T a1x = T(c1x), a1y = T(c1y), a1z = T(c1z), a2x = T(c2x), a2y = T(c2y), a2z = T(c2z),
-                    a3x = T(c3x), a3y = T(c3y), a3z = T(c3z);
-            const T vx = gx * a1x + gy * a2x + gz * a3x;
-            const T vy = gx * a1y + gy * a2y + gz * a3y;
-            const T vz = gx * a1z + gy * a2z + gz * a3z;
-            const T sc = s * T(inv);
-            const T wx = sc * (a1x * vx + a1y * vy + a1z * vz);
-            const T wy = sc * (a2x * vx + a2y * vy + a2z * vz);
-            const T wz = sc * (a3x * vx + a3y * vy + a3z * vz);
+            T wx, wy, wz;
+            if constexpr (GEO) {
+                wx = s * (g00 * gx + g01 * gy + g02 * gz);
+                wy = s * (g01 * gx + g11 * gy + g12 * gz);
+                wz = s * (g02 * gx + g12 * gy + g22 * gz);
+            } else {
+                const T a1x = T(c1x), a1y = T(c1y), a1z = T(c1z), a2x = T(c2x), a2y = T(c2y), a2z = T(c2z),
+                        a3x = T(c3x), a3y = T(c3y), a3z = T(c3z);
+                const T vx = gx * a1x + gy * a2x + gz * a3x;
+                const T vy = gx * a1y + gy * a2y + gz * a3y;
+                const T vz = gx * a1z + gy * a2z + gz * a3z;
+                const T sc = s * T(inv);
+                wx = sc * (a1x * vx + a1y * vy + a1z * vz);
+                wy = sc * (a2x * vx + a2y * vy + a2z * vz);
+                wz = sc * (a3x * vx + a3y * vy + a3z * vz);
+            }
 #pragma unroll
             for (int i = 0; i < NL; ++i) {
                 T acc_i = ys[CN.cp[t][i]];

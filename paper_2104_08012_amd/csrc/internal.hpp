@@ -75,6 +75,17 @@ struct fem_mesh {
     std::vector<fem::HostLevel> lev;
     std::vector<fem::RedTable> red;
     fem::Tabulation tab[2];          // [kvar]
+    // geometric factors of the whole hierarchy from the coarsest level (every level is a uniform
+    // refinement of it, so the mesh is affine on each coarsest tetrahedron): for coarsest cube q0,
+    // coarsest tetrahedron type t0 and fine tetrahedron type t, G(L E_t) with L the coarsest
+    // cell's lattice-to-physical map and E_t the lattice edges of type t; a tetrahedron of type t
+    // on level l inside that coarsest cell has G = 2^-l G(L E_t).  Entry e (00, 11, 22, 01, 02,
+    // 12) of index (q0 * 6 + t0) * 6 + t at 6 * index + e, so one coarsest cube's 216 values are
+    // consecutive.  Built when the coarsest level has at most kGeoMaxN^3 cubes (geo_ok).
+    bool geo_ok = false;
+    int64_t geo_count = 0;
+    std::vector<double> geo;
+    size_t d_geo = 0;
     std::vector<double> mref64;      // nloc * nloc
     std::vector<float> mref32;
     size_t d_mref64 = 0, d_mref32 = 0;
@@ -93,4 +104,6 @@ struct fem_mesh {
 namespace fem {
 fem_status build_mesh(const fem_mesh_desc& d, fem_mesh& m);
 void build_transfer_tables(fem_mesh& m);
+// FEM_GEOM_* of the stiffness action on a level (the kernel choice of the launcher)
+int action_geometry(const fem_mesh& m, int level);
 }

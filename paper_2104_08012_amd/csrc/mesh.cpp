@@ -100,6 +100,36 @@ static void cell_vertices(const HostLevel& L, int64_t c, int V[4][3]) {
     for (int k = 0; k < 3; ++k) V[3][k] = V[0][k] + 1;
 }
 
+// G = adj(M) adj(M)^T / |det M| (= |det M| M^-1 M^-T) for M with the edge vectors as columns;
+// returns det M.
+static double geometric_factor(const double M[3][3], double g6[6]) {
+    double adj[3][3];
+    adj[0][0] = M[1][1] * M[2][2] - M[1][2] * M[2][1];
+    adj[0][1] = M[0][2] * M[2][1] - M[0][1] * M[2][2];
+    adj[0][2] = M[0][1] * M[1][2] - M[0][2] * M[1][1];
+    adj[1][0] = M[1][2] * M[2][0] - M[1][0] * M[2][2];
+    adj[1][1] = M[0][0] * M[2][2] - M[0][2] * M[2][0];
+    adj[1][2] = M[0][2] * M[1][0] - M[0][0] * M[1][2];
+    adj[2][0] = M[1][0] * M[2][1] - M[1][1] * M[2][0];
+    adj[2][1] = M[0][1] * M[2][0] - M[0][0] * M[2][1];
+    adj[2][2] = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+    const double det = M[0][0] * adj[0][0] + M[0][1] * adj[1][0] + M[0][2] * adj[2][0];
+    double G[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += adj[a][k] * adj[b][k];
+            G[a][b] = s / std::fabs(det);
+        }
+    g6[0] = G[0][0];
+    g6[1] = G[1][1];
+    g6[2] = G[2][2];
+    g6[3] = G[0][1];
+    g6[4] = G[0][2];
+    g6[5] = G[1][2];
+    return det;
+}
+
 static void build_level(HostLevel& L, const std::vector<std::array<int, 4>>& mi) {
     const int n = L.n, p = L.p, nl = L.nloc;
     L.B = choose_brick(n);
@@ -140,27 +170,8 @@ static void build_level(HostLevel& L, const std::vector<std::array<int, 4>>& mi)
         double J[3][3];  // columns are the edges x1-x0, x2-x0, x3-x0
         for (int r = 0; r < 3; ++r)
             for (int col = 0; col < 3; ++col) J[r][col] = x[col + 1][r] - x[0][r];
-        // adjugate: J^-1 = adj / det
-        double adj[3][3];
-        adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-        adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-        adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-        adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-        adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-        adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-        adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-        adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-        adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-        const double det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
-        // G = |det| J^-1 J^-T = adj adj^T / |det|
-        double G[3][3];
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) {
-                double s = 0.0;
-                for (int k = 0; k < 3; ++k) s += adj[a][k] * adj[b][k];
-                G[a][b] = s / std::fabs(det);
-            }
-        const double g6[6] = {G[0][0], G[1][1], G[2][2], G[0][1], G[0][2], G[1][2]};
+        double g6[6];
+        const double det = geometric_factor(J, g6);
         for (int e = 0; e < 6; ++e) {
             L.G64[(size_t)e * C + c] = g6[e];
             L.G32[(size_t)e * C + c] = (float)g6[e];
@@ -183,6 +194,117 @@ static void build_cube_data(HostLevel& L) {
     for (int64_t v = 0; v < NV; ++v)
         for (int a = 0; a < 3; ++a) L.vsoa[(size_t)a * NV + v] = L.vxyz[(size_t)3 * v + a];
     L.cube = true;
+}
+
+// Geometric factors of every level from the coarsest level's cells (see fem_mesh::geo).  The
+// coarsest cell (cube q0, type t0) has lattice edges E_t0 (integer, det +-1) and physical edges
+// J0, so its lattice-to-physical map is L = J0 E_t0^-1; a type-t tetrahedron of the same lattice
+// scale inside it has physical edges L E_t.
+static void build_geometry_table(fem_mesh& m) {
+    const HostLevel& L0 = m.lev[0];
+    const int n0 = L0.n, N1 = n0 + 1;
+    m.geo_ok = n0 <= kGeoMaxN;
+    m.geo.clear();
+    m.geo_count = 0;
+    if (!m.geo_ok) return;
+    const int64_t cnt = (int64_t)n0 * n0 * n0 * 36;
+    m.geo_count = cnt;
+    m.geo.assign((size_t)6 * cnt, 0.0);   // entries of one coarsest cube: 216 consecutive doubles
+    auto edges = [](int t, double E[3][3]) {   // columns: V1 - V0, V2 - V0, V3 - V0 of path t
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) E[r][c] = 0.0;
+        const int s0 = perm_axis(t, 0), s1 = perm_axis(t, 1);
+        E[s0][0] = 1.0;
+        E[s0][1] = 1.0;
+        E[s1][1] = 1.0;
+        for (int r = 0; r < 3; ++r) E[r][2] = 1.0;
+    };
+    for (int64_t q0 = 0; q0 < (int64_t)n0 * n0 * n0; ++q0) {
+        const int ci = (int)(q0 % n0), cj = (int)((q0 / n0) % n0), ck = (int)(q0 / ((int64_t)n0 * n0));
+        for (int t0 = 0; t0 < 6; ++t0) {
+            const int s0 = perm_axis(t0, 0), s1 = perm_axis(t0, 1);
+            int V[4][3] = {{ci, cj, ck}, {ci, cj, ck}, {ci, cj, ck}, {ci + 1, cj + 1, ck + 1}};
+            V[1][s0] += 1;
+            V[2][s0] += 1;
+            V[2][s1] += 1;
+            double X[4][3];
+            for (int w = 0; w < 4; ++w) {
+                const int64_t vid = V[w][0] + (int64_t)N1 * (V[w][1] + (int64_t)N1 * V[w][2]);
+                for (int a = 0; a < 3; ++a) X[w][a] = L0.vxyz[3 * vid + a];
+            }
+            double J0[3][3], E0[3][3], Einv[3][3], Lm[3][3];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) J0[r][c] = X[c + 1][r] - X[0][r];
+            edges(t0, E0);
+            // E0 is unimodular: its inverse is its adjugate times det (+-1), exact in doubles
+            const double ed = E0[0][0] * (E0[1][1] * E0[2][2] - E0[1][2] * E0[2][1]) -
+                              E0[0][1] * (E0[1][0] * E0[2][2] - E0[1][2] * E0[2][0]) +
+                              E0[0][2] * (E0[1][0] * E0[2][1] - E0[1][1] * E0[2][0]);
+            Einv[0][0] = (E0[1][1] * E0[2][2] - E0[1][2] * E0[2][1]) / ed;
+            Einv[0][1] = (E0[0][2] * E0[2][1] - E0[0][1] * E0[2][2]) / ed;
+            Einv[0][2] = (E0[0][1] * E0[1][2] - E0[0][2] * E0[1][1]) / ed;
+            Einv[1][0] = (E0[1][2] * E0[2][0] - E0[1][0] * E0[2][2]) / ed;
+            Einv[1][1] = (E0[0][0] * E0[2][2] - E0[0][2] * E0[2][0]) / ed;
+            Einv[1][2] = (E0[0][2] * E0[1][0] - E0[0][0] * E0[1][2]) / ed;
+            Einv[2][0] = (E0[1][0] * E0[2][1] - E0[1][1] * E0[2][0]) / ed;
+            Einv[2][1] = (E0[0][1] * E0[2][0] - E0[0][0] * E0[2][1]) / ed;
+            Einv[2][2] = (E0[0][0] * E0[1][1] - E0[0][1] * E0[1][0]) / ed;
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) {
+                    double s = 0.0;
+                    for (int k = 0; k < 3; ++k) s += J0[r][k] * Einv[k][c];
+                    Lm[r][c] = s;
+                }
+            for (int t = 0; t < 6; ++t) {
+                double E[3][3], M[3][3], g6[6];
+                edges(t, E);
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) {
+                        double s = 0.0;
+                        for (int k = 0; k < 3; ++k) s += Lm[r][k] * E[k][c];
+                        M[r][c] = s;
+                    }
+                geometric_factor(M, g6);
+                const int64_t idx = (q0 * 6 + t0) * 6 + t;
+                for (int e = 0; e < 6; ++e) m.geo[(size_t)idx * 6 + e] = g6[e];
+            }
+        }
+    }
+    // Check: on every level, each cell's factors from its own vertex coordinates equal the table's
+    // (up to the rounding of the midpoint coordinates), with the coarsest cell found as the
+    // kernels find it, by ordering the centroid's coordinates inside the coarsest cube.
+    for (int l = 0; l < m.nlev; ++l) {
+        const HostLevel& L = m.lev[l];
+        const int mask = (1 << l) - 1;
+        const double scale = std::ldexp(1.0, -l);
+        for (int64_t c = 0; c < L.C; ++c) {
+            int V[4][3];
+            cell_vertices(L, c, V);
+            const int t = (int)((c % L.NC) / ((int64_t)L.B * L.B * L.B));
+            int u[3];
+            for (int a = 0; a < 3; ++a) u[a] = 4 * (V[0][a] & mask) + (V[1][a] - V[0][a]) + (V[2][a] - V[0][a]) + 1;
+            int t0 = -1;
+            for (int tt = 0; tt < 6; ++tt)
+                if (u[perm_axis(tt, 0)] > u[perm_axis(tt, 1)] && u[perm_axis(tt, 1)] > u[perm_axis(tt, 2)]) t0 = tt;
+            const int64_t q0 = (V[0][0] >> l) + (int64_t)n0 * ((V[0][1] >> l) + (int64_t)n0 * (V[0][2] >> l));
+            const double* g = &m.geo[(size_t)((q0 * 6 + t0) * 6 + t) * 6];
+            double gmax = 0.0, dmax = 0.0;
+            for (int e = 0; e < 6; ++e) {
+                const double ref = L.G64[(size_t)e * L.C + c];
+                gmax = std::max(gmax, std::fabs(ref));
+                dmax = std::max(dmax, std::fabs(ref - scale * g[e]));
+            }
+            if (t0 < 0 || !(dmax <= 1e-9 * gmax))
+                throw std::runtime_error("geometry table does not match the cells of level " + std::to_string(l));
+        }
+    }
+}
+
+int action_geometry(const fem_mesh& m, int level) {
+    const HostLevel& L = m.lev[level];
+    if (!L.cube) return FEM_GEOM_CELL;
+    // a 4-cube brick inside one coarsest cube: 2^level >= 4
+    return (m.geo_ok && level >= 2) ? FEM_GEOM_TABLE : FEM_GEOM_VERTEX;
 }
 
 // Structural check: every map entry equals the dof the brick reduction table expects.
@@ -277,6 +399,7 @@ fem_status build_mesh(const fem_mesh_desc& d, fem_mesh& m) {
         L.slot_elems = 8 * std::max(iface(p), iface(1));
     }
     for (int kv = 0; kv < 2; ++kv) build_tab(m.tab[kv], p, kv);
+    build_geometry_table(m);
     build_transfer_tables(m);
     mass_matrix(p, m.mref64);
     m.mref32.assign(m.mref64.begin(), m.mref64.end());
@@ -294,6 +417,7 @@ fem_status build_mesh(const fem_mesh_desc& d, fem_mesh& m) {
     }
     m.d_mref64 = take(m.mref64.size() * 8);
     m.d_mref32 = take(m.mref32.size() * 4);
+    m.d_geo = take(m.geo.size() * 8);
     m.d_pt_off = take(m.pt_off.size() * 4);
     m.d_pt_w64 = take(m.pt_w64.size() * 8);
     m.d_pt_w32 = take(m.pt_w32.size() * 4);

@@ -1,6 +1,7 @@
 // Launchers for the cell-wise kernels (stiffness action, diagonal, mass, transfers, adjoint
 // gradient): fill the kernel arguments from the mesh's device tables and dispatch the template
 // instance for the degree, brick size, coefficient kind and precision.
+#include <cmath>
 #include <mutex>
 
 #include "ops.hpp"
@@ -42,19 +43,25 @@ fem_status noalloc_scratch(void** ptr, size_t* bytes) {
 
 namespace {
 
+template <int P, int B, bool KV, bool GEO, typename T>
+void launch_cube(const SArgs<T>& a, int64_t nbricks, hipStream_t s) {
+    const int R = a.nb / a.nbx;
+    const unsigned grid = (unsigned)(nbricks / R);
+    if constexpr (P == 2) {
+        if (R == 4) { hipLaunchKernelGGL((k_cube_apply<P, B, 4, KV, GEO, T>), dim3(grid), dim3(4 * 64), 0, s, a); return; }
+        if (R == 2) { hipLaunchKernelGGL((k_cube_apply<P, B, 2, KV, GEO, T>), dim3(grid), dim3(2 * 64), 0, s, a); return; }
+    }
+    hipLaunchKernelGGL((k_cube_apply<P, B, 1, KV, GEO, T>), dim3(grid), dim3(64), 0, s, a);
+}
+
 template <int KIND, typename T, int P, int B, bool KV>
 void launch_main(const SArgs<T>& a, int64_t nbricks, hipStream_t s) {
     if constexpr (KIND == K_APPLY && P <= 2 && B == 4) {
         // one thread per cube for the low degrees (see cube.hpp), where the level has the cube
         // data; R = nb / nbx bricks along x per workgroup
         if (a.vxyz) {
-            const int R = a.nb / a.nbx;
-            const unsigned grid = (unsigned)(nbricks / R);
-            if constexpr (P == 2) {
-                if (R == 4) { hipLaunchKernelGGL((k_cube_apply<P, B, 4, KV, T>), dim3(grid), dim3(4 * 64), 0, s, a); return; }
-                if (R == 2) { hipLaunchKernelGGL((k_cube_apply<P, B, 2, KV, T>), dim3(grid), dim3(2 * 64), 0, s, a); return; }
-            }
-            hipLaunchKernelGGL((k_cube_apply<P, B, 1, KV, T>), dim3(grid), dim3(64), 0, s, a);
+            if (a.geo) launch_cube<P, B, KV, true, T>(a, nbricks, s);
+            else launch_cube<P, B, KV, false, T>(a, nbricks, s);
             return;
         }
     }
@@ -149,6 +156,11 @@ fem_status run_kind(const fem_mesh& m, int level, bool kvar, const ScatterIO<T>&
     a.xid = io.xid;
     a.vxyz = L.cube ? dptr<double>(m, L.d_vsoa) : nullptr;
     a.nv = (uint32_t)L.NV;
+    // geometry from the coarsest level's table once a brick of cubes lies inside one coarsest cube
+    const bool geo = KIND == K_APPLY && action_geometry(m, level) == FEM_GEOM_TABLE;
+    a.geo = geo ? dptr<double>(m, m.d_geo) : nullptr;
+    a.geo_shift = level;
+    a.geo_scale = std::ldexp(1.0, -level);
     // the P2 cube kernel merges R = 4 (or 2) bricks along x in one workgroup; the interface
     // numbering then has bricks of span R p B along x (iface.hpp)
     const int R = (KIND == K_APPLY && m.p == 2 && L.B == 4 && L.cube) ? (L.nb % 4 == 0 ? 4 : L.nb % 2 == 0 ? 2 : 1) : 1;

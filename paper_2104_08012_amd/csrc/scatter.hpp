@@ -54,6 +54,9 @@ struct SArgs {
     const T* xid;                    // values of identity rows
     const double* vxyz;              // cube kernel: vertex coordinates SoA x[nv], y[nv], z[nv]
     uint32_t nv;
+    const double* geo;               // cube kernel: the hierarchy's geometry table, or null
+    int geo_shift;                   // levels below the coarsest (2^geo_shift cubes per coarsest cube)
+    double geo_scale;                // 2^-geo_shift
 };
 
 constexpr int brick_threads(int B) { return B == 4 ? 384 : 64; }

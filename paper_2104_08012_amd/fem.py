@@ -78,7 +78,8 @@ class Mesh:
         i = L.LevelInfo()
         check(lib().fem_mesh_info(self._h, level, C.byref(i)), "fem_mesh_info")
         return {"n_cells": i.n_cells, "n_dofs": i.n_dofs, "n_interior": i.n_interior,
-                "n_vertices": i.n_vertices, "n": i.n, "degree": i.degree, "brick": i.brick}
+                "n_vertices": i.n_vertices, "n": i.n, "degree": i.degree, "brick": i.brick,
+                "geometry": ("cell", "vertex", "table")[i.geometry]}
 
     def _lev(self, level: int) -> int:
         return level % self.n_levels

@@ -58,6 +58,27 @@ def test_apply_fp32_parity(n, p, jit, kvar):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("n,r,p,jit", [(2, 3, 1, 0.15), (2, 3, 2, 0.15), (3, 2, 2, 0.15), (1, 4, 2, 0.0)])
+@pytest.mark.parametrize("kvar", [False, True])
+def test_apply_refined_levels_parity(n, r, p, jit, kvar):
+    """Every level of a refined hierarchy: from level 2 on, a 4-cube brick lies inside one cube of
+    the coarsest level and the cube kernel takes the geometry from the coarsest level's table
+    instead of the vertex coordinates (n = 2 -> 16: R = 2 and 4 bricks per workgroup; n = 3 -> 12:
+    R = 1, a coarsest level of odd size; n = 1 -> 16: a single coarsest cube)."""
+    banner(f"apply refined n={n} r={r} p={p} jit={jit} kvar={kvar}")
+    mesh, levels = make_pair(n, r, p, jit)
+    for ell, lev in enumerate(levels):
+        k = fem_inputs.k_exp_fourier(lev.vert_xyz) if kvar else None
+        x = fem_inputs.uniform_vector(lev.n_dofs, ell)
+        y_ref = oracle_A(lev, k) @ x
+        y = mesh.apply(_t(x), _t(k) if kvar else None, level=ell)
+        y32 = mesh.apply(_t(x, torch.float32), _t(k, torch.float32) if kvar else None, level=ell)
+        torch.cuda.synchronize()
+        assert rel(y.cpu().numpy(), y_ref) <= 1e-12, ell
+        assert rel(y32.cpu().numpy(), y_ref) <= 2e-6, ell
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("n", [8, 16])
 def test_apply_axpby_and_determinism(n):
     banner(f"apply axpby / determinism n={n}")

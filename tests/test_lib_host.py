@@ -192,3 +192,18 @@ def test_solver_workspace_with_patch_smoother():
     mp = fem.Mesh(2, 1, 1, upload=False)
     st, _ = ws(mp, smoother="patch")
     assert st == L.FEM_ERR_UNSUPPORTED
+
+
+def test_action_geometry_source_per_level():
+    """P1/P2 levels on 4-cube bricks take G from the coarsest level's table once a brick lies in
+    one coarsest cube (level >= 2, coarsest mesh up to 24^3), from the vertex coordinates before
+    that; P3 and smaller bricks keep per-cell factors.  (The library checks the table against every
+    cell's factors when it builds the mesh.)"""
+    from paper_2104_08012_amd import fem
+    m = fem.Mesh(4, 3, 2, upload=False)
+    assert [m.info(l)["geometry"] for l in range(4)] == ["vertex", "vertex", "table", "table"]
+    m = fem.Mesh(3, 2, 1, jitter=fem_inputs.jitter_offsets(3, 0.15), upload=False)
+    assert [m.info(l)["geometry"] for l in range(3)] == ["cell", "cell", "table"]   # n = 3, 6: bricks of 1, 2
+    assert fem.Mesh(32, 0, 2, upload=False).info(0)["geometry"] == "vertex"
+    assert fem.Mesh(28, 2, 1, upload=False).info(2)["geometry"] == "vertex"       # coarsest above 24^3
+    assert fem.Mesh(2, 2, 3, upload=False).info(2)["geometry"] == "cell"
