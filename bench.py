@@ -30,11 +30,12 @@ value = operator-action GDoF/s of step 1: n_dofs / (mean cold duration of the ac
 events recorded on the stream the action's kernels run on, over the timed steps).  The action is
 two launches (the cube kernel and the interface fix-up), bracketed together.  Algorithmic bytes
 of one action, by where the level takes its geometry (the mesh reports it per level):
-  table (P1/P2 on 4-cube bricks of a refined level, G from the coarsest level's table):
+  table (4-cube bricks of a refined level, G from the coarsest level's table):
       B = 2 N s + 1728 n0^3 (+ N_v s for a P1 coefficient)
   vertex (P1/P2 on 4-cube bricks, G from the vertex coordinates):
       B = 2 N s + 24 N_v (+ N_v s)
-  cell (stored per-cell factors and dof map): B = 2 N s + 4 C nloc + 6 C s (+ N_v s)
+  cell, P3 on 4-cube bricks (per-cell factors): B = 2 N s + 6 C s (+ N_v s)
+  cell, smaller bricks (per-cell factors and dof map): B = 2 N s + 4 C nloc + 6 C s (+ N_v s)
 (x read and y written once, dofs addressed by lattice point on 4-cube bricks, else int32 dof
 indices; the table holds 36 x 6 FP64 values per coarsest cube.)
 Algorithmic flops: (12 nq nloc + 20 nq) per cell, the tabulated-gradient contraction.  roofline
@@ -115,7 +116,8 @@ def flops_per_cell(p, kvar):
 
 def kernel_sources_sha():
     h = hashlib.sha256()
-    for f in ("cube.hpp", "scatter.hpp", "tabulate.hpp", "incidence.hpp", "iface.hpp", "common.hpp", "ops.hip"):
+    for f in ("cube.hpp", "lattice.hpp", "scatter.hpp", "tabulate.hpp", "incidence.hpp", "iface.hpp", "common.hpp",
+              "ops.hip"):
         with open(os.path.join(ROOT, "paper_2104_08012_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -136,7 +138,7 @@ def traffic_from_profiles(key):
     return e.get("traffic_bytes")
 
 
-def action_bytes(p, C, N, NV, s, kvar, geometry, n0):
+def action_bytes(p, C, N, NV, s, kvar, geometry, n0, brick):
     """Algorithmic bytes of one action for the layout the library uses on the level: x and y once
     and the vertex coefficient, plus the geometry the kernel reads (the coarsest level's table, the
     FP64 vertex coordinates, or the cell-to-dof map and the per-cell factors)."""
@@ -145,6 +147,8 @@ def action_bytes(p, C, N, NV, s, kvar, geometry, n0):
         return 2 * N * s + 36 * 6 * 8 * n0 ** 3 + kv
     if geometry == "vertex":
         return 2 * N * s + 24 * NV + kv
+    if brick == 4:
+        return 2 * N * s + 6 * C * s + kv
     return balg_bytes(C, N, nloc_of(p), s, NV if kvar else 0)
 
 
@@ -153,7 +157,7 @@ def roofline(p, kvar, mesh, s, t, key):
     and flops / vector peak, with the measured fraction of it."""
     info = mesh.levels[-1]
     C, N, NV, geometry = info["n_cells"], info["n_dofs"], info["n_vertices"], info["geometry"]
-    B = action_bytes(p, C, N, NV, s, kvar, geometry, mesh.levels[0]["n"])
+    B = action_bytes(p, C, N, NV, s, kvar, geometry, mesh.levels[0]["n"], info["brick"])
     gbs = B / t / 1e9
     out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(key),
@@ -169,7 +173,8 @@ def roofline(p, kvar, mesh, s, t, key):
         out["alu_frac"] = round(tf / peak, 4)
     # what was timed: one action = the cell kernel and the fix-up, bracketed together by HIP
     # events on the library's stream (the kernel trace in profiles/ lists the two separately)
-    out["kernels"] = ("k_brick + k_fixup" if geometry == "cell" else "k_cube_apply + k_fixup") + " (one action)"
+    main = "k_brick" if info["brick"] != 4 else "k_lattice_apply" if p == 3 else "k_cube_apply"
+    out["kernels"] = main + " + k_fixup (one action)"
     out["geometry"] = geometry
     out["duration_us"] = round(t * 1e6, 2)
     return out
@@ -834,7 +839,8 @@ def summarize_counters(fdir, wdir, workload, write_traffic):
     # for P1 both are the same instance with the same slot layout.
     cube = pw <= 2 and n % 4 == 0
     R = 4 if pw == 2 else 1
-    main_prefix = f"k_cube_apply<{pw}," if cube else f"k_brick<0, {pw},"
+    main_prefix = (f"k_cube_apply<{pw}," if cube else f"k_lattice_apply<{pw}," if n % 4 == 0
+                   else f"k_brick<0, {pw},")
     fix_prefix = f"k_fixup<{pw}, 4, {R}," if cube else f"k_fixup<{pw}, 4, 1,"
     acts = {prec: [(g, nm, b) for g, nm, b in lst if nm.startswith((main_prefix, fix_prefix))]
             for prec, lst in acts.items()}
@@ -1005,7 +1011,7 @@ def main():
     ap.add_argument("--summarize-valu", nargs="+", metavar="PMC_DIR",
                     help="rocprofv3 --pmc directories of the VALU_PASSES counter sets")
     ap.add_argument("--valu-trace", metavar="TRACE_DIR", help="kernel-trace directory for durations")
-    ap.add_argument("--valu-kernels", default="k_cube_apply,k_brick<0,k_fixup",
+    ap.add_argument("--valu-kernels", default="k_cube_apply,k_lattice_apply,k_brick<0,k_fixup",
                     help="comma-separated kernel-name prefixes to list")
     args = ap.parse_args()
     if args.summarize_trace:

@@ -34,6 +34,22 @@ FEM_HD constexpr int perm_axis(int t, int k) {
 // Coarsest levels up to this many cubes per direction carry the hierarchy's geometry table.
 constexpr int kGeoMaxN = 24;
 
+// Centroid of path tetrahedron t of the unit cube, times 4: 3, 2, 1 along axes s0, s1, s2.
+FEM_HD constexpr int centroid4(int t, int d) {
+    return perm_axis(t, 0) == d ? 3 : perm_axis(t, 1) == d ? 2 : 1;
+}
+// The type of the path tetrahedron holding a point with pairwise distinct coordinates u, from
+// the bits [u0 > u1] + 2 [u0 > u2] + 4 [u1 > u2]: three bits per code, packed.
+FEM_HD constexpr int path_type_code() {
+    int code = 0;
+    for (int t = 0; t < 6; ++t) {
+        const int u0 = centroid4(t, 0), u1 = centroid4(t, 1), u2 = centroid4(t, 2);
+        code |= t << (3 * ((u0 > u1) + 2 * (u0 > u2) + 4 * (u1 > u2)));
+    }
+    return code;
+}
+constexpr int kPathTypeCode = path_type_code();
+
 // The boundary flag of a dof lives in the sign bit of the cell-to-dof map entry.
 constexpr uint32_t kBoundaryBit = 0x80000000u;
 

@@ -115,22 +115,6 @@ __host__ __device__ constexpr int xo_of(int j) {
     return XL::idx(ja, jb, jc) - XL::idx(0, 0, 0);
 }
 
-// Centroid of path tetrahedron t of the unit cube, times 4: 3, 2, 1 along axes s0, s1, s2.
-__host__ __device__ constexpr int centroid4(int t, int d) {
-    return perm_axis(t, 0) == d ? 3 : perm_axis(t, 1) == d ? 2 : 1;
-}
-// The type of the path tetrahedron holding a point with pairwise distinct coordinates u, from
-// the bits [u0 > u1] + 2 [u0 > u2] + 4 [u1 > u2]: three bits per code, packed.
-__host__ __device__ constexpr int path_type_code() {
-    int code = 0;
-    for (int t = 0; t < 6; ++t) {
-        const int u0 = centroid4(t, 0), u1 = centroid4(t, 1), u2 = centroid4(t, 2);
-        code |= t << (3 * ((u0 > u1) + 2 * (u0 > u2) + 4 * (u1 > u2)));
-    }
-    return code;
-}
-constexpr int kPathTypeCode = path_type_code();
-
 constexpr int kQuadPrev = 0 | (0 << 2) | (1 << 4) | (2 << 6);   // quad_perm [0, 0, 1, 2]
 constexpr int kRowShr4 = 0x114;                                  // row_shr:4
 

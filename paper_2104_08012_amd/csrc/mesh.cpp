@@ -302,9 +302,11 @@ static void build_geometry_table(fem_mesh& m) {
 
 int action_geometry(const fem_mesh& m, int level) {
     const HostLevel& L = m.lev[level];
-    if (!L.cube) return FEM_GEOM_CELL;
+    // the cube kernel (P1/P2) and the lattice kernel (P3) on 4-cube bricks
+    if (L.B != 4 || (L.p <= 2 && !L.cube)) return FEM_GEOM_CELL;
     // a 4-cube brick inside one coarsest cube: 2^level >= 4
-    return (m.geo_ok && level >= 2) ? FEM_GEOM_TABLE : FEM_GEOM_VERTEX;
+    if (m.geo_ok && level >= 2) return FEM_GEOM_TABLE;
+    return L.p <= 2 ? FEM_GEOM_VERTEX : FEM_GEOM_CELL;
 }
 
 // Structural check: every map entry equals the dof the brick reduction table expects.

@@ -6,6 +6,7 @@
 
 #include "ops.hpp"
 #include "cube.hpp"
+#include "lattice.hpp"
 #include "scatter.hpp"
 
 namespace fem {
@@ -56,6 +57,14 @@ void launch_cube(const SArgs<T>& a, int64_t nbricks, hipStream_t s) {
 
 template <int KIND, typename T, int P, int B, bool KV>
 void launch_main(const SArgs<T>& a, int64_t nbricks, hipStream_t s) {
+    if constexpr (KIND == K_APPLY && P == 3 && B == 4) {
+        // P3 on 4-cube bricks: dofs addressed by lattice point (see lattice.hpp)
+        if (a.lattice) {
+            if (a.geo) hipLaunchKernelGGL((k_lattice_apply<P, KV, true, T>), dim3((unsigned)nbricks), dim3(brick_threads(B)), 0, s, a);
+            else hipLaunchKernelGGL((k_lattice_apply<P, KV, false, T>), dim3((unsigned)nbricks), dim3(brick_threads(B)), 0, s, a);
+            return;
+        }
+    }
     if constexpr (KIND == K_APPLY && P <= 2 && B == 4) {
         // one thread per cube for the low degrees (see cube.hpp), where the level has the cube
         // data; R = nb / nbx bricks along x per workgroup
@@ -159,6 +168,7 @@ fem_status run_kind(const fem_mesh& m, int level, bool kvar, const ScatterIO<T>&
     // geometry from the coarsest level's table once a brick of cubes lies inside one coarsest cube
     const bool geo = KIND == K_APPLY && action_geometry(m, level) == FEM_GEOM_TABLE;
     a.geo = geo ? dptr<double>(m, m.d_geo) : nullptr;
+    a.lattice = KIND == K_APPLY && L.B == 4 && m.p == 3;
     a.geo_shift = level;
     a.geo_scale = std::ldexp(1.0, -level);
     // the P2 cube kernel merges R = 4 (or 2) bricks along x in one workgroup; the interface

@@ -57,6 +57,7 @@ struct SArgs {
     const double* geo;               // cube kernel: the hierarchy's geometry table, or null
     int geo_shift;                   // levels below the coarsest (2^geo_shift cubes per coarsest cube)
     double geo_scale;                // 2^-geo_shift
+    int lattice;                     // P3 on 4-cube bricks: dofs addressed by lattice point
 };
 
 constexpr int brick_threads(int B) { return B == 4 ? 384 : 64; }
@@ -124,17 +125,53 @@ __device__ __forceinline__ void put_slot(const SArgs<T>& a, int bx, int by, int 
     a.slots[(size_t)code * a.if_tot + t] = v;
 }
 
-// Stiffness action: y_K = sum_q w_q k_q D_q^T G D_q x_K (compile-time tabulation, zero entries
-// of D generate no instructions).
+// The cell's stiffness contribution y_K = sum_q w_q k_q D_q^T G D_q x_K from its nodal values,
+// G (00, 11, 22, 01, 02, 12) and the coefficient at its vertices (compile-time tabulation, zero
+// entries of D generate no instructions).
+template <int P, bool KVAR, typename T>
+__device__ __forceinline__ void stiffness_local(const T* xs, const T* g, const T* kv, T* out) {
+    constexpr int NL = nloc_of(P), NQ = nq_of(P, KVAR);
+    constexpr StiffTab<P, KVAR> TB{};
+    const T g00 = g[0], g11 = g[1], g22 = g[2], g01 = g[3], g02 = g[4], g12 = g[5];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) out[i] = T(0);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        T gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            if (TB.D[q][0][i] != 0.0) gx += T(TB.D[q][0][i]) * xs[i];
+            if (TB.D[q][1][i] != 0.0) gy += T(TB.D[q][1][i]) * xs[i];
+            if (TB.D[q][2][i] != 0.0) gz += T(TB.D[q][2][i]) * xs[i];
+        }
+        T s = T(TB.w[q]);
+        if constexpr (KVAR)
+            s *= T(TB.lam[q][0]) * kv[0] + T(TB.lam[q][1]) * kv[1] + T(TB.lam[q][2]) * kv[2] +
+                 T(TB.lam[q][3]) * kv[3];
+        const T wx = s * (g00 * gx + g01 * gy + g02 * gz);
+        const T wy = s * (g01 * gx + g11 * gy + g12 * gz);
+        const T wz = s * (g02 * gx + g12 * gy + g22 * gz);
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            T v = out[i];
+            if (TB.D[q][0][i] != 0.0) v += T(TB.D[q][0][i]) * wx;
+            if (TB.D[q][1][i] != 0.0) v += T(TB.D[q][1][i]) * wy;
+            if (TB.D[q][2][i] != 0.0) v += T(TB.D[q][2][i]) * wz;
+            out[i] = v;
+        }
+    }
+}
+
+// Stiffness action from the cell-to-dof map and the per-cell factors.
 template <int P, int B, bool KVAR, typename T>
 struct Producer<K_APPLY, P, B, KVAR, T> {
-    static constexpr int NL = nloc_of(P), NQ = nq_of(P, KVAR);
+    static constexpr int NL = nloc_of(P);
     __device__ __forceinline__ static void run(const SArgs<T>& a, int64_t c, int cl, int bx, int by, int bz,
                                                T* out) {
-        constexpr StiffTab<P, KVAR> TB{};
         const int64_t C = a.C;
-        const T g00 = soa(a.G, 0, C, c), g11 = soa(a.G, 1, C, c), g22 = soa(a.G, 2, C, c);
-        const T g01 = soa(a.G, 3, C, c), g02 = soa(a.G, 4, C, c), g12 = soa(a.G, 5, C, c);
+        T g[6];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) g[e] = soa(a.G, e, C, c);
         T xs[NL];
 #pragma unroll
         for (int i = 0; i < NL; ++i) xs[i] = gather(a.x, soa(a.map, i, C, c), a.mask_cols);
@@ -146,33 +183,7 @@ struct Producer<K_APPLY, P, B, KVAR, T> {
 #pragma unroll
             for (int v = 0; v < 4; ++v) kv[v] = a.k[V[v][0] + n1 * (V[v][1] + n1 * V[v][2])];
         }
-#pragma unroll
-        for (int i = 0; i < NL; ++i) out[i] = T(0);
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            T gx = T(0), gy = T(0), gz = T(0);
-#pragma unroll
-            for (int i = 0; i < NL; ++i) {
-                if (TB.D[q][0][i] != 0.0) gx += T(TB.D[q][0][i]) * xs[i];
-                if (TB.D[q][1][i] != 0.0) gy += T(TB.D[q][1][i]) * xs[i];
-                if (TB.D[q][2][i] != 0.0) gz += T(TB.D[q][2][i]) * xs[i];
-            }
-            T s = T(TB.w[q]);
-            if constexpr (KVAR)
-                s *= T(TB.lam[q][0]) * kv[0] + T(TB.lam[q][1]) * kv[1] + T(TB.lam[q][2]) * kv[2] +
-                     T(TB.lam[q][3]) * kv[3];
-            const T wx = s * (g00 * gx + g01 * gy + g02 * gz);
-            const T wy = s * (g01 * gx + g11 * gy + g12 * gz);
-            const T wz = s * (g02 * gx + g12 * gy + g22 * gz);
-#pragma unroll
-            for (int i = 0; i < NL; ++i) {
-                T v = out[i];
-                if (TB.D[q][0][i] != 0.0) v += T(TB.D[q][0][i]) * wx;
-                if (TB.D[q][1][i] != 0.0) v += T(TB.D[q][1][i]) * wy;
-                if (TB.D[q][2][i] != 0.0) v += T(TB.D[q][2][i]) * wz;
-                out[i] = v;
-            }
-        }
+        stiffness_local<P, KVAR, T>(xs, g, kv, out);
     }
 };
 

@@ -58,13 +58,15 @@ def test_apply_fp32_parity(n, p, jit, kvar):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("n,r,p,jit", [(2, 3, 1, 0.15), (2, 3, 2, 0.15), (3, 2, 2, 0.15), (1, 4, 2, 0.0)])
+@pytest.mark.parametrize("n,r,p,jit", [(2, 3, 1, 0.15), (2, 3, 2, 0.15), (3, 2, 2, 0.15), (1, 4, 2, 0.0),
+                                       (2, 2, 3, 0.15), (3, 2, 3, 0.15)])
 @pytest.mark.parametrize("kvar", [False, True])
 def test_apply_refined_levels_parity(n, r, p, jit, kvar):
     """Every level of a refined hierarchy: from level 2 on, a 4-cube brick lies inside one cube of
-    the coarsest level and the cube kernel takes the geometry from the coarsest level's table
-    instead of the vertex coordinates (n = 2 -> 16: R = 2 and 4 bricks per workgroup; n = 3 -> 12:
-    R = 1, a coarsest level of odd size; n = 1 -> 16: a single coarsest cube)."""
+    the coarsest level and the action takes the geometry from the coarsest level's table (P1/P2:
+    the cube kernel, in place of the vertex coordinates; P3: the lattice kernel, in place of the
+    per-cell factors).  n = 2 -> 16: R = 2 and 4 bricks per workgroup; n = 3 -> 12: R = 1, a
+    coarsest level of odd size; n = 1 -> 16: a single coarsest cube."""
     banner(f"apply refined n={n} r={r} p={p} jit={jit} kvar={kvar}")
     mesh, levels = make_pair(n, r, p, jit)
     for ell, lev in enumerate(levels):

@@ -195,10 +195,10 @@ def test_solver_workspace_with_patch_smoother():
 
 
 def test_action_geometry_source_per_level():
-    """P1/P2 levels on 4-cube bricks take G from the coarsest level's table once a brick lies in
-    one coarsest cube (level >= 2, coarsest mesh up to 24^3), from the vertex coordinates before
-    that; P3 and smaller bricks keep per-cell factors.  (The library checks the table against every
-    cell's factors when it builds the mesh.)"""
+    """Levels on 4-cube bricks take G from the coarsest level's table once a brick lies in one
+    coarsest cube (level >= 2, coarsest mesh up to 24^3); before that P1/P2 form it from the vertex
+    coordinates and P3 reads per-cell factors, as every level on smaller bricks does.  (The library
+    checks the table against every cell's factors when it builds the mesh.)"""
     from paper_2104_08012_amd import fem
     m = fem.Mesh(4, 3, 2, upload=False)
     assert [m.info(l)["geometry"] for l in range(4)] == ["vertex", "vertex", "table", "table"]
@@ -206,4 +206,6 @@ def test_action_geometry_source_per_level():
     assert [m.info(l)["geometry"] for l in range(3)] == ["cell", "cell", "table"]   # n = 3, 6: bricks of 1, 2
     assert fem.Mesh(32, 0, 2, upload=False).info(0)["geometry"] == "vertex"
     assert fem.Mesh(28, 2, 1, upload=False).info(2)["geometry"] == "vertex"       # coarsest above 24^3
-    assert fem.Mesh(2, 2, 3, upload=False).info(2)["geometry"] == "cell"
+    m = fem.Mesh(2, 2, 3, upload=False)
+    assert [m.info(l)["geometry"] for l in range(3)] == ["cell", "cell", "table"]
+    assert fem.Mesh(8, 0, 3, upload=False).info(0)["geometry"] == "cell"
