@@ -1,13 +1,15 @@
 """Parity at the benchmark sizes, in the launch configurations bench.py times.
 
-* P2 on 64^3 x 6 tetrahedra, k = 1 (the default workload's finest level): the FP64 action
-  against the oracle's matrix-free action to 1e-12, FP32 to 2e-6.
-* P3 on 48^3 x 6 tetrahedra with k = exp(g): FP64 1e-12, FP32 2e-6.
-* P2 on 128^3 x 6 tetrahedra (12.6M cells): FP64 1e-12.
-* The 128^3 x 6 action sweep: P1 (2.1M dofs) FP64 1e-12 / FP32 2e-6 against the oracle's full
-  matrix-free action; P3 (57M dofs, the paper's own problem size) on sampled rows (seeded random
-  dofs, dofs on brick planes, next to the boundary and on it) against the oracle's evaluation of
-  those rows from the cells around them, FP64 1e-12 / FP32 2e-6 in the norm over the sample.
+* The actions bench.py times, on the finest level of the same hierarchies (the geometry from
+  the coarsest level's table): P2 on 64^3 x 6 tetrahedra refined from 16^3, k = 1, FP64 against
+  the oracle's matrix-free action to 1e-12, FP32 to 2e-6; P3 on 48^3 refined from 6^3 with
+  k = exp(g), FP64 1e-12, FP32 2e-6; P2 on 128^3 refined from 4^3 (12.6M cells), FP64 1e-12; and
+  P2 on a single-level 128^3 mesh (the geometry from the vertex coordinates), FP64 1e-12.
+* The 128^3 x 6 action sweep on the hierarchy refined from 4^3: P1 (2.1M dofs) FP64 1e-12 /
+  FP32 2e-6 against the oracle's full matrix-free action; P3 (57M dofs, the paper's own problem
+  size) on sampled rows (seeded random dofs, dofs on brick planes, next to the boundary and on
+  it) against the oracle's evaluation of those rows from the cells around them, FP64 1e-12 /
+  FP32 2e-6 in the norm over the sample.
 * The variable-coefficient P3 solve at full size (48^3, k = exp(g), f = 1, 4-level MG-CG, FP64 and
   mixed, rtol 1e-10) against sampled values of the oracle's solution (written by
   tests/golden/make_p3_48_vark_solution.py, oracle MG-CG to 1e-13): relative error over the
@@ -49,12 +51,15 @@ def _oracle_residual(lev, k, b, u_lib, perm):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("n,p,kvar", [(64, 2, False), (48, 3, True), (128, 2, False)])
-def test_action_at_bench_size(n, p, kvar):
-    banner(f"full-size action n={n} p={p} kvar={kvar}")
+@pytest.mark.parametrize("n0,refine,p,kvar", [(16, 2, 2, False), (6, 3, 3, True), (4, 5, 2, False),
+                                              (128, 0, 2, False)])
+def test_action_at_bench_size(n0, refine, p, kvar):
+    n = n0 * 2 ** refine
+    banner(f"full-size action n={n} (from {n0}^3) p={p} kvar={kvar}")
     from paper_2104_08012_amd import fem
-    mesh = fem.Mesh(n, 0, p, device="cuda:0")
-    lev = om.single_level(n, p)
+    mesh = fem.Mesh(n0, refine, p, device="cuda:0")
+    assert mesh.info(refine)["geometry"] == ("table" if refine >= 2 else "vertex")
+    lev = om.single_level(n, p)   # the uniform refinement of the uniform n0^3 mesh is uniform
     perm = _perm(mesh, lev)
     x = fem_inputs.uniform_vector(lev.n_dofs, 0)          # oracle order
     k = fem_inputs.k_exp_fourier(lev.vert_xyz) if kvar else None
@@ -117,7 +122,8 @@ def test_action_sweep_128(p):
     banner(f"full-size action sweep n=128 p={p}")
     from paper_2104_08012_amd import fem
     n = 128
-    mesh = fem.Mesh(n, 0, p, device="cuda:0")
+    mesh = fem.Mesh(4, 5, p, device="cuda:0")
+    assert mesh.info(5)["geometry"] == "table"
     L = p * n + 1
     N = L ** 3
     lat = mesh.dof_lattice().astype(np.int64)
