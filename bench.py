@@ -556,12 +556,12 @@ def sweep_rows(torch, fem, fem_inputs, flush, n, reps):
     single-level n^3 mesh (geometry from the vertex coordinates); cold (Infinity Cache flushed
     before each) and hot (back to back)."""
     rows = []
-    r = max(0, round(math.log2(n / 4)))
-    hier = 4 * 2 ** r == n
+    nref = max(0, round(math.log2(n / 4)))
+    hier = 4 * 2 ** nref == n
     for p, single in ((1, False), (2, False), (2, True), (3, False)):
         if single and not hier:
             continue
-        mesh = fem.Mesh(n, 0, p, device="cuda:0") if single or not hier else fem.Mesh(4, r, p, device="cuda:0")
+        mesh = fem.Mesh(n, 0, p, device="cuda:0") if single or not hier else fem.Mesh(4, nref, p, device="cuda:0")
         info = mesh.levels[-1]
         N, C, NV = info["n_dofs"], info["n_cells"], info["n_vertices"]
         for dt, s in ((torch.float64, 8), (torch.float32, 4)):
