@@ -823,8 +823,8 @@ def summarize_counters(fdir, wdir, workload, write_traffic):
     print(f"{'fetch_MB':>9} {'write_MB':>9}  kernel [grid threads]")
     acts = {}
     for (nm, full, g), c in sorted(res.items(), key=lambda kv: -kv[1].get("FETCH_SIZE", 0.0)):
-        if not any(k in nm for k in ("k_cube_apply", "k_fixup", "k_brick", "copyBuffer", "k_prolong", "k_sym",
-                                     "k_patch")):
+        if not any(k in nm for k in ("k_cube_apply", "k_lattice_apply", "k_fixup", "k_brick", "copyBuffer",
+                                     "k_prolong", "k_restrict", "k_sym", "k_patch", "k_star")):
             continue
         f, w = c.get("FETCH_SIZE", 0.0), c.get("WRITE_SIZE", 0.0)
         print(f"{f / 1e6:9.2f} {w / 1e6:9.2f}  {nm} [{g}]")
