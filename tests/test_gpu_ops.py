@@ -187,6 +187,29 @@ def test_transfer_parity(n, p, jit):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("p", [1, 2])
+def test_transfer_parity_large_levels(p):
+    """32^3 -> 64^3: from 32 coarse cubes per direction P1/P2 prolong one thread per coarse cube
+    (compile-time weights) instead of one thread per fine dof; the restriction runs the
+    compile-time class stencils at every size."""
+    banner(f"transfers 32^3 -> 64^3 p={p}")
+    mesh, levels = make_pair(32, 1, p, 0.0)
+    P = transfer.prolongation(levels[0], levels[1])
+    xc = fem_inputs.uniform_vector(levels[0].n_dofs, 0)
+    xf0 = fem_inputs.uniform_vector(levels[1].n_dofs, 1)
+    rf = fem_inputs.uniform_vector(levels[1].n_dofs, 2)
+    rc_ref = P.T @ rf
+    rc_ref[levels[0].boundary] = 0
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 2e-6)):
+        xf = _t(xf0, dt)
+        mesh.prolong(_t(xc, dt), xf, 1)
+        rc = mesh.restrict(_t(rf, dt), 1)
+        torch.cuda.synchronize()
+        assert rel(xf.double().cpu().numpy(), xf0 + P @ xc) <= tol, dt
+        assert rel(rc.double().cpu().numpy(), rc_ref) <= tol, dt
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("n,p,jit", [(8, 2, 0.15), (6, 3, 0.0), (5, 1, 0.15), (4, 2, 0.0)])
 def test_adjoint_grad_parity(n, p, jit):
     banner(f"grad n={n} p={p}")
