@@ -778,19 +778,22 @@ fem_status fem_solver::cg(const double* b, double* x, int& it, double& rel_true,
     auto tail = [&](int set) -> fem_status {
         evset = set;
         FEM_TRY(precondition(r, z));
-        dotdev(2, r, z, q, z, CG_RZNEW);
-        cg_beta_launch(sc, o.flexible != 0, s);
+        dot_beta_launch(n, r, z, q, part, sc, o.flexible != 0, s);
         cg_direction_dev_launch(n, sc, z, pp, s);
         return FEM_OK;
     };
     while (!converged && it < o.max_it) {
         FEM_TRY(apply64(hi, pp, 1.0, nullptr, 0.0, q));        // q = A p
-        dotdev(1, pp, q, nullptr, nullptr, CG_PQ);
-        cg_alpha_launch(sc, s);
-        cg_update_dev_launch(n, sc, pp, q, x, r, s);
+        dot_alpha_launch(n, pp, q, part, sc, s);
         ++it;
-        if (o.replace_every > 0 && it % o.replace_every == 0) FEM_TRY(apply64(hi, x, -1.0, b, 1.0, r));
-        dotdev(1, r, r, nullptr, nullptr, CG_RR);
+        if (o.replace_every > 0 && it % o.replace_every == 0) {
+            // residual replacement: r^T r of the true residual
+            cg_update_dev_launch(n, sc, pp, q, x, r, s);
+            FEM_TRY(apply64(hi, x, -1.0, b, 1.0, r));
+            dotdev(1, r, r, nullptr, nullptr, CG_RR);
+        } else {
+            cg_update_dot_launch(n, sc, pp, q, x, r, part, sc + CG_RR, s);
+        }
         hipError_t e = hipMemcpyAsync(hscal, sc + CG_RR, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipEventRecord(done, s);
         // far from convergence the next direction is computed speculatively, before the residual

@@ -43,9 +43,9 @@ __global__ void __launch_bounds__(VT) k_dot_partial(int64_t n, DotPairs<T> pr, d
     if (threadIdx.x < NPAIR) partial[threadIdx.x * DOT_BLOCKS + blockIdx.x] = sh[threadIdx.x][0];
 }
 
+// the partials' fixed tree, leaving the sums in sh[p][0]
 template <int NPAIR>
-__global__ void __launch_bounds__(VT) k_dot_final(const double* partial, double* out) {
-    __shared__ double sh[NPAIR][VT];
+__device__ __forceinline__ void dot_final_tree(const double* partial, double (*sh)[VT]) {
 #pragma unroll
     for (int p = 0; p < NPAIR; ++p) {
         double a = 0.0;
@@ -59,6 +59,12 @@ __global__ void __launch_bounds__(VT) k_dot_final(const double* partial, double*
             for (int p = 0; p < NPAIR; ++p) sh[p][threadIdx.x] += sh[p][threadIdx.x + s];
         __syncthreads();
     }
+}
+
+template <int NPAIR>
+__global__ void __launch_bounds__(VT) k_dot_final(const double* partial, double* out) {
+    __shared__ double sh[NPAIR][VT];
+    dot_final_tree<NPAIR>(partial, sh);
     if (threadIdx.x < NPAIR) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
@@ -71,8 +77,7 @@ __global__ void k_axpby(int64_t n, double a, const T* __restrict__ x, double b, 
 
 // Device-resident CG scalars (indices into the solver's scalar block, see vec.hpp).
 // alpha = rz / pq, or 0 with flag bit 1 when p^T A p is not positive and finite.
-__global__ void k_cg_alpha(double* sc) {
-    if (threadIdx.x != 0) return;
+__device__ __forceinline__ void cg_alpha(double* sc) {
     const double pq = sc[CG_PQ], rz = sc[CG_RZ];
     const bool ok = pq > 0.0 && pq < INFINITY;
     sc[CG_ALPHA] = ok ? rz / pq : 0.0;
@@ -81,13 +86,59 @@ __global__ void k_cg_alpha(double* sc) {
 
 // beta (Fletcher-Reeves rz_new / rz, or Polak-Ribiere -alpha qz / rz) and rz = rz_new; beta = 0
 // with flag bit 2 when r^T z is not positive and finite.
-__global__ void k_cg_beta(double* sc, int flexible) {
-    if (threadIdx.x != 0) return;
+__device__ __forceinline__ void cg_beta(double* sc, int flexible) {
     const double rzn = sc[CG_RZNEW], rz = sc[CG_RZ];
     const bool ok = rzn > 0.0 && rzn < INFINITY;
     sc[CG_BETA] = !ok ? 0.0 : flexible ? -sc[CG_ALPHA] * sc[CG_QZ] / rz : rzn / rz;
     sc[CG_RZ] = rzn;
     if (!ok) sc[CG_FLAG] = (double)((int)sc[CG_FLAG] | 2);
+}
+
+// The last reduction stage of p^T q fused with alpha (one launch instead of two; the same tree).
+__global__ void __launch_bounds__(VT) k_dot_final_alpha(const double* partial, double* sc) {
+    __shared__ double sh[1][VT];
+    dot_final_tree<1>(partial, sh);
+    if (threadIdx.x == 0) {
+        sc[CG_PQ] = sh[0][0];
+        cg_alpha(sc);
+    }
+}
+
+// The last reduction stage of (r^T z, q^T z) fused with beta.
+__global__ void __launch_bounds__(VT) k_dot_final_beta(const double* partial, double* sc, int flexible) {
+    __shared__ double sh[2][VT];
+    dot_final_tree<2>(partial, sh);
+    if (threadIdx.x == 0) {
+        sc[CG_RZNEW] = sh[0][0];
+        sc[CG_QZ] = sh[1][0];
+        cg_beta(sc, flexible);
+    }
+}
+
+// x += alpha p ; r -= alpha q, with the first reduction stage of r^T r over the updated r in
+// the same pass (the chunks, strides and tree of k_dot_partial, so r^T r is bitwise the one a
+// separate dot product would give).
+__global__ void __launch_bounds__(VT) k_cg_update_dot(int64_t n, const double* __restrict__ sc, const double* __restrict__ p,
+                                                    const double* __restrict__ q, double* __restrict__ x,
+                                                    double* __restrict__ r, double* __restrict__ partial) {
+    __shared__ double sh[VT];
+    const double alpha = sc[CG_ALPHA];
+    const int64_t chunk = (n + DOT_BLOCKS - 1) / DOT_BLOCKS;
+    const int64_t lo = blockIdx.x * chunk, hi = (lo + chunk < n) ? lo + chunk : n;
+    double acc = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += VT) {
+        x[i] += alpha * p[i];
+        const double rn = r[i] - alpha * q[i];
+        r[i] = rn;
+        acc += rn * rn;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = VT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
 // x += alpha p ; r -= alpha q with alpha read from device memory
@@ -499,9 +550,21 @@ void axpby_launch(int64_t n, double a, const T* x, double b, T* y, hipStream_t s
 template void axpby_launch<double>(int64_t, double, const double*, double, double*, hipStream_t);
 template void axpby_launch<float>(int64_t, double, const float*, double, float*, hipStream_t);
 
-void cg_alpha_launch(double* sc, hipStream_t s) { hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64), 0, s, sc); }
-void cg_beta_launch(double* sc, bool flexible, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64), 0, s, sc, flexible ? 1 : 0);
+void dot_alpha_launch(int64_t n, const double* p, const double* q, double* partial, double* sc, hipStream_t s) {
+    DotPairs<double> pr{{p, nullptr, nullptr}, {q, nullptr, nullptr}};
+    hipLaunchKernelGGL((k_dot_partial<double, 1>), dim3(DOT_BLOCKS), dim3(VT), 0, s, n, pr, partial);
+    hipLaunchKernelGGL(k_dot_final_alpha, dim3(1), dim3(VT), 0, s, partial, sc);
+}
+void dot_beta_launch(int64_t n, const double* r, const double* z, const double* q, double* partial, double* sc,
+                     bool flexible, hipStream_t s) {
+    DotPairs<double> pr{{r, q, nullptr}, {z, z, nullptr}};
+    hipLaunchKernelGGL((k_dot_partial<double, 2>), dim3(DOT_BLOCKS), dim3(VT), 0, s, n, pr, partial);
+    hipLaunchKernelGGL(k_dot_final_beta, dim3(1), dim3(VT), 0, s, partial, sc, flexible ? 1 : 0);
+}
+void cg_update_dot_launch(int64_t n, const double* sc, const double* p, const double* q, double* x, double* r,
+                          double* partial, double* rr, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_update_dot, dim3(DOT_BLOCKS), dim3(VT), 0, s, n, sc, p, q, x, r, partial);
+    hipLaunchKernelGGL((k_dot_final<1>), dim3(1), dim3(VT), 0, s, partial, rr);
 }
 void cg_update_dev_launch(int64_t n, const double* sc, const double* p, const double* q, double* x, double* r,
                           hipStream_t s) {

@@ -27,10 +27,16 @@ void axpby_launch(int64_t n, double a, const T* x, double b, T* y, hipStream_t s
 // no host round trip: alpha = rz / pq; beta and rz <- rz_new; flag bits 1 (p^T A p <= 0) and
 // 2 (r^T z <= 0) record breakdowns.
 enum { CG_RZ = 8, CG_PQ = 9, CG_ALPHA = 10, CG_RR = 11, CG_FLAG = 12, CG_RZNEW = 13, CG_QZ = 14, CG_BETA = 15 };
-void cg_alpha_launch(double* sc, hipStream_t s);
-void cg_beta_launch(double* sc, bool flexible, hipStream_t s);
 void cg_update_dev_launch(int64_t n, const double* sc, const double* p, const double* q, double* x, double* r,
                           hipStream_t s);
+// Fused forms with the reductions' fixed order (results bitwise those of the separate launches):
+// sc[CG_PQ] = p^T q then alpha; x += alpha p, r -= alpha q and *rr = r^T r of the updated r;
+// (sc[CG_RZNEW], sc[CG_QZ]) = (r^T z, q^T z) then beta.
+void dot_alpha_launch(int64_t n, const double* p, const double* q, double* partial, double* sc, hipStream_t s);
+void cg_update_dot_launch(int64_t n, const double* sc, const double* p, const double* q, double* x, double* r,
+                          double* partial, double* rr, hipStream_t s);
+void dot_beta_launch(int64_t n, const double* r, const double* z, const double* q, double* partial, double* sc,
+                     bool flexible, hipStream_t s);
 void cg_direction_dev_launch(int64_t n, const double* sc, const double* z, double* p, hipStream_t s);
 // d = c1 d + c2 dinv r (first: d = c2 dinv r); x = d (init) or x += d
 template <typename T>
