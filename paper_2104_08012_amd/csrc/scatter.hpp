@@ -1,8 +1,9 @@
 // Cell-wise kernels with a deterministic scatter-add, for gfx950.
 //
 // Every operator of the method that sums per-cell contributions into shared dofs (the stiffness
-// action, its diagonal, the mass action, the restriction and the adjoint gradient) runs through
-// the same two-kernel pattern:
+// action, its diagonal, the mass action and the adjoint gradient) runs through the same
+// two-kernel pattern (the stiffness action on 4-cube bricks replaces step 1 by the cube kernel,
+// cube.hpp, for P1/P2 and the lattice kernel, lattice.hpp, for P3):
 //
 //  1. k_brick: one workgroup per brick of B^3 cubes (6 B^3 cells, one cell per thread).  Each
 //     thread gathers its cell's inputs through the structure-of-arrays cell-to-dof map, forms the
