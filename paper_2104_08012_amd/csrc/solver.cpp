@@ -12,7 +12,7 @@
 //     coefficient injected at the coarse vertices.
 //   * Coarsest level used: exact FP64 solve with the dense inverse of the interior block,
 //     assembled by probing the matrix-free operator with (2p+1)^3 colour vectors, inverted by a
-//     blocked Gauss-Jordan sweep and kept as the packed lower tiles of its symmetric part (half the
+//     blocked Gauss-Jordan sweep on its lower triangle and kept as packed lower tiles (half the
 //     bytes read per coarse solve).  When that level is too large for a dense inverse it is solved
 //     by a nested FP64 MG-PCG over the levels below it, to a relative residual of coarse_rtol
 //     (deepening the hierarchy under an expensive coarse level, as the paper does in Section 4).
@@ -50,7 +50,7 @@ struct LevelWs {
 struct Layout {
     std::vector<LevelWs> lev;
     size_t cg_r = 0, cg_z = 0, cg_p = 0, cg_q = 0, partial = 0, scal = 0, dense = 0, dense_xc = 0, jac_diag = 0;
-    size_t dense_packed = 0, dense_part = 0;
+    size_t dense_packed = 0, dense_part = 0, dense_tmp = 0;
     size_t inner = 0, inner_bytes = 0;
     size_t total = 0;
     int top = 0, lo = 0, hi = 0, mixed = 0, nested = 0;
@@ -183,6 +183,7 @@ fem_status make_layout(const fem_mesh& m, const fem_solve_opts& o, int top, Layo
         L.coarse32 = method == FEM_COARSE_DENSE_F32 ? 1 : 0;
         L.dense_packed = take(sym_packed_doubles(nI) * (L.coarse32 ? 4 : 8));
         L.dense_part = take(sym_partial_doubles(nI) * 8);
+        L.dense_tmp = take(dense_invert_tmp_doubles(nI) * 8);
     }
     L.total = off;
     return FEM_OK;
@@ -659,7 +660,7 @@ fem_status fem_solver::setup(const double* k_top) {
                         FEM_TRY(apply64(L.lo, v, 1.0, nullptr, 0.0, y));
                         probe_extract_launch(C.L, P, S, c0, c1, c2, y, A, s);
                     }
-            FEM_TRY(dense_invert(nd, A, nullptr, s));
+            FEM_TRY(dense_invert(nd, A, p<double>(L.dense_tmp), s));
             if (L.coarse32) sym_pack_launch(nd, A, p<float>(L.dense_packed), s);
             else sym_pack_launch(nd, A, p<double>(L.dense_packed), s);
         }

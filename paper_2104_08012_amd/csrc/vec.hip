@@ -1,6 +1,7 @@
 // Vector kernels of the multigrid-CG solver: deterministic dot products, axpy forms, the fused
 // Chebyshev update, precision casts, coefficient injection, and the dense coarse-grid kernels
-// (probing assembly, blocked Gauss-Jordan inversion, matrix-vector product).
+// (probing assembly, packed symmetric tiles and their matrix-vector product; the inversion is in
+// dense.hip).
 #include "vec.hpp"
 
 namespace fem {
@@ -277,90 +278,6 @@ __global__ void k_probe_extract(int L, int p, int S, int c0, int c1, int c2, con
     A[t * (int64_t)M * M * M + col] = y[g];
 }
 
-// Invert one nb x nb diagonal block in place (Gauss-Jordan, no pivoting; the block of an SPD
-// matrix's Schur complement is SPD).  One workgroup; the block is staged in LDS.
-template <int NB>
-__global__ void __launch_bounds__(256) k_gj_pivot(int64_t ld, int64_t k0, int b, double* A) {
-    __shared__ double s[NB][NB + 1];
-    for (int e = threadIdx.x; e < b * b; e += 256) s[e / b][e % b] = A[(k0 + e / b) * ld + k0 + e % b];
-    __syncthreads();
-    for (int k = 0; k < b; ++k) {
-        const double piv = 1.0 / s[k][k];
-        __syncthreads();
-        // row k scaled, other rows eliminated, column k replaced (in-place Gauss-Jordan)
-        for (int e = threadIdx.x; e < b * b; e += 256) {
-            const int i = e / b, j = e % b;
-            if (i != k && j != k) s[i][j] -= s[i][k] * s[k][j] * piv;
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < b; e += 256) {
-            if (e != k) {
-                s[k][e] *= piv;
-                s[e][k] *= -piv;
-            }
-        }
-        if (threadIdx.x == 0) s[k][k] = piv;
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < b * b; e += 256) A[(k0 + e / b) * ld + k0 + e % b] = s[e / b][e % b];
-}
-
-// Tiled FP64 GEMM  C = alpha * A B + beta * C  (row-major, leading dimensions lda/ldb/ldc),
-// 64 x 64 tiles of C per workgroup, 4 x 4 register blocks per thread, K in chunks of 16 staged in
-// LDS.  Rows of C in [rskip_lo, rskip_hi) and columns in [cskip_lo, cskip_hi) are left untouched.  Every workgroup reads
-// all of its A and B inputs before writing its C tile, so the blocked Gauss-Jordan sweep can run
-// in place: its row panel writes the rows it reads (each tile only its own columns), its column
-// panel the columns it reads (each tile only its own rows), and its trailing update never writes
-// the pivot rows or columns it reads.
-constexpr int GT = 64, GK = 16;
-
-__global__ void __launch_bounds__(256) k_gemm(int64_t M, int64_t N, int K, double alpha, const double* A, int64_t lda,
-                                              const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
-                                              int64_t rskip_lo, int64_t rskip_hi, int64_t cskip_lo, int64_t cskip_hi) {
-    const int64_t i0 = (int64_t)blockIdx.y * GT, j0 = (int64_t)blockIdx.x * GT;
-    __shared__ double As[GK][GT + 1];
-    __shared__ double Bs[GK][GT + 1];
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[4][4] = {};
-    for (int kk = 0; kk < K; kk += GK) {
-        for (int e = threadIdx.x; e < GK * GT; e += 256) {
-            const int r = e / GK, c = e % GK;
-            const int64_t gi = i0 + r;
-            As[c][r] = (gi < M && kk + c < K) ? A[gi * lda + kk + c] : 0.0;
-            const int rr = e / GT, cc = e % GT;
-            const int64_t gj = j0 + cc;
-            Bs[rr][cc] = (gj < N && kk + rr < K) ? B[(int64_t)(kk + rr) * ldb + gj] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < GK; ++c) {
-            double a[4], bb[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                a[u] = As[c][ty * 4 + u];
-                bb[u] = Bs[c][tx * 4 + u];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * bb[v];
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int64_t gi = i0 + ty * 4 + u;
-        if (gi >= M || (gi >= rskip_lo && gi < rskip_hi)) continue;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t gj = j0 + tx * 4 + v;
-            if (gj >= N || (gj >= cskip_lo && gj < cskip_hi)) continue;
-            double* c = &C[gi * ldc + gj];
-            *c = (beta == 0.0) ? alpha * acc[u][v] : alpha * acc[u][v] + beta * *c;
-        }
-    }
-}
-
 // Symmetric coarse inverse in packed lower tiles: tile (I, J), I >= J, of 64 x 64 entries
 // (row-major inside the tile, zero beyond n) at offset (I (I + 1) / 2 + J) * 4096.
 constexpr int ST = 64;
@@ -373,8 +290,9 @@ __device__ __forceinline__ void tile_of(int64_t t, int& I, int& J) {
     J = (int)(t - (int64_t)i * (i + 1) / 2);
 }
 
-// Ap tile (I, J) = (A_IJ + A_JI^T) / 2: the symmetric part of the computed inverse, stored in TO
-// (FP64, or FP32 for the mixed-precision preconditioner: rounded once from the FP64 inverse).
+// Ap tile (I, J) = A_IJ from the lower triangle the inversion keeps, diagonal tiles
+// (A_II + A_II^T) / 2, stored in TO (FP64, or FP32 for the mixed-precision preconditioner: rounded
+// once from the FP64 inverse).
 template <typename TO>
 __global__ void __launch_bounds__(256) k_sym_pack(int64_t n, const double* __restrict__ A, TO* __restrict__ Ap) {
     int I, J;
@@ -382,7 +300,9 @@ __global__ void __launch_bounds__(256) k_sym_pack(int64_t n, const double* __res
     TO* out = Ap + (int64_t)blockIdx.x * ST * ST;
     for (int e = threadIdx.x; e < ST * ST; e += 256) {
         const int64_t i = (int64_t)I * ST + e / ST, j = (int64_t)J * ST + e % ST;
-        out[e] = (TO)((i < n && j < n) ? 0.5 * (A[i * n + j] + A[j * n + i]) : 0.0);
+        double v = 0.0;
+        if (i < n && j < n) v = I == J ? 0.5 * (A[i * n + j] + A[j * n + i]) : A[i * n + j];
+        out[e] = (TO)v;
     }
 }
 
@@ -639,30 +559,6 @@ void probe_fill_launch(int L, int S, int c0, int c1, int c2, double* v, hipStrea
 void probe_extract_launch(int L, int p, int S, int c0, int c1, int c2, const double* y, double* A, hipStream_t s) {
     const int64_t M = L - 2;
     hipLaunchKernelGGL(k_probe_extract, dim3(grid_for(M * M * M)), dim3(VT), 0, s, L, p, S, c0, c1, c2, y, A);
-}
-
-// In-place inversion of an SPD matrix by the blocked Gauss-Jordan sweep, pivot blocks of 64:
-//   P = A_kk^-1;  A_kj = P A_kj (j outside k);  A_ij -= A_ik A_kj (i, j outside k);
-//   A_ik = -A_ik P (i outside k);  A_kk = P.
-fem_status dense_invert(int64_t n, double* A, double* tmp, hipStream_t s) {
-    (void)tmp;
-    const int NB = 64;
-    const unsigned tn = (unsigned)((n + GT - 1) / GT);
-    for (int64_t k0 = 0; k0 < n; k0 += NB) {
-        const int b = (int)std::min<int64_t>(NB, n - k0);
-        double* Akk = A + k0 * n + k0;
-        hipLaunchKernelGGL((k_gj_pivot<64>), dim3(1), dim3(256), 0, s, n, k0, b, A);
-        // row panel: rows k (b of them), all columns outside the block
-        hipLaunchKernelGGL(k_gemm, dim3(tn, 1), dim3(256), 0, s, (int64_t)b, n, b, 1.0, (const double*)Akk, n,
-                           (const double*)(A + k0 * n), n, 0.0, A + k0 * n, n, (int64_t)0, (int64_t)0, k0, k0 + b);
-        // trailing update on all rows/columns outside the block
-        hipLaunchKernelGGL(k_gemm, dim3(tn, tn), dim3(256), 0, s, n, n, b, -1.0, (const double*)(A + k0), n,
-                           (const double*)(A + k0 * n), n, 1.0, A, n, k0, k0 + b, k0, k0 + b);
-        // column panel: all rows outside the block, columns k
-        hipLaunchKernelGGL(k_gemm, dim3(1, tn), dim3(256), 0, s, n, (int64_t)b, b, -1.0, (const double*)(A + k0), n,
-                           (const double*)Akk, n, 0.0, A + k0, n, k0, k0 + b, (int64_t)0, (int64_t)0);
-    }
-    return check_launch("dense inversion");
 }
 
 int64_t sym_tiles(int64_t n) {

@@ -57,6 +57,9 @@ void inject_launch(int nc, int stride, int nf, const double* kf, T* kc, hipStrea
 void random_launch(int64_t n, int L, uint64_t seed, double* v, hipStream_t s);
 void probe_fill_launch(int L, int S, int c0, int c1, int c2, double* v, hipStream_t s);
 void probe_extract_launch(int L, int p, int S, int c0, int c1, int c2, const double* y, double* A, hipStream_t s);
+// In-place inverse of an n x n SPD matrix (row-major), kept in its lower 64 x 64 tiles (diagonal
+// tiles whole; the strict upper tiles are left stale).  tmp: dense_invert_tmp_doubles(n) doubles.
+size_t dense_invert_tmp_doubles(int64_t n);
 fem_status dense_invert(int64_t n, double* A, double* tmp, hipStream_t s);
 // Coarse inverse kept as the packed lower 64 x 64 tiles of its symmetric part; the solve reads
 // each stored tile once (y_I += A_IJ x_J and y_J += A_IJ^T x_I through per-tile partials summed in

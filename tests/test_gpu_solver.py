@@ -11,6 +11,9 @@
 * Failure handling: max_it reached, NaN right-hand side, negative coefficient, bad arguments.
 * Determinism and warm start.
 * Mixed precision keeps the coarse solve in FP64 (the FP32-stored inverse only on request).
+* The dense coarse inverse alone (full multigrid on one level is the coarse solve) against the
+  oracle's direct solve to FP64 accuracy, at sizes with several 256-wide pivot blocks and ragged
+  tails.
 """
 import numpy as np
 import pytest
@@ -274,3 +277,21 @@ def test_mixed_precision_coarse_solve_is_fp64():
     u, res = S.solve(_t(b))
     torch.cuda.synchronize()
     assert res.rel_residual_true <= 1e-10 and rel(u.cpu().numpy(), u_ref) <= 1e-8
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n0,r,p,jit,kvar", [(2, 1, 3, 0.1, True),     # 11^3 = 1331 interior: 5 blocks + 51
+                                             (10, 1, 1, 0.1, False)])  # 19^3 = 6859: 26 blocks + 203
+def test_dense_coarse_inverse_is_exact(n0, r, p, jit, kvar):
+    banner(f"dense coarse inverse n0={n0} r={r} p={p}")
+    from paper_2104_08012_amd import fem
+    mesh, levels = make_pair(n0, r, p, jit)
+    lev = levels[-1]
+    k = fem_inputs.k_exp_fourier(lev.vert_xyz) if kvar else None
+    A = assemble.apply_bc(assemble.stiffness(lev, k), lev.boundary)
+    b = _rhs(lev)
+    u_ref = solvers.direct_solve(A, b, rtol=1e-14)
+    S = fem.Solver(mesh, fem.SolveOptions(n_levels_used=1, coarse_method="dense")).setup(_t(k) if kvar else None)
+    u, _ = S.fmg(_t(b))
+    torch.cuda.synchronize()
+    assert rel(u.cpu().numpy(), u_ref) <= 1e-11
