@@ -887,7 +887,9 @@ def summarize_valu(dirs, trace_dir, kernels):
     one run each), averaged per kernel and grid, with the kernel's median duration from a
     --kernel-trace run:
       flops: 64 lanes x (add + mul + transcendental + 2 fma) wave instructions, FP64 for kernels
-             instantiated in double, FP32 otherwise (SQ_INSTS_VALU_FLOPS_* counts one lane);
+             instantiated in double or issuing FP64 matrix instructions, FP32 otherwise
+             (SQ_INSTS_VALU_FLOPS_* counts one lane), plus 512 per FP64 MFMA op
+             (SQ_INSTS_VALU_MFMA_MOPS_F64); mfma: the matrix cores' share of the flops;
       rate:  flops / duration, and its fraction of the vector peak;
       issue: VALU wave instructions x 4 cycles / (1024 SIMDs x 2.4 GHz x duration), the share of
              the VALU issue slots the kernel fills (full-rate FP32/FP64 instructions take 4
@@ -906,17 +908,18 @@ def summarize_valu(dirs, trace_dir, kernels):
         for r in _csv(os.path.join(trace_dir, "run_kernel_trace.csv")):
             dur[(_short(r["Kernel_Name"]), int(r["Grid_Size_X"]))].append(
                 (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
-    print(f"{'GFLOP':>8} {'valu_Minst':>10} {'t_us':>8} {'TF/s':>6} {'frac':>5} {'issue':>5} {'busy%':>6} "
+    print(f"{'GFLOP':>8} {'mfma':>5} {'valu_Minst':>10} {'t_us':>8} {'TF/s':>6} {'frac':>5} {'issue':>5} {'busy%':>6} "
           f"{'grbm_MHz':>8} {'lds_Minst':>9}  kernel [grid threads]")
     rows = []
     for (nm, g), c in vals.items():
         if kernels and not any(nm.startswith(k) for k in kernels):
             continue
         m = {k: sum(v) / len(v) for k, v in c.items()}
-        dbl = "double" in nm
+        mf = 512 * m.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0)
+        dbl = "double" in nm or mf > 0
         sfx = "F64" if dbl else "F32"
         fl = 64 * (m.get(f"SQ_INSTS_VALU_ADD_{sfx}", 0) + m.get(f"SQ_INSTS_VALU_MUL_{sfx}", 0)
-                   + m.get(f"SQ_INSTS_VALU_TRANS_{sfx}", 0) + 2 * m.get(f"SQ_INSTS_VALU_FMA_{sfx}", 0))
+                   + m.get(f"SQ_INSTS_VALU_TRANS_{sfx}", 0) + 2 * m.get(f"SQ_INSTS_VALU_FMA_{sfx}", 0)) + mf
         t = sorted(dur.get((nm, g), []))
         tm = t[len(t) // 2] if t else 0.0
         rate = fl / tm / 1e12 if tm else 0.0
@@ -925,7 +928,7 @@ def summarize_valu(dirs, trace_dir, kernels):
         issue = vi * 4 / (1024 * 2.4e9 * tm) if tm else 0.0
         gg = m.get("GRBM_GUI_ACTIVE", 0.0)
         busy = 100.0 * m.get("SQ_ACTIVE_INST_VALU", 0.0) / 256 / (gg / 8) if gg else 0.0
-        rows.append((fl, f"{fl / 1e9:8.3f} {vi / 1e6:10.2f} {tm * 1e6:8.2f} {rate:6.2f} {rate / peak:5.2f} "
+        rows.append((fl, f"{fl / 1e9:8.3f} {mf / fl if fl else 0.0:5.2f} {vi / 1e6:10.2f} {tm * 1e6:8.2f} {rate:6.2f} {rate / peak:5.2f} "
                          f"{issue:5.2f} {busy:6.1f} {gg / (tm * 1e6) if tm else 0:8.0f} "
                          f"{m.get('SQ_INSTS_LDS', 0) / 1e6:9.2f}  {nm} [{g}]"))
     for _, line in sorted(rows, key=lambda r: -r[0]):
