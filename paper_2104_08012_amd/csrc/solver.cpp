@@ -318,7 +318,7 @@ struct fem_solver {
     fem_status lanczos_patch(int l, double& lm);
     fem_status patch64(int l, const double* x, double* y);
     fem_status precondition(const double* r, double* z);
-    fem_status cg(const double* b, double* x, int& iters, double& rel_true, bool& converged);
+    fem_status cg(const double* b, double* x, int& iters, double& rel_true, bool& converged, bool x_zero = false);
     fem_status fmg(const double* b, double* x, double& rel_true);
     void accumulate_times(int set);
 };
@@ -383,7 +383,7 @@ fem_status fem_solver::coarse_solve(const double* b64, double* x64) {
         int its = 0;
         double rel = 0.0;
         bool conv = false;
-        FEM_TRY(inner->cg(b64, x64, its, rel, conv));
+        FEM_TRY(inner->cg(b64, x64, its, rel, conv, true));
         coarse_iters += its;
         if (!conv) {
             set_error("nested coarse solve stopped at relative residual " + std::to_string(rel) + " > coarse_rtol");
@@ -711,14 +711,15 @@ fem_status fem_solver::precondition(const double* r, double* z) {
 }
 
 // Preconditioned CG on this solver's finest level; x holds the initial guess and returns the
-// iterate.  converged reports whether the true relative residual reached o.rtol.
+// iterate (x_zero: the guess is known to be zero, so r = b).  converged reports whether the true
+// relative residual reached o.rtol.
 //
 // The scalars alpha, beta and r^T z stay on the device.  Each iteration enqueues q = A p, alpha,
 // the update of x and r, r^T r (copied to pinned host memory behind an event) and then,
 // speculatively, the preconditioner, r^T z, beta and the new direction; the host waits only for
 // that iteration's r^T r, which is ready before the preconditioner runs, so the queue never
 // drains.  On convergence the speculative work is discarded (it touches only z, p and scalars).
-fem_status fem_solver::cg(const double* b, double* x, int& it, double& rel_true, bool& converged) {
+fem_status fem_solver::cg(const double* b, double* x, int& it, double& rel_true, bool& converged, bool x_zero) {
     const int hi = L.hi;
     const int64_t n = m->lev[hi].N;
     double* r = p<double>(L.cg_r);
@@ -751,9 +752,15 @@ fem_status fem_solver::cg(const double* b, double* x, int& it, double& rel_true,
         converged = true;
         return check_launch("solver");
     }
-    FEM_TRY(apply64(hi, x, -1.0, b, 1.0, r));                 // r = b - A x
-    FEM_TRY(dot(n, r, r, rr));
+    if (x_zero) {
+        axpby_launch<double>(n, 1.0, b, 0.0, r, s);              // r = b
+        rr = bb;
+    } else {
+        FEM_TRY(apply64(hi, x, -1.0, b, 1.0, r));             // r = b - A x
+        FEM_TRY(dot(n, r, r, rr));
+    }
     double rel = std::sqrt(rr) / nb;
+    double rel_checked = -1.0;   // true relative residual of the current x, once computed
     record(0, rel);
     // z = B r, rz, p = z (also the restart after a failed true-residual check)
     auto start = [&]() -> fem_status {
@@ -771,8 +778,12 @@ fem_status fem_solver::cg(const double* b, double* x, int& it, double& rel_true,
         axpby_launch<double>(n, 1.0, z, 0.0, pp, s);
         return FEM_OK;
     };
-    if (rel <= o.rtol) converged = true;
-    else FEM_TRY(start());
+    if (rel <= o.rtol) {
+        converged = true;
+        rel_checked = rel;
+    } else {
+        FEM_TRY(start());
+    }
     hipEvent_t done = ev.back();
     bool pending_times = false;
     // next search direction: z = B r, r^T z and q^T z (q = A p), beta, p = z + beta p
@@ -830,6 +841,7 @@ fem_status fem_solver::cg(const double* b, double* x, int& it, double& rel_true,
             if (tmg && spec) accumulate_times(set);
             if (std::sqrt(tt) / nb <= o.rtol) {
                 converged = true;
+                rel_checked = std::sqrt(tt) / nb;
                 break;
             }
             if (spec) {
@@ -849,7 +861,11 @@ fem_status fem_solver::cg(const double* b, double* x, int& it, double& rel_true,
         const hipError_t e = hipStreamSynchronize(s);
         if (e == hipSuccess) accumulate_times(evset);
     }
-    // true residual at exit
+    // true residual at exit (already known when the loop stopped on its check)
+    if (rel_checked >= 0.0) {
+        rel_true = rel_checked;
+        return check_launch("solver");
+    }
     FEM_TRY(apply64(hi, x, -1.0, b, 1.0, q));
     double tt = 0.0;
     FEM_TRY(dot(n, q, q, tt));

@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(VT) k_dot_final(const double* partial, double*
 template <typename T>
 __global__ void k_axpby(int64_t n, double a, const T* __restrict__ x, double b, T* y) {
     const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
-    if (i < n) y[i] = (T)(a * (double)x[i] + b * (double)y[i]);
+    if (i < n) y[i] = (T)(b == 0.0 ? a * (double)x[i] : a * (double)x[i] + b * (double)y[i]);   // b = 0: y not read
 }
 
 // Device-resident CG scalars (indices into the solver's scalar block, see vec.hpp).

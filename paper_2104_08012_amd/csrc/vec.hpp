@@ -20,6 +20,7 @@ template <typename T>
 void dot_launch(int npair, int64_t n, const DotPairs<T>& pr, double* partial, double* out, hipStream_t s);
 size_t dot_partial_doubles();
 
+// y = a x + b y (b = 0: y = a x, y not read)
 template <typename T>
 void axpby_launch(int64_t n, double a, const T* x, double b, T* y, hipStream_t s);
 
