@@ -8,8 +8,9 @@
 //  * k_csr_gather: one thread per stored entry, the sum of its element-matrix contributions in
 //    the fixed (ascending cell) order the host listed, or the identity row / zero column of a
 //    Dirichlet dof (symmetric elimination, as in the matrix-free operator).
-//  * k_spmv: y = A x with LANES lanes per row and a fixed-shape shuffle reduction, so results are
-//    bitwise reproducible.
+//  * k_spmv: y = A x with LANES lanes per row (each lane's entries in ascending order, their loads
+//    issued four at a time) and a fixed-shape shuffle reduction, so results are bitwise
+//    reproducible.
 #include "csr.hpp"
 
 namespace fem {
@@ -78,13 +79,31 @@ template <typename T, int LANES>
 __global__ void __launch_bounds__(VT) k_spmv(int64_t nrows, const int32_t* __restrict__ rp,
                                             const int32_t* __restrict__ col, const T* __restrict__ val,
                                             const T* __restrict__ x, T* __restrict__ y) {
+    constexpr int U = 4;   // entries per lane whose loads are issued together
     const int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x;
     const int64_t row = t / LANES;
     const int lane = (int)(t % LANES);
     T acc = T(0);
     if (row < nrows) {
         const int32_t b = rp[row], e = rp[row + 1];
-        for (int32_t k = b + lane; k < e; k += LANES) acc += val[k] * x[col[k]];
+        // lane entries k = b + lane + LANES j, summed in ascending j; U at a time: their column and
+        // value loads first, then the U gathers of x, so a row costs two memory round trips per U
+        // entries instead of two per entry
+        for (int32_t k = b + lane; k < e; k += U * LANES) {
+            int32_t c[U];
+            T v[U], xv[U];
+            // indices past the row's end are clamped to its last entry (loaded, not summed)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t kk = min(k + u * LANES, e - 1);
+                c[u] = col[kk];
+                v[u] = val[kk];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc = k + u * LANES < e ? acc + v[u] * xv[u] : acc;
+        }
     }
 #pragma unroll
     for (int off = LANES / 2; off > 0; off >>= 1) acc += __shfl_down(acc, off, LANES);
@@ -117,7 +136,9 @@ template void csr_gather_launch<float>(int64_t, const int64_t*, const int32_t*, 
 template <typename T>
 void csr_spmv_launch(int64_t nrows, int lanes, const int32_t* rp, const int32_t* col, const T* val, const T* x, T* y,
                      hipStream_t s) {
-    if (lanes <= 8)
+    if (lanes <= 4)
+        hipLaunchKernelGGL((k_spmv<T, 4>), dim3(blocks(nrows * 4)), dim3(VT), 0, s, nrows, rp, col, val, x, y);
+    else if (lanes <= 8)
         hipLaunchKernelGGL((k_spmv<T, 8>), dim3(blocks(nrows * 8)), dim3(VT), 0, s, nrows, rp, col, val, x, y);
     else
         hipLaunchKernelGGL((k_spmv<T, 16>), dim3(blocks(nrows * 16)), dim3(VT), 0, s, nrows, rp, col, val, x, y);
