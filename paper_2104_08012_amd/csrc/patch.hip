@@ -174,13 +174,15 @@ __global__ void __launch_bounds__(256) k_patch_local2(PatchGeom g, const T* __re
 
 // P3: one thread per vertex (64 per workgroup).  The 65 residual values and the symmetric half of
 // the products live in LDS (one column per lane); the packed rows are taken in blocks of RB
-// whose results stay in registers: for row a of the block and b < a the entry m_ab adds
+// (16 rows in FP64, 24 in FP32: each column b of a block issues RB independent coalesced loads,
+// which is what keeps enough bytes in flight at two workgroups per CU) whose results stay in
+// registers: for row a of the block and b < a the entry m_ab adds
 // m_ab r_b to row a and m_ab r_a to row b (an LDS accumulation); the block's own lower triangle
 // is unrolled.  Row a's result is complete once the later blocks have added their column-a terms.
 template <typename T>
 __global__ void __launch_bounds__(64) k_patch_local3(PatchGeom g, const T* __restrict__ inv, const T* __restrict__ r,
                                                      T* __restrict__ u) {
-    constexpr int NS = StarTab<3>::NS, RB = 8;
+    constexpr int NS = StarTab<3>::NS, RB = sizeof(T) == 8 ? 16 : 24;   // the most rows without spills
     __shared__ T rs[NS][64];
     __shared__ T us[NS][64];
     const int lane = threadIdx.x;
