@@ -22,7 +22,7 @@ Setup (mesh upload, Jacobi diagonals, Lanczos estimates, coarse inverse) is outs
 region and reported separately.
 After the timed steps ("sections", all by default): per-level times ("levels"), the additive
 vertex-star patch preconditioner of Listing 2's smoother and the patch-smoothed solves
-("patch", P2), the action sweep P1/P2/P3 x FP64/FP32 on 128^3 x 6 tetrahedra ("sweep"), the
+("patch", P2 and P3), the action sweep P1/P2/P3 x FP64/FP32 on 128^3 x 6 tetrahedra ("sweep"), the
 64^3 P2 workload of the same method (3 levels from 16^3, dense FP64 coarse inverse; "p2-64"),
 and the oracle timed on the host ("cpu", also --no-cpu-baseline).
 
@@ -481,9 +481,9 @@ def run_solve(args, name, w):
     del s64, smx
     torch.cuda.empty_cache()
 
-    if "patch" in sections and p == 2:
+    if "patch" in sections and p in (2, 3):
         out["patch_smoother"] = patch_section(torch, fem, tm, flush, mesh, k64, x64, x32, y64, y32, b, w, used, cm,
-                                              N, NV)
+                                              N, NV, p)
         print("[bench] patch smoother done", file=sys.stderr, flush=True)
     del mesh, x64, x32, y64, y32, b
     torch.cuda.empty_cache()
@@ -501,10 +501,10 @@ def run_solve(args, name, w):
     return out
 
 
-def patch_section(torch, fem, tm, flush, mesh, k64, x64, x32, y64, y32, b, w, used, cm, N, NV):
-    """Listing 2's patch preconditioner inside the Chebyshev smoother (P2): the patch application
-    on the finest level (cold cache, HIP events on the stream it runs on) and the patch-smoothed
-    MG-CG solves."""
+def patch_section(torch, fem, tm, flush, mesh, k64, x64, x32, y64, y32, b, w, used, cm, N, NV, p):
+    """Listing 2's patch preconditioner inside the Chebyshev smoother (P2 and P3 vertex stars of 15
+    and 65 dofs): the patch application on the finest level (cold cache, HIP events on the stream
+    it runs on) and the patch-smoothed MG-CG solves."""
     prec_rec = {}
     pc64 = fem.PatchPreconditioner(mesh, -1, k64, dtype=torch.float64)
     pc32 = fem.PatchPreconditioner(mesh, -1, k64, dtype=torch.float32)
@@ -535,13 +535,15 @@ def patch_section(torch, fem, tm, flush, mesh, k64, x64, x32, y64, y32, b, w, us
         tp64.append(t1 - t0)
         tpmx.append(t2 - t1)
     a64, a32 = mean(prec_rec["patch64"]), mean(prec_rec["patch32"])
-    alg64, alg32 = 120 * NV * 8 + 2 * N * 8, 120 * NV * 4 + 2 * N * 4
+    ns = 15 if p == 2 else 65
+    npk = ns * (ns + 1) // 2
+    alg64, alg32 = npk * NV * 8 + 2 * N * 8, npk * NV * 4 + 2 * N * 4
     return {
         "apply_us_fp64_cold": stats_us(prec_rec["patch64"]), "apply_us_fp32_cold": stats_us(prec_rec["patch32"]),
         "alg_bytes_fp64": alg64, "alg_bytes_fp32": alg32,
         "hbm_frac_fp64": round(alg64 / a64 / 8.0e12, 3), "hbm_frac_fp32": round(alg32 / a32 / 8.0e12, 3),
-        "bytes_note": "packed 15x15 star inverses (120 entries per vertex) + r in + z out; the 15 partial "
-                      "results per vertex (written and read back) are not counted",
+        "bytes_note": f"packed {ns}x{ns} star inverses ({npk} entries per vertex) + r in + z out; the {ns} "
+                      "partial results per vertex (written and read back) are not counted",
         "mgcg_fp64_ms": stats_ms(tp64), "mgcg_mixed_ms": stats_ms(tpmx),
         "mgcg_fp64_iterations": rp64.iterations, "mgcg_mixed_iterations": rpmx.iterations,
         "mgcg_fp64_rel_residual": rp64.rel_residual_true, "mgcg_mixed_rel_residual": rpmx.rel_residual_true,
