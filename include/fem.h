@@ -305,10 +305,12 @@ fem_status fem_adjoint_grad_k(const fem_mesh* mesh, int32_t level, const double*
  * with A the stiffness matrix of k.  Degrees 2 and 3: an interior star holds 15 dofs for P2 (the
  * vertex and the 14 edge midpoints around it) and 65 for P3 (the vertex, two dofs on each of 14
  * edges, one on each of 36 faces).  Degree 1 (every star one dof: point Jacobi) and levels whose
- * packed index (entries per vertex x n_vertices) reaches 2^32 return FEM_ERR_UNSUPPORTED.
+ * packed index (entries per vertex x n_vertices rounded up to 64) reaches 2^32 return
+ * FEM_ERR_UNSUPPORTED.
  * fem_patch_bytes: size of the caller-owned patch buffer of `level` for dtype (the packed
  * lower triangles of the star inverses, 120 (P2) or 2145 (P3) entries per vertex, plus 15 or 65
- * partial results per vertex), 256-byte aligned parts.
+ * partial results per vertex, over the vertex count rounded up to a multiple of 64), 256-byte
+ * aligned parts.
  * fem_patch_setup: fills the buffer for k_vertex (FP64 device, n_vertices; NULL => k = 1); the
  * inverses are computed in FP64 and stored in dtype.  FEM_ERR_WORKSPACE for a NULL or short
  * buffer.  Stream-ordered.

@@ -13,11 +13,13 @@
 // the P1-coefficient stiffness (exact for k = 1 too), the cell's geometric factor G and the
 // vertex values of k; then inverted by Gauss-Jordan elimination in LDS in FP64 (A_v is symmetric
 // positive definite, so no pivoting) and stored as its packed lower triangle (120 entries per
-// vertex for P2, 2145 for P3), entry-major (entry e of all vertices contiguous).
+// vertex for P2, 2145 for P3) in blocks of 64 vertices: entry e of vertex v at
+// ((v / 64) NE + e) 64 + v % 64 (NE entries per vertex), so the 64 lanes of a wave read 512
+// contiguous bytes per entry and a wave's whole stream is one contiguous region.
 // Apply: a per-star product of every star's inverse with the gathered residual (P2: one thread
 // per vertex, all in registers; P3: one thread per vertex with the residual and the symmetric
-// half of the products in LDS, rows in blocks of 16 held in registers), storing the star results
-// per vertex; then k_patch_combine sums, for every dof, the results of the one to three stars
+// half of the products in LDS, rows in blocks held in registers), storing the star results per
+// vertex in the same blocked layout; then k_patch_combine sums, for every dof, the results of the one to three stars
 // that contain it in increasing vertex order (a deterministic gather, no atomics).
 #include <hip/hip_runtime.h>
 
@@ -38,6 +40,9 @@ struct PatchGeom {
     int n, B, nb, NC;
     uint32_t C, NV, L;
 };
+
+// blocked per-vertex layout of the packed inverses and star results (NE entries per vertex)
+__device__ __forceinline__ uint32_t pblock(uint32_t v, uint32_t NE) { return (v >> 6) * NE * 64u + (v & 63u); }
 
 // Lattice point of star slot s of vertex (vi, vj, vk) and whether it is an interior dof.
 template <int P>
@@ -138,7 +143,7 @@ __global__ void __launch_bounds__(64) k_star_setup(PatchGeom g, const double* __
         uint32_t ia, ib;
         const bool live = star_point<P>(a, vi, vj, vk, Lm, g.L, ia) && star_point<P>(b, vi, vj, vk, Lm, g.L, ib);
         const double val = live ? 0.5 * (A[a * LD + b] + A[b * LD + a]) : 0.0;
-        inv[(uint32_t)(a * (a + 1) / 2 + b) * g.NV + v] = (T)val;
+        inv[pblock(v, StarTab<P>::NP) + (uint32_t)(a * (a + 1) / 2 + b) * 64u] = (T)val;
     }
 }
 
@@ -149,6 +154,7 @@ __global__ void __launch_bounds__(256) k_patch_local2(PatchGeom g, const T* __re
     constexpr int NS = StarTab<2>::NS;
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= g.NV) return;
+    const uint32_t ib = pblock(v, StarTab<2>::NP), ub = pblock(v, NS);
     const int n = g.n, N1 = n + 1, Lm = 2 * n;
     const int vi = (int)(v % N1), vj = (int)((v / N1) % N1), vk = (int)(v / (N1 * N1));
     T rs[NS];
@@ -164,12 +170,12 @@ __global__ void __launch_bounds__(256) k_patch_local2(PatchGeom g, const T* __re
     for (int a = 0; a < NS; ++a)
 #pragma unroll
         for (int b = 0; b <= a; ++b) {
-            const T m = inv[(uint32_t)(a * (a + 1) / 2 + b) * g.NV + v];
+            const T m = inv[ib + (uint32_t)(a * (a + 1) / 2 + b) * 64u];
             us[a] += m * rs[b];
             if (b != a) us[b] += m * rs[a];
         }
 #pragma unroll
-    for (int a = 0; a < NS; ++a) u[(uint32_t)a * g.NV + v] = us[a];
+    for (int a = 0; a < NS; ++a) u[ub + (uint32_t)a * 64u] = us[a];
 }
 
 // P3: one thread per vertex (64 per workgroup).  The 65 residual values and the symmetric half of
@@ -189,6 +195,7 @@ __global__ void __launch_bounds__(64) k_patch_local3(PatchGeom g, const T* __res
     const uint32_t v = blockIdx.x * 64 + lane;
     const bool valid = v < g.NV;
     const uint32_t vv = valid ? v : 0;
+    const uint32_t ib = pblock(v, StarTab<3>::NP), ub = pblock(v, NS);
     const int n = g.n, N1 = n + 1, Lm = 3 * n;
     const int vi = (int)(vv % N1), vj = (int)((vv / N1) % N1), vk = (int)(vv / (N1 * N1));
 #pragma unroll
@@ -215,7 +222,7 @@ __global__ void __launch_bounds__(64) k_patch_local3(PatchGeom g, const T* __res
             T sym = T(0);
 #pragma unroll
             for (int j = 0; j < RB; ++j) {
-                const T m = (valid && j < nr) ? inv[(row[j] + (uint32_t)b) * g.NV + v] : T(0);
+                const T m = (valid && j < nr) ? inv[ib + (row[j] + (uint32_t)b) * 64u] : T(0);
                 acc[j] += m * rb;
                 sym += m * ra[j];
             }
@@ -225,7 +232,7 @@ __global__ void __launch_bounds__(64) k_patch_local3(PatchGeom g, const T* __res
         for (int j = 0; j < RB; ++j)
 #pragma unroll
             for (int jb = 0; jb <= j; ++jb) {
-                const T m = (valid && j < nr) ? inv[(row[j] + (uint32_t)(a0 + jb)) * g.NV + v] : T(0);
+                const T m = (valid && j < nr) ? inv[ib + (row[j] + (uint32_t)(a0 + jb)) * 64u] : T(0);
                 acc[j] += m * ra[jb];
                 if (jb != j) acc[jb] += m * ra[j];
             }
@@ -235,7 +242,7 @@ __global__ void __launch_bounds__(64) k_patch_local3(PatchGeom g, const T* __res
     }
     if (!valid) return;
 #pragma unroll
-    for (int a = 0; a < NS; ++a) u[(uint32_t)a * g.NV + v] = us[a][lane];
+    for (int a = 0; a < NS; ++a) u[ub + (uint32_t)a * 64u] = us[a][lane];
 }
 
 // z at every dof: the star results of the stars holding it (1 for a vertex, 2 for an edge node,
@@ -260,7 +267,8 @@ __global__ void __launch_bounds__(256) k_patch_combine(PatchGeom g, const T* __r
     for (int k = 0; k < cnt; ++k) {
         const int bits = st.rv[rx][ry][rz][k];
         const uint32_t vid = base + (uint32_t)(bits & 1) + N1 * ((uint32_t)((bits >> 1) & 1) + N1 * (uint32_t)(bits >> 2));
-        acc = k == 0 ? u[(uint32_t)st.rs[rx][ry][rz][k] * g.NV + vid] : acc + u[(uint32_t)st.rs[rx][ry][rz][k] * g.NV + vid];
+        const T uk = u[pblock(vid, StarTab<P>::NS) + (uint32_t)st.rs[rx][ry][rz][k] * 64u];
+        acc = k == 0 ? uk : acc + uk;
     }
     z[i] = acc;
 }
@@ -278,6 +286,7 @@ PatchGeom patch_geom(const HostLevel& H) {
 }
 
 int star_size(int p) { return p == 2 ? StarTab<2>::NS : p == 3 ? StarTab<3>::NS : 0; }
+int64_t padded_vertices(const HostLevel& H) { return (H.NV + 63) / 64 * 64; }
 int star_packed(int p) { return p == 2 ? StarTab<2>::NP : p == 3 ? StarTab<3>::NP : 0; }
 
 }  // namespace
@@ -287,8 +296,9 @@ bool patch_supported(const HostLevel& H, std::string& why) {
         why = "star patches are built for degrees 2 and 3 (for degree 1 every star is one dof: Jacobi)";
         return false;
     }
-    // packed entry e of vertex v is element e * NV + v (32-bit) and the star results follow
-    if ((uint64_t)(star_packed(H.p) + star_size(H.p)) * (uint64_t)H.NV >= ((uint64_t)1 << 32)) {
+    // packed entry e of vertex v is element ((v / 64) NE + e) 64 + v % 64 (32-bit), over the
+    // vertex count rounded up to a multiple of 64
+    if ((uint64_t)(star_packed(H.p) + star_size(H.p)) * (uint64_t)padded_vertices(H) >= ((uint64_t)1 << 32)) {
         why = "level has too many vertices for the 32-bit packed star index (" + std::to_string(star_packed(H.p)) +
               " entries per vertex)";
         return false;
@@ -297,7 +307,8 @@ bool patch_supported(const HostLevel& H, std::string& why) {
 }
 
 size_t patch_bytes(const HostLevel& H, size_t ts) {
-    return align256((size_t)star_packed(H.p) * H.NV * ts) + align256((size_t)star_size(H.p) * H.NV * ts);
+    const size_t nv = padded_vertices(H);
+    return align256((size_t)star_packed(H.p) * nv * ts) + align256((size_t)star_size(H.p) * nv * ts);
 }
 
 template <typename T>
@@ -317,7 +328,8 @@ fem_status patch_apply(const fem_mesh& m, int level, void* buf, const T* r, T* z
     const HostLevel& H = m.lev[level];
     const PatchGeom g = patch_geom(H);
     const T* inv = reinterpret_cast<const T*>(buf);
-    T* u = reinterpret_cast<T*>(reinterpret_cast<char*>(buf) + align256((size_t)star_packed(H.p) * H.NV * sizeof(T)));
+    T* u = reinterpret_cast<T*>(reinterpret_cast<char*>(buf) +
+                                align256((size_t)star_packed(H.p) * padded_vertices(H) * sizeof(T)));
     const unsigned gc = (unsigned)((H.N + 255) / 256);
     if (H.p == 2) {
         hipLaunchKernelGGL((k_patch_local2<T>), dim3((g.NV + 255) / 256), dim3(256), 0, s, g, inv, r, u);

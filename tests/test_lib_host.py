@@ -140,16 +140,19 @@ def test_patch_buffer_bytes_and_degree_check():
     def a256(x):
         return (x + 255) // 256 * 256
 
+    def pad64(x):   # the per-vertex entries are stored in blocks of 64 vertices
+        return (x + 63) // 64 * 64
+
     m = fem.Mesh(6, 1, 2, upload=False)
     nb = C.c_size_t()
     for level, n in ((0, 6), (1, 12)):
-        NV = (n + 1) ** 3
+        NV = pad64((n + 1) ** 3)
         for dt, s in ((0, 8), (1, 4)):
             assert lib().fem_patch_bytes(m.handle, level, dt, C.byref(nb)) == FEM_OK
             assert nb.value == a256(120 * NV * s) + a256(15 * NV * s)
     m3 = fem.Mesh(3, 1, 3, upload=False)           # P3 stars: 2145 packed entries + 65 results
     for level, n in ((0, 3), (1, 6)):
-        NV = (n + 1) ** 3
+        NV = pad64((n + 1) ** 3)
         for dt, s in ((0, 8), (1, 4)):
             assert lib().fem_patch_bytes(m3.handle, level, dt, C.byref(nb)) == FEM_OK
             assert nb.value == a256(2145 * NV * s) + a256(65 * NV * s)
@@ -164,7 +167,8 @@ def test_patch_buffer_bytes_and_degree_check():
 
 def test_solver_workspace_with_patch_smoother():
     """The star-patch smoother adds, per smoothed level, the patch buffer (120 + 15 entries per
-    vertex for P2, 2145 + 65 for P3) and one level vector; degree 1 is refused."""
+    vertex for P2, 2145 + 65 for P3, the vertex count rounded up to a multiple of 64) and one level
+    vector; degree 1 is refused."""
     import ctypes as C
     from paper_2104_08012_amd import fem
     from paper_2104_08012_amd import _lib as L
@@ -180,14 +184,16 @@ def test_solver_workspace_with_patch_smoother():
         st_j, b_j = ws(m, precision=prec)
         st_p, b_p = ws(m, precision=prec, smoother="patch")
         assert st_j == 0 and st_p == 0
-        extra = sum(135 * m.levels[l]["n_vertices"] * s + m.levels[l]["n_dofs"] * s for l in (1, 2))
+        extra = sum(135 * ((m.levels[l]["n_vertices"] + 63) // 64 * 64) * s + m.levels[l]["n_dofs"] * s
+                    for l in (1, 2))
         assert extra <= b_p - b_j <= extra + 6 * 256
     m3 = fem.Mesh(2, 2, 3, upload=False)
     for prec, s in (("fp64", 8), ("mixed", 4)):
         st_j, b_j = ws(m3, precision=prec)
         st_p, b_p = ws(m3, precision=prec, smoother="patch")
         assert st_j == 0 and st_p == 0
-        extra = sum(2210 * m3.levels[l]["n_vertices"] * s + m3.levels[l]["n_dofs"] * s for l in (1, 2))
+        extra = sum(2210 * ((m3.levels[l]["n_vertices"] + 63) // 64 * 64) * s + m3.levels[l]["n_dofs"] * s
+                    for l in (1, 2))
         assert extra <= b_p - b_j <= extra + 6 * 256
     mp = fem.Mesh(2, 1, 1, upload=False)
     st, _ = ws(mp, smoother="patch")
