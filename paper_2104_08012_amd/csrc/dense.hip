@@ -12,10 +12,10 @@
 // the stored M_IK; rows above: -M_KI^T) and Vs_J = s_J W_J P (s_J = -1 above K, +1 below):
 //   M_IJ -= W_I Vs_J^T on the lower tiles outside K      (n^3 flops in all, half of the full sweep),
 //   M_IK = -Vs_I below K,  M_KJ = Vs_J^T left of K,  M_KK = P.
-// Pivot blocks of 256 make the trailing update a rank-256 product, bound by FP64 arithmetic
-// rather than by re-reading the matrix (7.1 GB at the largest size) once per block.  P is the
-// inverse of a dense copy of M_KK by the same sweep with 64-wide blocks, each 64 x 64 pivot
-// inverted by one workgroup in LDS.
+// Pivot blocks of 256 make the trailing update a rank-256 product on the FP64 matrix cores,
+// bound by arithmetic rather than by re-reading the matrix (12.8 GB at 40000 rows) once per
+// block.  P is the inverse of a dense copy of M_KK by the full sweep with 64-wide blocks, each
+// 64 x 64 pivot inverted by one workgroup with the block in registers.
 #include "vec.hpp"
 
 namespace fem {
