@@ -296,3 +296,8 @@ def test_dense_coarse_inverse_is_exact(n0, r, p, jit, kvar):
     u, _ = S.fmg(_t(b))
     torch.cuda.synchronize()
     assert rel(u.cpu().numpy(), u_ref) <= 1e-11
+    # a second, independent setup gives the same inverse bit for bit (fixed reduction orders)
+    S2 = fem.Solver(mesh, fem.SolveOptions(n_levels_used=1, coarse_method="dense")).setup(_t(k) if kvar else None)
+    u2, _ = S2.fmg(_t(b))
+    torch.cuda.synchronize()
+    assert torch.equal(u, u2)
