@@ -7,12 +7,12 @@
 // tetrahedron holding the point weighted by their basis functions' values (a compile-time table of
 // exact rational weights, rounded once).  Small levels and P3: one thread per fine dof reading the
 // same table from memory (transfer.cpp).
-// Restriction r_c = P^T r_f with boundary rows zero.  P1, P2: one thread per coarse dof, the
-// threads of a launch row (blockIdx.y) all of one residue class modulo p, so each wave runs its
-// class's compile-time stencil (fine offsets d in [-2p, 2p]^3 with P[2J + d][J] != 0) over r_f at
-// 2J + d; coarse dofs at least p from the boundary skip the bounds checks.  P3 (27 classes, up to
-// 427 stencil entries): 8 lanes per coarse dof walk the class's stencil from the table and add
-// their partial sums by a fixed butterfly.
+// Restriction r_c = P^T r_f with boundary rows zero.  P1 and large P2 levels: one thread per
+// coarse dof, the threads of a launch row (blockIdx.y) all of one residue class modulo p, so each
+// wave runs its class's compile-time stencil (fine offsets d in [-2p, 2p]^3 with P[2J + d][J] != 0)
+// over r_f at 2J + d; coarse dofs at least p from the boundary skip the bounds checks.  P3 (27
+// classes, up to 427 stencil entries) and small P2 levels: 8 lanes per coarse dof walk the class's
+// stencil from the table and add their partial sums by a fixed butterfly.
 // Both write every output once in a fixed order of terms: deterministic, one launch each, no
 // interface pass.
 #include <hip/hip_runtime.h>
@@ -282,8 +282,11 @@ __global__ void __launch_bounds__(256) k_restrict_lattice(TArgs<T> a) {
     if (valid && part == 0) a.out[j] = acc;
 }
 
-// coarse levels of at least this many cubes per direction prolong one thread per coarse cube
+// coarse levels of at least this many cubes per direction prolong one thread per coarse cube, and
+// (P2) restrict one thread per coarse dof; smaller ones, where a kernel's time is one thread's
+// chain of loads, take the table kernels (8 lanes per coarse dof for the restriction)
 constexpr uint32_t kProlongCubeMinN = 32;
+constexpr uint32_t kRestrictClassMinN = 32;
 
 template <typename T>
 const T* wtab(const fem_mesh& m, size_t off64, size_t off32) {
@@ -337,7 +340,9 @@ fem_status run_restrict(const fem_mesh& m, int fine_level, const T* rf, T* rc, h
     const TArgs<T> a = targs<T>(m, fine_level, rf, rc);
     const uint32_t n1 = a.nc + 1;
     if (m.p == 1) hipLaunchKernelGGL((k_restrict_class<1, T>), dim3((n1 * n1 * n1 + 255) / 256, 1), dim3(256), 0, s, a);
-    else if (m.p == 2) hipLaunchKernelGGL((k_restrict_class<2, T>), dim3((n1 * n1 * n1 + 255) / 256, 8), dim3(256), 0, s, a);
+    else if (m.p == 2 && a.nc >= kRestrictClassMinN)
+        hipLaunchKernelGGL((k_restrict_class<2, T>), dim3((n1 * n1 * n1 + 255) / 256, 8), dim3(256), 0, s, a);
+    else if (m.p == 2) hipLaunchKernelGGL((k_restrict_lattice<2, T>), dim3((8 * n1 * n1 * n1 + 255) / 256, 8), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_restrict_lattice<3, T>), dim3((8 * n1 * n1 * n1 + 255) / 256, 27), dim3(256), 0, s, a);
     return check_launch("restriction kernel");
 }
