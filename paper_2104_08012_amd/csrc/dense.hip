@@ -323,6 +323,10 @@ size_t dense_invert_tmp_doubles(int64_t n) {
 
 fem_status dense_invert(int64_t n, double* A, double* tmp, hipStream_t s) {
     if (n <= 0) return FEM_OK;
+    if (!A || !tmp) {
+        set_error("dense inversion: NULL matrix or scratch");
+        return FEM_ERR_INVALID_ARG;
+    }
     const int64_t bmax = std::min<int64_t>(DB, n);
     double* W = tmp;
     double* Vs = W + n * bmax;
