@@ -282,7 +282,8 @@ def test_mixed_precision_coarse_solve_is_fp64():
 @pytest.mark.gpu
 @pytest.mark.parametrize("n0,r,p,jit,kvar", [(2, 1, 3, 0.1, True),     # 11^3 = 1331 interior: 5 blocks + 51
                                              (10, 1, 1, 0.1, False),   # 19^3 = 6859: 26 blocks + 203
-                                             (9, 0, 1, 0.1, True)])    # 8^3 = 512: exactly 2 blocks
+                                             (9, 0, 1, 0.1, True),     # 8^3 = 512: exactly 2 blocks
+                                             (35, 0, 1, 0.1, False)])  # 34^3 = 39304, near the 40000 limit
 def test_dense_coarse_inverse_is_exact(n0, r, p, jit, kvar):
     banner(f"dense coarse inverse n0={n0} r={r} p={p}")
     from paper_2104_08012_amd import fem
