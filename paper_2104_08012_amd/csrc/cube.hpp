@@ -128,7 +128,7 @@ constexpr int cube_min_waves() {
 template <int P, int B, int R, bool KVAR, bool GEO, typename T>
 __global__ void __launch_bounds__(B * B * B * R, (cube_min_waves<P, KVAR, T>())) k_cube_apply(SArgs<T> a) {
     static_assert(B == 4, "one wave per brick of 4^3 cubes");
-    static_assert(R == 1 || P == 2, "bricks are merged along x for P2 only");
+    static_assert(R == 1 || P <= 2, "bricks are merged along x for P1 and P2");
     constexpr int NL = nloc_of(P), NQ = nq_of(P, KVAR), PC = P + 1, NCP = PC * PC * PC;
     constexpr int NT = B * B * B, PB = P * B, QS = PB + 1, NQ3 = QS * QS * QS;
     constexpr int VS = B + 1, NV3 = VS * VS * VS;
@@ -544,11 +544,26 @@ __global__ void __launch_bounds__(B * B * B * R, (cube_min_waves<P, KVAR, T>()))
                 }
         }
     } else {
+        // x faces shared by the workgroup's bricks, as for P2: wave w > 0 adds the upper x face of
+        // wave w - 1 to its own lower x face and writes it to y with its interior; the x position
+        // of a brick point in the workgroup is w PB + la
+        if constexpr (R > 1) {
+            if (wave > 0) {
+                const T* __restrict__ xp = xcs[wave - 1];
+                for (int r = lane; r < QS * QS; r += NT) {
+                    const int lb = r % QS, lc = r / QS;
+                    const int i = XL::idx(0, lb, lc);
+                    xc[i] = xp[XL::idx(PB, lb, lc)] + xc[i];
+                }
+            }
+        }
+        const int la_lo = wave == 0 ? 1 : 0;
+        const uint32_t LA0 = (uint32_t)(wave * PB);
 #pragma unroll
-        for (int it = 0; it < (NIN + NT - 1) / NT; ++it) {
+        for (int it = 0; it < (PB * QI * QI + NT - 1) / NT; ++it) {   // interior: la in [la_lo, PB - 1]
             const int r = lane + NT * it;
-            if (r < NIN) {
-                const int la = 1 + r % QI, q = r / QI, lb = 1 + q % QI, lc = 1 + q / QI;
+            const int la = r % PB, q = r / PB, lb = 1 + q % QI, lc = 1 + q / QI;
+            if (r < PB * QI * QI && la >= la_lo) {
                 const uint32_t g = gb + (uint32_t)la + Lo * ((uint32_t)lb + Lo * (uint32_t)lc);
                 T v = alpha * xc[XL::idx(la, lb, lc)];
                 if (beta != T(0)) v += beta * ldg(a.z, g);
@@ -557,21 +572,24 @@ __global__ void __launch_bounds__(B * B * B * R, (cube_min_waves<P, KVAR, T>()))
         }
         // Face points, one face family at a time (the slot index is affine within a face); the
         // slot plane is code = [la == 0] + 2 [lb == 0] + 4 [lc == 0].
-        for (int r = lane; r < 2 * QS * QS; r += NT) {                 // x faces: la = 0, PB
+        for (int r = lane; r < 2 * QS * QS; r += NT) {                 // workgroup x faces
             const int sd = r / (QS * QS), u = r % (QS * QS), lb = u % QS, lc = u / QS, la = sd * PB;
-            const uint32_t t = iface_x0<PB, PB>(bx, by, bz, sd, Lo) + (uint32_t)lb + Lo * (uint32_t)lc;
+            if (sd == 0 ? wave != 0 : wave != R - 1) continue;
+            const uint32_t t = iface_x0<PBX, PB>(px, by, bz, sd, Lo) + (uint32_t)lb + Lo * (uint32_t)lc;
             const uint32_t code = (sd == 0 ? 1u : 0u) | (lb == 0 ? 2u : 0u) | (lc == 0 ? 4u : 0u);
             slots[(size_t)code * tot + t] = xc[XL::idx(la, lb, lc)];
         }
-        for (int r = lane; r < 2 * QI * QS; r += NT) {                 // y faces: lb = 0, PB; la inside
-            const int sd = r / (QI * QS), u = r % (QI * QS), la = 1 + u % QI, lc = u / QI, lb = sd * PB;
-            const uint32_t t = iface_y0<PB, PB>(bx, by, bz, sd, Lo, nbu, a.if_c0) + (uint32_t)la + npx * (uint32_t)lc;
+        for (int r = lane; r < 2 * PB * QS; r += NT) {                 // y faces: lb = 0, PB
+            const int sd = r / (PB * QS), u = r % (PB * QS), la = u % PB, lc = u / PB, lb = sd * PB;
+            if (la < la_lo) continue;
+            const uint32_t t = iface_y0<PBX, PB>(px, by, bz, sd, Lo, nbxu, a.if_c0) + LA0 + (uint32_t)la + npx * (uint32_t)lc;
             const uint32_t code = (sd == 0 ? 2u : 0u) | (lc == 0 ? 4u : 0u);
             slots[(size_t)code * tot + t] = xc[XL::idx(la, lb, lc)];
         }
-        for (int r = lane; r < 2 * QI * QI; r += NT) {                 // z faces: lc = 0, PB; la, lb inside
-            const int sd = r / (QI * QI), u = r % (QI * QI), la = 1 + u % QI, lb = 1 + u / QI, lc = sd * PB;
-            const uint32_t t = iface_z0<PB, PB>(bx, by, bz, sd, Lo, nbu, nbu, a.if_c01) + (uint32_t)la + npx * (uint32_t)lb;
+        for (int r = lane; r < 2 * PB * QI; r += NT) {                 // z faces: lc = 0, PB; lb inside
+            const int sd = r / (PB * QI), u = r % (PB * QI), la = u % PB, lb = 1 + u / PB, lc = sd * PB;
+            if (la < la_lo) continue;
+            const uint32_t t = iface_z0<PBX, PB>(px, by, bz, sd, Lo, nbxu, nbu, a.if_c01) + LA0 + (uint32_t)la + npx * (uint32_t)lb;
             const uint32_t code = sd == 0 ? 4u : 0u;
             slots[(size_t)code * tot + t] = xc[XL::idx(la, lb, lc)];
         }

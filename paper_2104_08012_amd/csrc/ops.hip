@@ -48,7 +48,7 @@ template <int P, int B, bool KV, bool GEO, typename T>
 void launch_cube(const SArgs<T>& a, int64_t nbricks, hipStream_t s) {
     const int R = a.nb / a.nbx;
     const unsigned grid = (unsigned)(nbricks / R);
-    if constexpr (P == 2) {
+    if constexpr (P <= 2) {
         if (R == 4) { hipLaunchKernelGGL((k_cube_apply<P, B, 4, KV, GEO, T>), dim3(grid), dim3(4 * 64), 0, s, a); return; }
         if (R == 2) { hipLaunchKernelGGL((k_cube_apply<P, B, 2, KV, GEO, T>), dim3(grid), dim3(2 * 64), 0, s, a); return; }
     }
@@ -105,7 +105,7 @@ template <typename T, int PO>
 void launch_fix_b(int B, const SArgs<T>& a, const FixGeom& fg, hipStream_t s) {
     const unsigned grid = (fg.total + 255) / 256;
     const int R = a.nb / a.nbx;
-    if constexpr (PO == 2) {
+    if constexpr (PO <= 2) {
         if (B == 4 && R == 4) { hipLaunchKernelGGL((k_fixup<PO, 4, 4, T>), dim3(grid), dim3(256), 0, s, a, fg); return; }
         if (B == 4 && R == 2) { hipLaunchKernelGGL((k_fixup<PO, 4, 2, T>), dim3(grid), dim3(256), 0, s, a, fg); return; }
     }
@@ -171,9 +171,9 @@ fem_status run_kind(const fem_mesh& m, int level, bool kvar, const ScatterIO<T>&
     a.lattice = KIND == K_APPLY && L.B == 4 && m.p == 3;
     a.geo_shift = level;
     a.geo_scale = std::ldexp(1.0, -level);
-    // the P2 cube kernel merges R = 4 (or 2) bricks along x in one workgroup; the interface
+    // the P1/P2 cube kernel merges R = 4 (or 2) bricks along x in one workgroup; the interface
     // numbering then has bricks of span R p B along x (iface.hpp)
-    const int R = (KIND == K_APPLY && m.p == 2 && L.B == 4 && L.cube) ? (L.nb % 4 == 0 ? 4 : L.nb % 2 == 0 ? 2 : 1) : 1;
+    const int R = (KIND == K_APPLY && m.p <= 2 && L.B == 4 && L.cube) ? (L.nb % 4 == 0 ? 4 : L.nb % 2 == 0 ? 2 : 1) : 1;
     a.nbx = L.nb / R;
     const int64_t Lo = a.Lout, nb = L.nb, nbx = a.nbx, np = Lo - nb - 1, npx = Lo - nbx - 1;
     const IfaceCounts ic = iface_counts((uint32_t)Lo, (uint32_t)nbx, (uint32_t)nb);
